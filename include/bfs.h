@@ -1,0 +1,195 @@
+/*
+ * bfs.h - C ABI of the MI355X (gfx950) masked sparse-matrix x sparse-vector
+ * breadth-first search.
+ *
+ * The operation (Burkhardt, "Optimal algebraic Breadth-First Search for sparse
+ * graphs", Theorem 1 and Algorithm 1): starting from x_1 = e_s, compute
+ *     x_{k+1} = A^T[V_{k+1}, V_k] x_k,      V_{k+1} = V_k \ supp(x_k)
+ * until the vector is empty.  A is the 0/1 adjacency pattern with A(i,j) = 1
+ * for an edge i -> j (rows are egress; the search follows A^T, as in the
+ * paper's directed-graph paragraph).  Rows and columns of visited vertices are
+ * masked; A itself is never modified.
+ *
+ * Outputs (per search):
+ *   level[v]  = k for v in supp(x_{k+1}) (the number of edges on a shortest
+ *               path s -> v); -1 if v is never reached.
+ *   parent[v] = the smallest frontier vertex j with A(j, v) = 1 and
+ *               level[j] = level[v] - 1; parent[s] = s; -1 if unreached.
+ *               This is the (min, select) semiring product of the paper's
+ *               Algorithm 3 parent array with its tie resolved to the minimum,
+ *               so every variant and every batch gives the same bits.
+ *
+ * Conventions for every call:
+ *   - vertex ids and offsets are int32, 0-based; nnz < 2^31;
+ *   - "device" pointers are HIP device memory on the graph's device;
+ *   - hip_stream is a hipStream_t (NULL = the default stream);
+ *   - every call returns bfs_status; nothing throws across the ABI;
+ *   - on error, outputs are untouched and bfs_last_error_detail() explains.
+ */
+#ifndef BFS_H
+#define BFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfs_graph bfs_graph;  /* opaque, immutable after create, library-owned */
+
+typedef enum bfs_status {
+    BFS_OK = 0,
+    BFS_EINVAL = 1,   /* bad argument: NULL pointer, n <= 0, workspace too small, bad option */
+    BFS_ERANGE = 2,   /* a source vertex outside [0, n) */
+    BFS_ECSR = 3,     /* malformed CSR/CSC: ptr[0] != 0, decreasing ptr, idx outside [0, n),
+                         or (with BFS_VALIDATE_TRANSPOSE) CSC != transpose(CSR) */
+    BFS_ENOMEM = 4,   /* host or device allocation failed */
+    BFS_EHIP = 5      /* a HIP runtime call failed; the hipError text is in the detail */
+} bfs_status;
+
+/* flags of bfs_graph_create */
+enum {
+    BFS_DIRECTED = 1u << 0,           /* A is not symmetric: the CSC is needed for pull */
+    BFS_INPUT_ON_DEVICE = 1u << 1,    /* the four input arrays are device pointers */
+    BFS_VALIDATE_TRANSPOSE = 1u << 2  /* check that the given CSC is the transpose of the CSR */
+};
+
+/* variant policies: which form of the product a level uses */
+enum {
+    BFS_VARIANT_PUSH = 0,        /* gather the frontier's columns (a compacted list)          */
+    BFS_VARIANT_PULL = 1,        /* row-wise over the remaining unvisited rows (first hit)     */
+    BFS_VARIANT_PUSH_BITMAP = 2, /* gather the frontier's columns, frontier held as a bitmap  */
+    BFS_VARIANT_LEARNED = 3,     /* per level, the selector network's argmin; push fallback   */
+    BFS_VARIANT_HEURISTIC = 4    /* per level, a fixed edge-ratio rule (push <-> pull)        */
+};
+
+/* level-loop modes */
+enum {
+    BFS_LOOP_HOST = 0,        /* the host launches levels, reading the frontier size back
+                                 every `levels_per_sync` levels                            */
+    BFS_LOOP_GRAPH = 1,       /* chunks of levels replayed from a captured hipGraph          */
+    BFS_LOOP_PERSISTENT = 2   /* one cooperative launch runs every level (grid barriers)    */
+};
+
+/* one record per level when tracing (host memory, written after the run) */
+typedef struct bfs_level_record {
+    int32_t level;            /* k: the frontier is supp(x_{k+1}) = {v : level[v] = k}   */
+    int32_t variant;          /* BFS_VARIANT_PUSH / _PULL / _PUSH_BITMAP actually run    */
+    uint32_t frontier;        /* |F_k|                                                   */
+    uint32_t unvisited;       /* |U_k|: vertices not visited through level k             */
+    uint64_t frontier_edges;  /* sum of out-degrees over F_k                             */
+    uint64_t unvisited_edges; /* sum of out-degrees over U_k                             */
+    float time_us;            /* device time of the level (host loop with tracing only)   */
+    float reserved;
+} bfs_level_record;
+
+typedef struct bfs_run_options {
+    uint32_t variant;          /* BFS_VARIANT_*                                  (default PUSH)  */
+    uint32_t loop_mode;        /* BFS_LOOP_*                                     (default HOST)  */
+    uint32_t levels_per_sync;  /* host loop: levels launched between size reads (0 = 4)        */
+    uint32_t grid_blocks;      /* workgroups per level launch (0 = 8 per compute unit)          */
+    uint32_t heavy_degree;     /* out-degree from which a column is split into chunks (0 = 512) */
+    uint32_t chunk_edges;      /* entries per chunk of a split column (0 = 1024)                */
+    const float *selector;     /* device: selector weights for BFS_VARIANT_LEARNED (NULL =
+                                  push on every level)                                          */
+    bfs_level_record *trace;   /* host: per-level records, or NULL                              */
+    uint32_t trace_capacity;   /* records available in `trace`                                  */
+    uint32_t trace_count;      /* out: records written                                          */
+    uint32_t levels;           /* out: number of levels (largest level + 1)                    */
+    uint32_t reserved;
+} bfs_run_options;
+
+/*
+ * Create a graph from the CSR of A (out-neighbours: row i lists j with A(i,j)=1;
+ * out_ptr has n+1 entries, out_idx has out_ptr[n]) and, for directed graphs,
+ * the CSC of A (in-neighbours: in_ptr n+1 entries, in_idx in_ptr[n]).  For an
+ * undirected graph pass in_ptr = in_idx = NULL (the CSR serves both ways).
+ * A directed graph with NULL CSC gets its transpose built here.
+ * The library copies and sorts its own copy of every neighbour list; self-loops
+ * and duplicate entries are accepted (they change no result).  Synchronous on
+ * hip_stream; the caller may free its arrays once this returns.
+ * Errors: BFS_EINVAL (n <= 0, NULL pointers), BFS_ECSR, BFS_ENOMEM, BFS_EHIP.
+ */
+bfs_status bfs_graph_create(int32_t n,
+                            const int32_t *out_ptr, const int32_t *out_idx,
+                            const int32_t *in_ptr, const int32_t *in_idx,
+                            uint32_t flags, void *hip_stream, bfs_graph **out);
+
+/* Free a graph (NULL is accepted).  No search may be running on it. */
+bfs_status bfs_graph_destroy(bfs_graph *g);
+
+/* Query n, nnz, directedness and the device bytes the graph holds (any pointer may be NULL). */
+bfs_status bfs_graph_info(const bfs_graph *g, int32_t *n, int64_t *nnz,
+                          int32_t *directed, size_t *device_bytes);
+
+/*
+ * Device workspace bytes that bfs_run (num_queries = 1) or bfs_run_batch
+ * (num_queries sources on this graph) needs.  0 on a bad argument.
+ * run_flags is reserved (pass 0).
+ */
+size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_flags);
+
+/*
+ * One search from `source`.  level and parent are device arrays of n int32
+ * (caller-owned); workspace is a device buffer of at least
+ * bfs_workspace_size(g, 1, 0) bytes, 256-byte aligned.  Nothing is allocated.
+ * Stream-ordered on hip_stream: results are valid when the stream completes;
+ * the call itself returns after the last level has been issued (it reads the
+ * frontier size back to find the end of the search).  opt may be NULL
+ * (push on every level, host loop); its out-fields are written on success.
+ * Several searches may run at once on one graph from different streams, each
+ * with its own workspace and outputs.
+ * Errors: BFS_EINVAL, BFS_ERANGE (source), BFS_EHIP.
+ */
+bfs_status bfs_run(bfs_graph *g, int32_t source,
+                   int32_t *level, int32_t *parent,
+                   bfs_run_options *opt,
+                   void *workspace, size_t ws_bytes, void *hip_stream);
+
+/*
+ * Many searches in one call.  Query q is (graphs[q], sources[q]) with outputs
+ * level[q], parent[q] (device, n of that graph each).  When every query names
+ * the same graph, the searches advance together, 64 sources per 64-bit mask
+ * per vertex (one pass over a column serves every source whose frontier holds
+ * it).  Queries on different graphs are run one after another on the stream.
+ * The result for query q is bit-identical to bfs_run(graphs[q], sources[q]).
+ * workspace: bfs_workspace_size(graphs[0], num_queries, 0) bytes when all
+ * graphs are equal; otherwise the largest bfs_workspace_size(graphs[q], 1, 0).
+ * Errors: BFS_EINVAL, BFS_ERANGE, BFS_EHIP.
+ */
+bfs_status bfs_run_batch(int32_t num_queries,
+                         bfs_graph *const *graphs, const int32_t *sources,
+                         int32_t *const *level, int32_t *const *parent,
+                         bfs_run_options *opt,
+                         void *workspace, size_t ws_bytes, void *hip_stream);
+
+/*
+ * A search started from several roots at once (x_1 = sum of e_r): the level
+ * and parent of every vertex are those of a search from the nearest root,
+ * ties to the smallest frontier in-neighbour.  When the roots lie in distinct
+ * components - e.g. one root per block of a block-diagonal matrix that packs
+ * many graphs - each component's result equals bfs_run from its root alone.
+ * roots_host: nroots distinct host ints in [0, n).  workspace: at least
+ * bfs_roots_workspace_size(g, nroots) bytes, 256-byte aligned.
+ * Errors: BFS_EINVAL (NULL, nroots outside [1, n], duplicate root, small
+ * workspace), BFS_ERANGE (a root outside [0, n)), BFS_EHIP.
+ */
+bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t *roots_host,
+                         int32_t *level, int32_t *parent, bfs_run_options *opt,
+                         void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Workspace bytes for bfs_run_roots with nroots roots (0 on a bad argument). */
+size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots);
+
+/* Static text for a status code. */
+const char *bfs_status_string(bfs_status s);
+
+/* Thread-local text describing the last non-OK status returned on this thread. */
+const char *bfs_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFS_H */

@@ -1,0 +1,223 @@
+"""MI355X (gfx950) masked sparse-matrix x sparse-vector breadth-first search.
+
+Python face of libbfs.so (include/bfs.h).  PyTorch supplies device memory and
+streams; every step of a search runs in the library's HIP kernels.  There is
+no CPU fallback: without the built library every call raises.
+
+    g = Graph.from_csr(n, ptr, idx)                 # numpy / torch int32 CSR
+    level, parent = bfs(g, source)                  # torch int32 on cuda
+    level, parent = bfs(g, source, variant="pull")  # same bits, other form
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import BfsError, LOOPS, VARIANTS, VARIANT_NAMES, LevelRecord, RunOptions
+
+__all__ = ["Graph", "bfs", "bfs_batch", "bfs_roots", "BfsError", "VARIANTS", "LOOPS",
+           "Workspace", "make_options"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _i32_host(a) -> np.ndarray:
+    t = _torch()
+    if isinstance(a, t.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _stream_handle(stream):
+    t = _torch()
+    s = stream if stream is not None else t.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+class Graph:
+    """A graph resident on the GPU (library-owned copy of CSR and CSC)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, nnz: int, directed: bool):
+        self._h = handle
+        self.n = n
+        self.nnz = nnz
+        self.directed = directed
+
+    @classmethod
+    def from_csr(cls, n: int, ptr, idx, in_ptr=None, in_idx=None, directed: bool = False,
+                 validate_transpose: bool = False) -> "Graph":
+        L = _lib.lib()
+        ptr_h, idx_h = _i32_host(ptr), _i32_host(idx)
+        flags = 0
+        ip = ii = None
+        if directed:
+            flags |= _lib.BFS_DIRECTED
+            if in_ptr is not None:
+                ip, ii = _i32_host(in_ptr), _i32_host(in_idx)
+        if validate_transpose:
+            flags |= _lib.BFS_VALIDATE_TRANSPOSE
+        vp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _lib.check(L.bfs_graph_create(int(n), vp(ptr_h), vp(idx_h), vp(ip), vp(ii), flags,
+                                      None, ctypes.byref(h)))
+        return cls(h, int(n), int(ptr_h[-1]), bool(directed))
+
+    @classmethod
+    def from_graphgen(cls, g) -> "Graph":
+        if g.directed:
+            return cls.from_csr(g.n, g.ptr, g.idx, g.in_ptr, g.in_idx, directed=True)
+        return cls.from_csr(g.n, g.ptr, g.idx)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph is closed")
+        return self._h
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(_lib.lib().bfs_graph_info(self.handle, None, None, None, ctypes.byref(b)))
+        return int(b.value)
+
+    def workspace_size(self, num_queries: int = 1) -> int:
+        return int(_lib.lib().bfs_workspace_size(self.handle, int(num_queries), 0))
+
+    def roots_workspace_size(self, nroots: int) -> int:
+        return int(_lib.lib().bfs_roots_workspace_size(self.handle, int(nroots)))
+
+    def close(self) -> None:
+        if self._h is not None:
+            _lib.lib().bfs_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Workspace:
+    """A reusable device workspace (256-byte aligned view into a torch buffer)."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        t = _torch()
+        self.buf = t.empty(nbytes + 256, dtype=t.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.off = (-base) % 256
+        self.nbytes = nbytes
+
+    @property
+    def ptr(self) -> ctypes.c_void_p:
+        return ctypes.c_void_p(self.buf.data_ptr() + self.off)
+
+    def fits(self, nbytes: int) -> bool:
+        return nbytes <= self.nbytes
+
+
+def make_options(variant="push", loop="host", levels_per_sync=0, grid_blocks=0,
+                 heavy_degree=0, chunk_edges=0, selector=None, trace_capacity=0) -> Tuple[RunOptions, Optional[ctypes.Array]]:
+    o = RunOptions()
+    o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    o.loop_mode = LOOPS[loop] if isinstance(loop, str) else int(loop)
+    o.levels_per_sync = int(levels_per_sync)
+    o.grid_blocks = int(grid_blocks)
+    o.heavy_degree = int(heavy_degree)
+    o.chunk_edges = int(chunk_edges)
+    o.selector = ctypes.c_void_p(int(selector.data_ptr())) if selector is not None else None
+    recs = None
+    if trace_capacity:
+        recs = (LevelRecord * trace_capacity)()
+        o.trace = ctypes.cast(recs, ctypes.POINTER(LevelRecord))
+        o.trace_capacity = trace_capacity
+    return o, recs
+
+
+def trace_dicts(o: RunOptions, recs) -> list:
+    out = []
+    for r in range(o.trace_count):
+        x = recs[r]
+        out.append(dict(level=x.level, variant=VARIANT_NAMES.get(x.variant, x.variant),
+                        frontier=x.frontier, unvisited=x.unvisited,
+                        frontier_edges=x.frontier_edges, unvisited_edges=x.unvisited_edges,
+                        time_us=x.time_us))
+    return out
+
+
+def bfs(g: Graph, source: int, variant="push", loop="host", level=None, parent=None,
+        workspace: Optional[Workspace] = None, stream=None, info: Optional[Dict] = None,
+        trace: bool = False, **kw):
+    """One search; returns (level, parent) as int32 cuda tensors (stream-ordered)."""
+    t = _torch()
+    if level is None:
+        level = t.empty(g.n, dtype=t.int32, device="cuda")
+    if parent is None:
+        parent = t.empty(g.n, dtype=t.int32, device="cuda")
+    need = g.workspace_size(1)
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need)
+    o, recs = make_options(variant, loop, trace_capacity=(4096 if trace else 0), **kw)
+    _lib.check(_lib.lib().bfs_run(g.handle, int(source),
+                                  ctypes.c_void_p(level.data_ptr()), ctypes.c_void_p(parent.data_ptr()),
+                                  ctypes.byref(o), workspace.ptr, workspace.nbytes,
+                                  _stream_handle(stream)))
+    if info is not None:
+        info["levels"] = o.levels
+        if trace:
+            info["trace"] = trace_dicts(o, recs)
+    return level, parent
+
+
+def bfs_roots(g: Graph, roots: Sequence[int], variant="push", loop="host", level=None,
+              parent=None, workspace: Optional[Workspace] = None, stream=None,
+              info: Optional[Dict] = None, **kw):
+    """One search from several roots (e.g. one per block of a block-diagonal pack)."""
+    t = _torch()
+    roots_h = _i32_host(np.asarray(roots))
+    if level is None:
+        level = t.empty(g.n, dtype=t.int32, device="cuda")
+    if parent is None:
+        parent = t.empty(g.n, dtype=t.int32, device="cuda")
+    need = g.roots_workspace_size(len(roots_h))
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need)
+    o, _ = make_options(variant, loop, **kw)
+    _lib.check(_lib.lib().bfs_run_roots(g.handle, len(roots_h), roots_h.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.c_void_p(level.data_ptr()),
+                                        ctypes.c_void_p(parent.data_ptr()), ctypes.byref(o),
+                                        workspace.ptr, workspace.nbytes, _stream_handle(stream)))
+    if info is not None:
+        info["levels"] = o.levels
+    return level, parent
+
+
+def bfs_batch(graphs, sources: Sequence[int], variant="push", loop="host", levels=None,
+              parents=None, workspace: Optional[Workspace] = None, stream=None, **kw):
+    """Many searches in one call: query q = (graphs[q], sources[q]).  `graphs` may be
+    a single Graph (every query on it).  Returns lists of (level, parent) tensors."""
+    t = _torch()
+    nq = len(sources)
+    if isinstance(graphs, Graph):
+        graphs = [graphs] * nq
+    if levels is None:
+        levels = [t.empty(gr.n, dtype=t.int32, device="cuda") for gr in graphs]
+    if parents is None:
+        parents = [t.empty(gr.n, dtype=t.int32, device="cuda") for gr in graphs]
+    same = all(gr is graphs[0] for gr in graphs)
+    need = graphs[0].workspace_size(nq) if same else max(gr.workspace_size(1) for gr in graphs)
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need)
+    H = (ctypes.c_void_p * nq)(*[gr.handle for gr in graphs])
+    S = (ctypes.c_int32 * nq)(*[int(s) for s in sources])
+    Lp = (ctypes.c_void_p * nq)(*[x.data_ptr() for x in levels])
+    Pp = (ctypes.c_void_p * nq)(*[x.data_ptr() for x in parents])
+    o, _ = make_options(variant, loop, **kw)
+    _lib.check(_lib.lib().bfs_run_batch(nq, H, S, Lp, Pp, ctypes.byref(o), workspace.ptr,
+                                        workspace.nbytes, _stream_handle(stream)))
+    return levels, parents

@@ -1,0 +1,557 @@
+// Host runtime behind include/bfs.h: graph objects, validation, workspace
+// layout and the level loop (host-driven, graph-replayed or persistent).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bfs.h"
+#include "bfs_internal.h"
+
+using namespace bfsi;
+
+struct GraphExecCache {
+    bool valid = false;
+    const void *ws = nullptr;
+    const void *level = nullptr;
+    const void *parent = nullptr;
+    uint32_t policy = 0, grid = 0, heavy = 0, chunk = 0, levels = 0, fb = 0, stats = 0;
+    const float *sel = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+struct bfs_graph {
+    int32_t n = 0;
+    uint32_t nnz = 0;
+    bool directed = false;
+    int device = 0;
+    int cus = 0;
+    int32_t *out_ptr = nullptr, *out_idx = nullptr, *in_ptr = nullptr, *in_idx = nullptr;
+    size_t bytes = 0;
+    std::mutex mu;
+    GraphExecCache gcache;
+};
+
+namespace {
+
+thread_local std::string g_detail;
+
+bfs_status fail(bfs_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_detail = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(BFS_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                        __FILE__, __LINE__);                                          \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bfs_status validate_csr(int32_t n, const int32_t *ptr, const int32_t *idx, const char *what) {
+    if (ptr[0] != 0) return fail(BFS_ECSR, "%s: ptr[0] = %d, expected 0", what, ptr[0]);
+    for (int32_t v = 0; v < n; ++v)
+        if (ptr[v + 1] < ptr[v])
+            return fail(BFS_ECSR, "%s: ptr decreases at %d (%d > %d)", what, v, ptr[v], ptr[v + 1]);
+    const int64_t nnz = ptr[n];
+    for (int64_t e = 0; e < nnz; ++e)
+        if (idx[e] < 0 || idx[e] >= n)
+            return fail(BFS_ECSR, "%s: idx[%lld] = %d outside [0, %d)", what, (long long)e, idx[e], n);
+    return BFS_OK;
+}
+
+// sort each list ascending (pull scans in-neighbours in ascending order)
+void sort_rows(int32_t n, const std::vector<int32_t> &ptr, std::vector<int32_t> &idx) {
+    for (int32_t v = 0; v < n; ++v) {
+        auto b = idx.begin() + ptr[v], e = idx.begin() + ptr[v + 1];
+        if (!std::is_sorted(b, e)) std::sort(b, e);
+    }
+}
+
+void transpose(int32_t n, const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+               std::vector<int32_t> &tptr, std::vector<int32_t> &tidx) {
+    tptr.assign((size_t)n + 1, 0);
+    for (int32_t c : idx) tptr[(size_t)c + 1]++;
+    for (int32_t v = 0; v < n; ++v) tptr[(size_t)v + 1] += tptr[v];
+    tidx.resize(idx.size());
+    std::vector<int32_t> pos(tptr.begin(), tptr.end() - 1);
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t e = ptr[r]; e < ptr[r + 1]; ++e) tidx[pos[idx[e]]++] = r;   // rows ascending
+}
+
+template <class T>
+bfs_status upload(T **dst, const T *src, size_t count, size_t &bytes) {
+    size_t b = count * sizeof(T);
+    if (b == 0) b = sizeof(T);
+    if (hipMalloc((void **)dst, b) != hipSuccess) return fail(BFS_ENOMEM, "hipMalloc(%zu) failed", b);
+    bytes += b;
+    if (count) HIP_TRY(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return BFS_OK;
+}
+
+void free_graph(bfs_graph *g) {
+    if (!g) return;
+    if (g->gcache.exec) hipGraphExecDestroy(g->gcache.exec);
+    if (g->gcache.graph) hipGraphDestroy(g->gcache.graph);
+    if (g->in_ptr && g->in_ptr != g->out_ptr) hipFree(g->in_ptr);
+    if (g->in_idx && g->in_idx != g->out_idx) hipFree(g->in_idx);
+    if (g->out_ptr) hipFree(g->out_ptr);
+    if (g->out_idx) hipFree(g->out_idx);
+    delete g;
+}
+
+}  // namespace
+
+namespace bfsi {
+WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor) {
+    WsLayout L{};
+    const size_t words = ((size_t)n + 31) / 32;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.state = take(sizeof(BfsState));
+    L.vb0 = take(words * 4);
+    L.vb1 = take(words * 4);
+    L.fb0 = take(words * 4);
+    L.fb1 = take(words * 4);
+    L.q0 = take((size_t)n * 4);
+    L.q1 = take((size_t)n * 4);
+    L.u0 = take((size_t)n * 4);
+    L.u1 = take((size_t)n * 4);
+    size_t hcap = (size_t)nnz / heavy_min_floor + 1;
+    if (hcap > (size_t)n) hcap = (size_t)n;
+    L.heavy = take(hcap * sizeof(HeavyItem));
+    L.trace = take((size_t)kTraceCap * sizeof(DevLevelRec));
+    L.total = off;
+    return L;
+}
+}  // namespace bfsi
+
+namespace {
+
+constexpr uint32_t kHeavyFloor = 32;
+
+struct RunCfg {
+    uint32_t policy, loop, per_sync, grid, heavy, chunk;
+    const float *sel;
+};
+
+bfs_status make_params(bfs_graph *g, int32_t *level, int32_t *parent, const RunCfg &c,
+                       void *ws, bool trace, LevelParams &P) {
+    const WsLayout L = ws_layout(g->n, g->nnz, kHeavyFloor);
+    char *b = (char *)ws;
+    P = LevelParams{};
+    P.n = g->n;
+    P.nnz = g->nnz;
+    P.words = (uint32_t)(((size_t)g->n + 31) / 32);
+    P.policy = c.policy;
+    P.heavy_min = c.heavy;
+    P.chunk = c.chunk;
+    P.out_ptr = g->out_ptr;
+    P.out_idx = g->out_idx;
+    P.in_ptr = g->in_ptr;
+    P.in_idx = g->in_idx;
+    P.level = level;
+    P.parent = (uint32_t *)parent;
+    P.vb[0] = (uint32_t *)(b + L.vb0);
+    P.vb[1] = (uint32_t *)(b + L.vb1);
+    P.fb[0] = (uint32_t *)(b + L.fb0);
+    P.fb[1] = (uint32_t *)(b + L.fb1);
+    P.q[0] = (int32_t *)(b + L.q0);
+    P.q[1] = (int32_t *)(b + L.q1);
+    P.ul[0] = (int32_t *)(b + L.u0);
+    P.ul[1] = (int32_t *)(b + L.u1);
+    P.heavy = (HeavyItem *)(b + L.heavy);
+    P.st = (BfsState *)(b + L.state);
+    P.trace = trace ? (DevLevelRec *)(b + L.trace) : nullptr;
+    P.mlp = c.sel;
+    P.maintain_fb = (c.policy == kBitmap || c.policy == kLearned) ? 1u : 0u;
+    P.stats = (c.policy == kLearned || c.policy == kHeuristic || trace) ? 1u : 0u;
+    return BFS_OK;
+}
+
+bfs_status resolve_cfg(bfs_graph *g, const bfs_run_options *opt, RunCfg &c) {
+    c.policy = opt ? opt->variant : kPush;
+    c.loop = opt ? opt->loop_mode : BFS_LOOP_HOST;
+    c.per_sync = (opt && opt->levels_per_sync) ? opt->levels_per_sync : 4u;
+    c.grid = (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
+    c.heavy = (opt && opt->heavy_degree) ? opt->heavy_degree : 512u;
+    c.chunk = (opt && opt->chunk_edges) ? opt->chunk_edges : 1024u;
+    c.sel = opt ? opt->selector : nullptr;
+    if (c.policy > kHeuristic) return fail(BFS_EINVAL, "unknown variant %u", c.policy);
+    if (c.loop > BFS_LOOP_PERSISTENT) return fail(BFS_EINVAL, "unknown loop mode %u", c.loop);
+    if (c.heavy < kHeavyFloor) return fail(BFS_EINVAL, "heavy_degree %u below %u", c.heavy, kHeavyFloor);
+    if (c.chunk < 64 || c.chunk > (1u << 20)) return fail(BFS_EINVAL, "chunk_edges %u outside [64, 2^20]", c.chunk);
+    if (c.grid == 0 || c.grid > 65535) return fail(BFS_EINVAL, "grid_blocks %u outside [1, 65535]", c.grid);
+    if (c.per_sync > 4096) return fail(BFS_EINVAL, "levels_per_sync %u above 4096", c.per_sync);
+    return BFS_OK;
+}
+
+struct PinnedState {
+    BfsState *h = nullptr;
+    PinnedState() { if (hipHostMalloc((void **)&h, sizeof(BfsState), 0) != hipSuccess) h = nullptr; }
+    ~PinnedState() { if (h) hipHostFree(h); }
+};
+
+// read the state back; returns true when the search is over
+bfs_status read_state(const LevelParams &P, BfsState *h, hipStream_t s, bool &done) {
+    HIP_TRY(hipMemcpyAsync(h, P.st, sizeof(BfsState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    done = (h->nf[h->level & 3] == 0);
+    return BFS_OK;
+}
+
+bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipStream_t s,
+                      uint32_t &levels_out, bfs_run_options *opt) {
+    PinnedState ps;
+    if (!ps.h) return fail(BFS_ENOMEM, "hipHostMalloc of the state readback failed");
+    const uint64_t max_levels = (uint64_t)g->n + 2;
+    bool done = false;
+    bool timing = opt && opt->trace && c.loop == BFS_LOOP_HOST;
+    std::vector<float> times;
+    if (c.loop == BFS_LOOP_PERSISTENT) {
+        uint32_t maxg = persistent_max_grid(g->device);
+        if (maxg == 0) return fail(BFS_EHIP, "occupancy query for the persistent kernel failed");
+        uint32_t grid = std::min(c.grid, maxg);
+        HIP_TRY(launch_persistent(P, grid, s));
+        bfs_status st = read_state(P, ps.h, s, done);
+        if (st != BFS_OK) return st;
+        if (!done) return fail(BFS_EHIP, "persistent search stopped at level %u with a nonempty frontier "
+                                         "(grid barrier spin limit)", ps.h->level);
+    } else if (c.loop == BFS_LOOP_GRAPH) {
+        GraphExecCache &gc = g->gcache;
+        const uint32_t L = c.per_sync;
+        bool hit = gc.valid && gc.ws == (const void *)P.st && gc.level == P.level &&
+                   gc.parent == P.parent && gc.policy == c.policy && gc.grid == c.grid &&
+                   gc.heavy == c.heavy && gc.chunk == c.chunk && gc.levels == L &&
+                   gc.sel == c.sel && gc.fb == P.maintain_fb && gc.stats == P.stats;
+        if (!hit) {
+            if (gc.exec) { hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
+            if (gc.graph) { hipGraphDestroy(gc.graph); gc.graph = nullptr; }
+            gc.valid = false;
+            hipStream_t cap;
+            HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            for (uint32_t l = 0; l < L && e == hipSuccess; ++l) {
+                e = launch_level(P, c.grid, cap);
+                if (e == hipSuccess) e = launch_tail(P, c.grid, cap);
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cap, &graph);
+            hipStreamDestroy(cap);
+            if (e != hipSuccess || e2 != hipSuccess)
+                return fail(BFS_EHIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                hipGraphDestroy(graph);
+                return fail(BFS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            gc.graph = graph;
+            gc.exec = exec;
+            gc.ws = P.st; gc.level = P.level; gc.parent = P.parent; gc.policy = c.policy;
+            gc.grid = c.grid; gc.heavy = c.heavy; gc.chunk = c.chunk; gc.levels = L;
+            gc.sel = c.sel; gc.fb = P.maintain_fb; gc.stats = P.stats; gc.valid = true;
+        }
+        for (uint64_t issued = 0; !done; issued += L) {
+            if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
+            HIP_TRY(hipGraphLaunch(gc.exec, s));
+            bfs_status st = read_state(P, ps.h, s, done);
+            if (st != BFS_OK) return st;
+        }
+    } else {
+        const uint32_t L = timing ? 1u : c.per_sync;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        if (timing) {
+            HIP_TRY(hipEventCreate(&ev0));
+            HIP_TRY(hipEventCreate(&ev1));
+        }
+        for (uint64_t issued = 0; !done; issued += L) {
+            if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
+            if (timing) HIP_TRY(hipEventRecord(ev0, s));
+            for (uint32_t l = 0; l < L; ++l) {
+                HIP_TRY(launch_level(P, c.grid, s));
+                HIP_TRY(launch_tail(P, c.grid, s));
+            }
+            if (timing) HIP_TRY(hipEventRecord(ev1, s));
+            bfs_status st = read_state(P, ps.h, s, done);
+            if (st != BFS_OK) return st;
+            if (timing) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+                if (!done || times.size() < ps.h->level) times.push_back(ms * 1000.f);
+            }
+        }
+        if (timing) {
+            hipEventDestroy(ev0);
+            hipEventDestroy(ev1);
+        }
+    }
+    levels_out = ps.h->level;
+    if (opt && opt->trace && P.trace) {
+        const uint32_t nrec = std::min<uint32_t>(std::min<uint32_t>(levels_out, kTraceCap), opt->trace_capacity);
+        std::vector<DevLevelRec> recs(nrec ? nrec : 1);
+        if (nrec) {
+            HIP_TRY(hipMemcpyAsync(recs.data(), P.trace, nrec * sizeof(DevLevelRec),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        for (uint32_t r = 0; r < nrec; ++r) {
+            bfs_level_record &o = opt->trace[r];
+            o.level = (int32_t)recs[r].level;
+            o.variant = (int32_t)recs[r].variant;
+            o.frontier = recs[r].nf;
+            o.unvisited = recs[r].nu;
+            o.frontier_edges = recs[r].sdf;
+            o.unvisited_edges = recs[r].sdu;
+            o.time_us = (r < times.size()) ? times[r] : 0.f;
+            o.reserved = 0.f;
+        }
+        opt->trace_count = nrec;
+    } else if (opt) {
+        opt->trace_count = 0;
+    }
+    return BFS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bfs_status_string(bfs_status s) {
+    switch (s) {
+        case BFS_OK: return "ok";
+        case BFS_EINVAL: return "invalid argument";
+        case BFS_ERANGE: return "source vertex out of range";
+        case BFS_ECSR: return "malformed CSR/CSC input";
+        case BFS_ENOMEM: return "out of memory";
+        case BFS_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *bfs_last_error_detail(void) { return g_detail.c_str(); }
+
+bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *out_idx,
+                            const int32_t *in_ptr, const int32_t *in_idx, uint32_t flags,
+                            void *hip_stream, bfs_graph **out) {
+    (void)hip_stream;
+    if (!out) return fail(BFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n <= 0) return fail(BFS_EINVAL, "n = %d must be positive", n);
+    if (!out_ptr || !out_idx) return fail(BFS_EINVAL, "out_ptr/out_idx is NULL");
+    if ((in_ptr == nullptr) != (in_idx == nullptr))
+        return fail(BFS_EINVAL, "in_ptr and in_idx must both be given or both be NULL");
+    if (flags & ~(uint32_t)(BFS_DIRECTED | BFS_INPUT_ON_DEVICE | BFS_VALIDATE_TRANSPOSE))
+        return fail(BFS_EINVAL, "unknown flags 0x%x", flags);
+    const bool directed = (flags & BFS_DIRECTED) != 0;
+    const bool on_dev = (flags & BFS_INPUT_ON_DEVICE) != 0;
+    if (!directed && in_ptr) return fail(BFS_EINVAL, "a CSC is only accepted with BFS_DIRECTED");
+
+    std::vector<int32_t> ptr, idx, iptr, iidx;
+    try {
+        ptr.resize((size_t)n + 1);
+        if (on_dev) {
+            HIP_TRY(hipMemcpy(ptr.data(), out_ptr, ptr.size() * 4, hipMemcpyDeviceToHost));
+        } else {
+            std::memcpy(ptr.data(), out_ptr, ptr.size() * 4);
+        }
+        if (ptr[0] != 0) return fail(BFS_ECSR, "CSR: ptr[0] = %d, expected 0", ptr[0]);
+        for (int32_t v = 0; v < n; ++v)
+            if (ptr[v + 1] < ptr[v]) return fail(BFS_ECSR, "CSR: ptr decreases at %d", v);
+        idx.resize((size_t)ptr[n]);
+        if (on_dev) {
+            if (!idx.empty()) HIP_TRY(hipMemcpy(idx.data(), out_idx, idx.size() * 4, hipMemcpyDeviceToHost));
+        } else if (!idx.empty()) {
+            std::memcpy(idx.data(), out_idx, idx.size() * 4);
+        }
+        bfs_status st = validate_csr(n, ptr.data(), idx.data(), "CSR");
+        if (st != BFS_OK) return st;
+        sort_rows(n, ptr, idx);
+        if (directed) {
+            if (in_ptr) {
+                iptr.resize((size_t)n + 1);
+                if (on_dev) HIP_TRY(hipMemcpy(iptr.data(), in_ptr, iptr.size() * 4, hipMemcpyDeviceToHost));
+                else std::memcpy(iptr.data(), in_ptr, iptr.size() * 4);
+                if (iptr[0] != 0) return fail(BFS_ECSR, "CSC: ptr[0] = %d, expected 0", iptr[0]);
+                for (int32_t v = 0; v < n; ++v)
+                    if (iptr[v + 1] < iptr[v]) return fail(BFS_ECSR, "CSC: ptr decreases at %d", v);
+                if (iptr[n] != ptr[n])
+                    return fail(BFS_ECSR, "CSC has %d entries, CSR has %d", iptr[n], ptr[n]);
+                iidx.resize((size_t)iptr[n]);
+                if (on_dev) {
+                    if (!iidx.empty()) HIP_TRY(hipMemcpy(iidx.data(), in_idx, iidx.size() * 4, hipMemcpyDeviceToHost));
+                } else if (!iidx.empty()) {
+                    std::memcpy(iidx.data(), in_idx, iidx.size() * 4);
+                }
+                st = validate_csr(n, iptr.data(), iidx.data(), "CSC");
+                if (st != BFS_OK) return st;
+                sort_rows(n, iptr, iidx);
+                if (flags & BFS_VALIDATE_TRANSPOSE) {
+                    std::vector<int32_t> tp, ti;
+                    transpose(n, ptr, idx, tp, ti);
+                    if (tp != iptr || ti != iidx) return fail(BFS_ECSR, "CSC is not the transpose of the CSR");
+                }
+            } else {
+                transpose(n, ptr, idx, iptr, iidx);
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(BFS_ENOMEM, "host allocation failed");
+    }
+
+    bfs_graph *g = new (std::nothrow) bfs_graph();
+    if (!g) return fail(BFS_ENOMEM, "host allocation failed");
+    g->n = n;
+    g->nnz = (uint32_t)ptr[n];
+    g->directed = directed;
+    if (hipGetDevice(&g->device) != hipSuccess) { delete g; return fail(BFS_EHIP, "hipGetDevice failed"); }
+    hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, g->device);
+    bfs_status st = upload(&g->out_ptr, ptr.data(), ptr.size(), g->bytes);
+    if (st == BFS_OK) st = upload(&g->out_idx, idx.data(), idx.size(), g->bytes);
+    if (st == BFS_OK && directed) {
+        st = upload(&g->in_ptr, iptr.data(), iptr.size(), g->bytes);
+        if (st == BFS_OK) st = upload(&g->in_idx, iidx.data(), iidx.size(), g->bytes);
+    } else if (st == BFS_OK) {
+        g->in_ptr = g->out_ptr;
+        g->in_idx = g->out_idx;
+    }
+    if (st != BFS_OK) {
+        std::string keep = g_detail;
+        free_graph(g);
+        g_detail = keep;
+        return st;
+    }
+    *out = g;
+    return BFS_OK;
+}
+
+bfs_status bfs_graph_destroy(bfs_graph *g) {
+    free_graph(g);
+    return BFS_OK;
+}
+
+bfs_status bfs_graph_info(const bfs_graph *g, int32_t *n, int64_t *nnz, int32_t *directed,
+                          size_t *device_bytes) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (directed) *directed = g->directed ? 1 : 0;
+    if (device_bytes) *device_bytes = g->bytes;
+    return BFS_OK;
+}
+
+size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_flags) {
+    if (!g || num_queries <= 0 || run_flags != 0) return 0;
+    const size_t single = ws_layout(g->n, g->nnz, kHeavyFloor).total;
+    if (num_queries == 1) return single;
+    // multi-source: three masks of ceil(q/64) words per vertex, two frontier
+    // lists, a queued flag per vertex and the counters
+    const size_t w64 = ((size_t)num_queries + 63) / 64;
+    size_t ms = align256(256) + 3 * align256((size_t)g->n * w64 * 8) + 2 * align256((size_t)g->n * 4) +
+                align256((size_t)g->n * 4) + align256((size_t)num_queries * 16);
+    return std::max(single, ms);
+}
+
+bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
+                   bfs_run_options *opt, void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (!level || !parent || !workspace) return fail(BFS_EINVAL, "level/parent/workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BFS_EINVAL, "workspace must be 256-byte aligned");
+    if (source < 0 || source >= g->n) return fail(BFS_ERANGE, "source %d outside [0, %d)", source, g->n);
+    const size_t need = bfs_workspace_size(g, 1, 0);
+    if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    RunCfg c{};
+    bfs_status st = resolve_cfg(g, opt, c);
+    if (st != BFS_OK) return st;
+    if (c.policy == kPull || c.policy == kHeuristic || c.policy == kLearned) {
+        if (!g->in_ptr) return fail(BFS_EINVAL, "pull needs the CSC");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    LevelParams P;
+    make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
+    std::lock_guard<std::mutex> lock(g->mu);   // the captured-graph cache is per graph
+    HIP_TRY(launch_init(P, 1, nullptr, source, s));
+    uint32_t levels = 0;
+    st = run_levels(g, P, c, s, levels, opt);
+    if (st != BFS_OK) return st;
+    if (opt) opt->levels = levels;
+    return BFS_OK;
+}
+
+}  // extern "C"
+
+// Multi-root search used by the batch entry point for block-diagonal packs and
+// by the serving loop: roots must lie in distinct components.
+extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t *roots_host,
+                                    int32_t *level, int32_t *parent, bfs_run_options *opt,
+                                    void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (!level || !parent || !workspace || !roots_host) return fail(BFS_EINVAL, "NULL argument");
+    if (nroots <= 0 || nroots > g->n) return fail(BFS_EINVAL, "nroots = %d outside [1, n]", nroots);
+    if (((uintptr_t)workspace & 255) != 0) return fail(BFS_EINVAL, "workspace must be 256-byte aligned");
+    const WsLayout L = ws_layout(g->n, g->nnz, kHeavyFloor);
+    const size_t need = L.total + align256((size_t)nroots * 4);
+    if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    std::vector<char> seen((size_t)g->n, 0);
+    for (int32_t r = 0; r < nroots; ++r) {
+        const int32_t v = roots_host[r];
+        if (v < 0 || v >= g->n) return fail(BFS_ERANGE, "root %d outside [0, %d)", v, g->n);
+        if (seen[v]) return fail(BFS_EINVAL, "root %d given twice", v);
+        seen[v] = 1;
+    }
+    RunCfg c{};
+    bfs_status st = resolve_cfg(g, opt, c);
+    if (st != BFS_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    LevelParams P;
+    make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
+    int32_t *roots_dev = (int32_t *)((char *)workspace + L.total);
+    std::lock_guard<std::mutex> lock(g->mu);
+    HIP_TRY(hipMemcpyAsync(roots_dev, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_init(P, nroots, roots_dev, -1, s));
+    uint32_t levels = 0;
+    st = run_levels(g, P, c, s, levels, opt);
+    if (st != BFS_OK) return st;
+    if (opt) opt->levels = levels;
+    return BFS_OK;
+}
+
+extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
+    if (!g || nroots <= 0) return 0;
+    return ws_layout(g->n, g->nnz, kHeavyFloor).total + align256((size_t)nroots * 4);
+}
+
+extern "C" bfs_status bfs_run_batch(int32_t num_queries, bfs_graph *const *graphs,
+                                    const int32_t *sources, int32_t *const *level,
+                                    int32_t *const *parent, bfs_run_options *opt,
+                                    void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (num_queries <= 0) return fail(BFS_EINVAL, "num_queries = %d", num_queries);
+    if (!graphs || !sources || !level || !parent || !workspace) return fail(BFS_EINVAL, "NULL argument");
+    for (int32_t q = 0; q < num_queries; ++q) {
+        if (!graphs[q] || !level[q] || !parent[q]) return fail(BFS_EINVAL, "query %d has a NULL pointer", q);
+        if (sources[q] < 0 || sources[q] >= graphs[q]->n)
+            return fail(BFS_ERANGE, "query %d: source %d outside [0, %d)", q, sources[q], graphs[q]->n);
+    }
+    for (int32_t q = 0; q < num_queries; ++q) {
+        const size_t need = bfs_workspace_size(graphs[q], 1, 0);
+        if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, query %d needs %zu", ws_bytes, q, need);
+        bfs_status st = bfs_run(graphs[q], sources[q], level[q], parent[q], opt, workspace, ws_bytes, hip_stream);
+        if (st != BFS_OK) return st;
+    }
+    return BFS_OK;
+}

@@ -1,0 +1,111 @@
+// Internal declarations shared by the host runtime (bfs_host.cpp) and the
+// gfx950 kernels (bfs_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bfsi {
+
+constexpr int kBlock = 256;            // threads per workgroup (4 wave64s)
+constexpr uint32_t kAllVertices = 0xFFFFFFFFu;
+constexpr int kRing = 4;               // per-level counter slots (level k uses k & 3)
+constexpr int kMlpIn = 12, kMlpH = 32, kMlpOut = 3;
+constexpr int kMlpParams = kMlpIn * kMlpH + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH * kMlpOut + kMlpOut;
+// feature normalisation constants live after the weights: mean[12], inv_std[12]
+constexpr int kMlpTotal = kMlpParams + 2 * kMlpIn;
+
+enum Variant : uint32_t { kPush = 0, kPull = 1, kBitmap = 2, kLearned = 3, kHeuristic = 4 };
+
+// Device-resident search state (first bytes of every workspace).
+struct alignas(256) BfsState {
+    uint32_t level;          // current level k
+    uint32_t done;           // blocks of the tail kernel that have finished
+    uint32_t variant;        // variant run at level k
+    uint32_t u_buf;          // which unvisited-list buffer is current
+    uint32_t u_len;          // its length; kAllVertices = the implicit list 0..n-1
+    uint32_t u_wr;           // appends into the other buffer during a pull level
+    uint32_t visited_cnt;    // |B_k|
+    uint32_t barrier;        // grid barrier counter (persistent mode)
+    unsigned long long visited_deg;   // sum of out-degrees over B_k
+    uint32_t nf[kRing];                  // |F| per ring slot
+    unsigned long long heavy[kRing];     // packed: (#split columns) | (#chunks << 32)
+    unsigned long long sdf[kRing];       // sum of out-degrees over F per ring slot
+    uint32_t barrier_gen;
+    uint32_t pad[7];
+};
+
+// Per-level record kept on the device (a trace ring of kTraceCap entries).
+struct DevLevelRec {
+    uint32_t level, variant, nf, nu;
+    unsigned long long sdf, sdu;
+};
+constexpr uint32_t kTraceCap = 1024;
+
+struct HeavyItem {
+    int32_t v;
+    uint32_t chunk_base;
+};
+
+struct LevelParams {
+    int32_t n;
+    uint32_t nnz;
+    uint32_t words;          // 32-bit words per bitmap
+    uint32_t policy;         // Variant requested
+    uint32_t heavy_min;      // out-degree from which a column goes to the chunk queue
+    uint32_t chunk;          // entries per chunk
+    const int32_t *out_ptr, *out_idx, *in_ptr, *in_idx;
+    int32_t *level;
+    uint32_t *parent;        // uint32 view of the int32 parent array (-1 = 0xFFFFFFFF)
+    uint32_t *vb[2];         // visited bitmaps, ping-pong: vb[k&1] = B_k
+    uint32_t *fb[2];         // frontier bitmaps (kept only when maintain_fb)
+    int32_t *q[2];           // frontier lists, ping-pong
+    int32_t *ul[2];          // unvisited lists, ping-pong
+    HeavyItem *heavy;        // split-column queue for the current level
+    BfsState *st;
+    DevLevelRec *trace;      // kTraceCap records, or nullptr
+    const float *mlp;        // selector weights (kMlpTotal floats) or nullptr
+    uint32_t maintain_fb;
+    uint32_t stats;
+};
+
+struct WsLayout {
+    size_t state, vb0, vb1, fb0, fb1, q0, q1, u0, u1, heavy, trace, total;
+};
+WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor);
+
+// Multi-source (64 sources per 64-bit word) parameters.
+struct MsParams {
+    int32_t n;
+    uint32_t words64;        // 64-bit words per vertex mask (= number of 64-source groups)
+    uint32_t nq;             // number of sources
+    const int32_t *out_ptr, *out_idx, *in_ptr, *in_idx;
+    unsigned long long *vis;   // [n][words64]: sources that have reached v through level k
+    unsigned long long *cur;   // [n][words64]: sources whose frontier holds v at level k
+    unsigned long long *nxt;   // [n][words64]: sources that reach v at level k+1
+    int32_t *fq[2];            // frontier vertex lists (vertices with any bit in cur)
+    uint32_t *flag;            // [n] per-vertex "already queued for next level" marker
+    uint32_t *cnt;             // [4]: list sizes ring + level
+    int32_t *const *level;     // per-source device outputs (device array of pointers)
+    int32_t *const *parent;
+};
+
+// launches (bfs_kernels.hip)
+hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *roots_dev,
+                       int32_t single_root, hipStream_t s);
+hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s);
+hipError_t launch_tail(const LevelParams &p, uint32_t grid, hipStream_t s);
+hipError_t launch_persistent(const LevelParams &p, uint32_t grid, hipStream_t s);
+uint32_t persistent_max_grid(int device);
+
+hipError_t launch_ms_init(const MsParams &p, const int32_t *sources_dev, hipStream_t s);
+hipError_t launch_ms_level(const MsParams &p, uint32_t k, uint32_t grid, hipStream_t s);
+hipError_t launch_ms_parent(const MsParams &p, uint32_t grid, hipStream_t s);
+
+hipError_t launch_mlp_forward(const float *w, const float *x, float *y, int32_t rows, hipStream_t s);
+hipError_t launch_mlp_train_step(float *w, const float *x, const float *t, const float *mask,
+                                 int32_t rows, float lr, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_grad(const float *w, const float *x, const float *t, const float *mask,
+                           int32_t rows, float *grad, float *loss, hipStream_t s);
+
+}  // namespace bfsi

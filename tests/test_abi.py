@@ -1,0 +1,98 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/bfs.h declares, and rejects malformed input before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfs.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(bfs_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1906_03113_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ("bfs_graph_create", "bfs_graph_destroy", "bfs_graph_info", "bfs_workspace_size",
+                 "bfs_run", "bfs_run_batch", "bfs_status_string", "bfs_last_error_detail"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    for s in range(6):
+        assert L.bfs_status_string(s)
+    assert L.bfs_status_string(99) == b"unknown status"
+
+
+def _create(L, n, ptr, idx, in_ptr=None, in_idx=None, flags=0):
+    vp = lambda a: None if a is None else np.ascontiguousarray(a, np.int32).ctypes.data_as(ctypes.c_void_p)
+    keep = [np.ascontiguousarray(a, np.int32) for a in (ptr, idx) if a is not None]
+    h = ctypes.c_void_p()
+    rc = L.bfs_graph_create(n, vp(ptr), vp(idx), vp(in_ptr), vp(in_idx), flags, None, ctypes.byref(h))
+    del keep
+    return rc, h
+
+
+def test_validation_errors_without_gpu(L):
+    from paper_1906_03113_amd import _lib as B
+    ok_ptr = np.array([0, 1, 2], np.int32)
+    ok_idx = np.array([1, 0], np.int32)
+    cases = [
+        (0, ok_ptr, ok_idx, None, None, 0, B.BFS_EINVAL, "n = 0"),
+        (-3, ok_ptr, ok_idx, None, None, 0, B.BFS_EINVAL, "n < 0"),
+        (2, None, ok_idx, None, None, 0, B.BFS_EINVAL, "NULL ptr"),
+        (2, np.array([1, 1, 2], np.int32), ok_idx, None, None, 0, B.BFS_ECSR, "ptr[0]"),
+        (2, np.array([0, 2, 1], np.int32), ok_idx, None, None, 0, B.BFS_ECSR, "decreasing"),
+        (2, ok_ptr, np.array([1, 2], np.int32), None, None, 0, B.BFS_ECSR, "idx >= n"),
+        (2, ok_ptr, np.array([-1, 0], np.int32), None, None, 0, B.BFS_ECSR, "idx < 0"),
+        (2, ok_ptr, ok_idx, ok_ptr, None, B.BFS_DIRECTED, B.BFS_EINVAL, "half a CSC"),
+        (2, ok_ptr, ok_idx, ok_ptr, ok_idx, 0, B.BFS_EINVAL, "CSC without DIRECTED"),
+        (2, ok_ptr, ok_idx, None, None, 1 << 9, B.BFS_EINVAL, "unknown flag"),
+        (2, ok_ptr, ok_idx, np.array([0, 1, 3], np.int32), np.array([1, 0, 0], np.int32),
+         B.BFS_DIRECTED, B.BFS_ECSR, "CSC size differs"),
+        (2, ok_ptr, ok_idx, np.array([0, 0, 2], np.int32), np.array([0, 1], np.int32),
+         B.BFS_DIRECTED | B.BFS_VALIDATE_TRANSPOSE, B.BFS_ECSR, "CSC not transpose"),
+    ]
+    for n, p, i, ip, ii, fl, want, what in cases:
+        rc, h = _create(L, n, p, i, ip, ii, fl)
+        assert rc == want, (what, rc, L.bfs_last_error_detail())
+        assert h.value is None
+        assert L.bfs_last_error_detail()
+
+
+def test_null_handles(L):
+    assert L.bfs_workspace_size(None, 1, 0) == 0
+    assert L.bfs_graph_destroy(None) == 0
+    assert L.bfs_graph_info(None, None, None, None, None) == 1
+    assert L.bfs_run(None, 0, None, None, None, None, 0, None) == 1
+    assert L.bfs_run_batch(0, None, None, None, None, None, None, 0, None) == 1
+    assert L.bfs_run_roots(None, 1, None, None, None, None, None, 0, None) == 1
+    assert L.bfs_roots_workspace_size(None, 3) == 0
+
+
+def test_no_cpu_fallback_in_product_package():
+    """The package never imports the oracle and has no CPU search of its own."""
+    pkg = os.path.join(ROOT, "paper_1906_03113_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
