@@ -1,0 +1,193 @@
+"""Throughput of the masked SpMSpV BFS on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat22]
+
+One step = one search from each of the workload's sources (R-MAT scale 22:
+64 seeded sources of nonzero degree), the graph resident in HBM.  Prints ONE
+JSON line on stdout; progress goes to stderr.
+
+value = GTEPS = sum over the step's searches of m_c (edges of the reached
+component, each undirected edge once) / wall time of the step.
+roofline = the level kernel (k_level): algorithmic bytes per launch / mean
+launch duration, the durations from HIP events around every launch in the
+timed region.
+cpu_baseline = the CPU oracle (queue BFS + min-parent pass, one thread) timed
+on a bounded sample of the same searches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+WORKLOADS = {
+    # name: (graphgen key, number of sources, source seed, description)
+    "rmat22": ("rmat22", 64, 22, "R-MAT scale 22, edgefactor 16, A/B/C/D=.57/.19/.19/.05, "
+                                 "permuted labels, undirected, int32 CSR"),
+    "er16k": ("er16k", 1, None, "Erdos-Renyi n=16384, avg degree 8, undirected"),
+    "grid4096": ("grid4096", 16, 31, "4096x4096 grid, edges kept with p=0.9, undirected"),
+    "rmatd20": ("rmat20d", 16, 32, "R-MAT scale 20, edgefactor 16, directed (out-edges)"),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="push")
+    ap.add_argument("--loop", default="host")
+    ap.add_argument("--levels-per-sync", type=int, default=0)
+    ap.add_argument("--grid-blocks", type=int, default=0)
+    ap.add_argument("--heavy-degree", type=int, default=0)
+    ap.add_argument("--chunk-edges", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-time-kernels", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the search is single-GPU and sharding is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1906_03113_amd as P
+
+    key, nsrc, sseed, desc = WORKLOADS[args.workload]
+    t0 = time.time()
+    log(f"[bench] building graph {key} ...")
+    g = graphgen.workload(key)
+    log(f"[bench] graph n={g.n} nnz={g.nnz} directed={g.directed} ({time.time() - t0:.1f}s)")
+    sources = np.array([0], np.int32) if sseed is None else graphgen.pick_sources(g, nsrc, sseed)
+    torch.cuda.set_device(0)
+    G = P.Graph.from_graphgen(g)
+    log(f"[bench] resident on GPU: {G.device_bytes() / 1e6:.1f} MB")
+    ws = P.Workspace(G.workspace_size(1))
+    level = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    kw = dict(variant=args.variant, loop=args.loop, levels_per_sync=args.levels_per_sync,
+              grid_blocks=args.grid_blocks, heavy_degree=args.heavy_degree,
+              chunk_edges=args.chunk_edges)
+    timek = (args.loop == "host") and not args.no_time_kernels
+
+    # edge counts of each search (from the search's own output)
+    deg = np.diff(g.ptr.astype(np.int64))
+    m_c, n_c, nnz_c = [], [], []
+    for s in sources:
+        P.bfs(G, int(s), level=level, parent=parent, workspace=ws, **kw)
+        lv = level.cpu().numpy()
+        reached = lv >= 0
+        nz = int(deg[reached].sum())
+        nnz_c.append(nz)
+        n_c.append(int(reached.sum()))
+        m_c.append(nz if g.directed else nz // 2)
+    total_m = float(sum(m_c))
+    log(f"[bench] {len(sources)} sources: mean n_c={np.mean(n_c):.0f} mean m_c={np.mean(m_c):.0f}")
+
+    def step(info_acc=None):
+        for s in sources:
+            info = {} if info_acc is not None else None
+            P.bfs(G, int(s), level=level, parent=parent, workspace=ws, info=info,
+                  time_kernels=timek, **kw)
+            if info_acc is not None:
+                info_acc.append(info)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    infos = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(infos)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    dt = (t_end - t_start) / args.steps
+    gteps = total_m / dt / 1e9
+    log(f"[bench] {args.steps} steps: {dt * 1e3:.3f} ms/step, {gteps:.2f} GTEPS")
+
+    roofline = None
+    if timek and infos:
+        launches = sum(i["launches"] for i in infos)
+        kern_us = sum(i["kernel_us"] for i in infos)
+        # algorithmic bytes of the level kernel per search (the method's own traffic):
+        # 4 B per entry of every reached column, 8 B for its two row pointers,
+        # 8 B to write and read it in the frontier list, 8 B for its level and parent
+        b_search = [4 * nz + 24 * nc for nz, nc in zip(nnz_c, n_c)]
+        bytes_total = float(sum(b_search)) * args.steps
+        avg_bytes = bytes_total / launches
+        avg_us = kern_us / launches
+        ach = avg_bytes / (avg_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_level", "launches_per_search": round(launches / (len(sources) * args.steps), 2),
+                    "mean_launch_us": round(avg_us, 3),
+                    "algorithmic_bytes_per_launch": round(avg_bytes),
+                    "kernel_us_per_search": round(kern_us / (len(sources) * args.steps), 2)}
+        log(f"[bench] k_level: {launches} launches, mean {avg_us:.2f} us, {ach:.1f} GB/s algorithmic "
+            f"({ach / HBM_PEAK_GBS * 100:.1f}% of 8 TB/s)")
+
+    # per-level view of the first search (stderr only)
+    info = {}
+    P.bfs(G, int(sources[0]), level=level, parent=parent, workspace=ws, info=info, trace=True,
+          time_kernels=timek, **kw)
+    for r in info.get("trace", []):
+        log(f"[bench]   level {r['level']:5d} {r['variant']:>7s} |F|={r['frontier']:9d} "
+            f"sumdeg(F)={r['frontier_edges']:11d} |U|={r['unvisited']:9d} {r['time_us']:9.1f} us")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ip, ii = g.csc()
+        t_first = oracle.time_queue_bfs(g.n, g.ptr, g.idx, sources[:1], ip, ii)
+        count = max(1, min(len(sources), int(args.cpu_seconds / max(t_first, 1e-6))))
+        t_cpu = oracle.time_queue_bfs(g.n, g.ptr, g.idx, sources[:count], ip, ii) if count > 1 else t_first
+        cpu_gteps = float(sum(m_c[:count])) / t_cpu / 1e9
+        cpu = {"value": round(cpu_gteps, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"first {count} of the {len(sources)} sources of the step "
+                         f"({t_cpu:.2f} s, single thread, queue BFS + min-parent pass)",
+               "gpu_over_cpu": round(gteps / cpu_gteps, 1)}
+        log(f"[bench] cpu oracle: {count} searches in {t_cpu:.2f}s = {cpu_gteps:.4f} GTEPS")
+
+    out = {
+        "metric": "GTEPS, R-MAT s22 plain masked push (64 sources, one search per launch sequence)",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": desc, "n": g.n, "nnz": g.nnz,
+                   "sources": int(len(sources)), "searches_per_step": int(len(sources)),
+                   "edges_per_step_m_c": int(total_m), "variant": args.variant, "loop": args.loop},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,7 +87,8 @@ typedef struct bfs_level_record {
 typedef struct bfs_run_options {
     uint32_t variant;          /* BFS_VARIANT_*                                  (default PUSH)  */
     uint32_t loop_mode;        /* BFS_LOOP_*                                     (default HOST)  */
-    uint32_t levels_per_sync;  /* host loop: levels launched between size reads (0 = 4)        */
+    uint32_t levels_per_sync;  /* host loop / graph loop: levels launched between two reads of
+                                  the frontier size (0 = 4)                                    */
     uint32_t grid_blocks;      /* workgroups per level launch (0 = 8 per compute unit)          */
     uint32_t heavy_degree;     /* out-degree from which a column is split into chunks (0 = 512) */
     uint32_t chunk_edges;      /* entries per chunk of a split column (0 = 1024)                */
@@ -95,9 +96,12 @@ typedef struct bfs_run_options {
                                   push on every level)                                          */
     bfs_level_record *trace;   /* host: per-level records, or NULL                              */
     uint32_t trace_capacity;   /* records available in `trace`                                  */
+    uint32_t time_kernels;     /* host loop: 1 = bracket every level launch with HIP events     */
     uint32_t trace_count;      /* out: records written                                          */
     uint32_t levels;           /* out: number of levels (largest level + 1)                    */
-    uint32_t reserved;
+    uint32_t launches;         /* out (time_kernels): level-kernel launches issued, including
+                                  launches after the last level, which return at once          */
+    float kernel_us;           /* out (time_kernels): summed device time of those launches      */
 } bfs_run_options;
 
 /*

@@ -122,8 +122,10 @@ class Workspace:
 
 
 def make_options(variant="push", loop="host", levels_per_sync=0, grid_blocks=0,
-                 heavy_degree=0, chunk_edges=0, selector=None, trace_capacity=0) -> Tuple[RunOptions, Optional[ctypes.Array]]:
+                 heavy_degree=0, chunk_edges=0, selector=None, trace_capacity=0,
+                 time_kernels=False) -> Tuple[RunOptions, Optional[ctypes.Array]]:
     o = RunOptions()
+    o.time_kernels = 1 if time_kernels else 0
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.loop_mode = LOOPS[loop] if isinstance(loop, str) else int(loop)
     o.levels_per_sync = int(levels_per_sync)
@@ -169,6 +171,8 @@ def bfs(g: Graph, source: int, variant="push", loop="host", level=None, parent=N
                                   _stream_handle(stream)))
     if info is not None:
         info["levels"] = o.levels
+        info["launches"] = o.launches
+        info["kernel_us"] = o.kernel_us
         if trace:
             info["trace"] = trace_dicts(o, recs)
     return level, parent

@@ -28,8 +28,9 @@ class RunOptions(ctypes.Structure):
                 ("heavy_degree", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
                 ("selector", ctypes.c_void_p),
                 ("trace", ctypes.POINTER(LevelRecord)), ("trace_capacity", ctypes.c_uint32),
-                ("trace_count", ctypes.c_uint32), ("levels", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("time_kernels", ctypes.c_uint32), ("trace_count", ctypes.c_uint32),
+                ("levels", ctypes.c_uint32), ("launches", ctypes.c_uint32),
+                ("kernel_us", ctypes.c_float)]
 
 
 class BfsError(RuntimeError):

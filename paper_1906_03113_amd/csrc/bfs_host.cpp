@@ -23,6 +23,7 @@ struct GraphExecCache {
     const void *parent = nullptr;
     uint32_t policy = 0, grid = 0, heavy = 0, chunk = 0, levels = 0, fb = 0, stats = 0;
     const float *sel = nullptr;
+    const void *trace = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -37,6 +38,7 @@ struct bfs_graph {
     size_t bytes = 0;
     std::mutex mu;
     GraphExecCache gcache;
+    std::vector<hipEvent_t> events;   // pool for per-launch timing
 };
 
 namespace {
@@ -106,6 +108,7 @@ bfs_status upload(T **dst, const T *src, size_t count, size_t &bytes) {
 
 void free_graph(bfs_graph *g) {
     if (!g) return;
+    for (hipEvent_t e : g->events) hipEventDestroy(e);
     if (g->gcache.exec) hipGraphExecDestroy(g->gcache.exec);
     if (g->gcache.graph) hipGraphDestroy(g->gcache.graph);
     if (g->in_ptr && g->in_ptr != g->out_ptr) hipFree(g->in_ptr);
@@ -118,6 +121,7 @@ void free_graph(bfs_graph *g) {
 }  // namespace
 
 namespace bfsi {
+constexpr uint32_t kChunkFloor = 64;
 WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor) {
     WsLayout L{};
     const size_t words = ((size_t)n + 31) / 32;
@@ -128,13 +132,20 @@ WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor) {
     L.vb1 = take(words * 4);
     L.fb0 = take(words * 4);
     L.fb1 = take(words * 4);
-    L.q0 = take((size_t)n * 4);
-    L.q1 = take((size_t)n * 4);
+    L.fb2 = take(words * 4);
+    L.q0 = take((size_t)n * sizeof(QEnt));
+    L.q1 = take((size_t)n * sizeof(QEnt));
     L.u0 = take((size_t)n * 4);
     L.u1 = take((size_t)n * 4);
+    // long columns in one frontier: at most nnz / heavy_min of them
     size_t hcap = (size_t)nnz / heavy_min_floor + 1;
     if (hcap > (size_t)n) hcap = (size_t)n;
-    L.heavy = take(hcap * sizeof(HeavyItem));
+    L.h0 = take(hcap * sizeof(HeavyItem));
+    L.h1 = take(hcap * sizeof(HeavyItem));
+    // chunks in one frontier: at most nnz / chunk_floor + (number of long columns)
+    const size_t ccap = (size_t)nnz / kChunkFloor + hcap + 1;
+    L.c0 = take(ccap * 4);
+    L.c1 = take(ccap * 4);
     L.trace = take((size_t)kTraceCap * sizeof(DevLevelRec));
     L.total = off;
     return L;
@@ -171,15 +182,19 @@ bfs_status make_params(bfs_graph *g, int32_t *level, int32_t *parent, const RunC
     P.vb[1] = (uint32_t *)(b + L.vb1);
     P.fb[0] = (uint32_t *)(b + L.fb0);
     P.fb[1] = (uint32_t *)(b + L.fb1);
-    P.q[0] = (int32_t *)(b + L.q0);
-    P.q[1] = (int32_t *)(b + L.q1);
+    P.fb[2] = (uint32_t *)(b + L.fb2);
+    P.q[0] = (QEnt *)(b + L.q0);
+    P.q[1] = (QEnt *)(b + L.q1);
     P.ul[0] = (int32_t *)(b + L.u0);
     P.ul[1] = (int32_t *)(b + L.u1);
-    P.heavy = (HeavyItem *)(b + L.heavy);
+    P.hl[0] = (HeavyItem *)(b + L.h0);
+    P.hl[1] = (HeavyItem *)(b + L.h1);
+    P.cmap[0] = (uint32_t *)(b + L.c0);
+    P.cmap[1] = (uint32_t *)(b + L.c1);
     P.st = (BfsState *)(b + L.state);
     P.trace = trace ? (DevLevelRec *)(b + L.trace) : nullptr;
     P.mlp = c.sel;
-    P.maintain_fb = (c.policy == kBitmap || c.policy == kLearned) ? 1u : 0u;
+    P.maintain_fb = (c.policy == kBitmap || c.policy == kLearned || c.policy == kHeuristic) ? 1u : 0u;
     P.stats = (c.policy == kLearned || c.policy == kHeuristic || trace) ? 1u : 0u;
     return BFS_OK;
 }
@@ -195,7 +210,8 @@ bfs_status resolve_cfg(bfs_graph *g, const bfs_run_options *opt, RunCfg &c) {
     if (c.policy > kHeuristic) return fail(BFS_EINVAL, "unknown variant %u", c.policy);
     if (c.loop > BFS_LOOP_PERSISTENT) return fail(BFS_EINVAL, "unknown loop mode %u", c.loop);
     if (c.heavy < kHeavyFloor) return fail(BFS_EINVAL, "heavy_degree %u below %u", c.heavy, kHeavyFloor);
-    if (c.chunk < 64 || c.chunk > (1u << 20)) return fail(BFS_EINVAL, "chunk_edges %u outside [64, 2^20]", c.chunk);
+    if (c.chunk < kChunkFloor || c.chunk > (1u << 20))
+        return fail(BFS_EINVAL, "chunk_edges %u outside [%u, 2^20]", c.chunk, kChunkFloor);
     if (c.grid == 0 || c.grid > 65535) return fail(BFS_EINVAL, "grid_blocks %u outside [1, 65535]", c.grid);
     if (c.per_sync > 4096) return fail(BFS_EINVAL, "levels_per_sync %u above 4096", c.per_sync);
     return BFS_OK;
@@ -211,7 +227,8 @@ struct PinnedState {
 bfs_status read_state(const LevelParams &P, BfsState *h, hipStream_t s, bool &done) {
     HIP_TRY(hipMemcpyAsync(h, P.st, sizeof(BfsState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    done = (h->nf[h->level & 3] == 0);
+    const uint32_t slot = h->level & 3;
+    done = (h->nf[slot] == 0 && (uint32_t)h->heavy[slot] == 0);
     return BFS_OK;
 }
 
@@ -221,7 +238,6 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
     if (!ps.h) return fail(BFS_ENOMEM, "hipHostMalloc of the state readback failed");
     const uint64_t max_levels = (uint64_t)g->n + 2;
     bool done = false;
-    bool timing = opt && opt->trace && c.loop == BFS_LOOP_HOST;
     std::vector<float> times;
     if (c.loop == BFS_LOOP_PERSISTENT) {
         uint32_t maxg = persistent_max_grid(g->device);
@@ -238,7 +254,8 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
         bool hit = gc.valid && gc.ws == (const void *)P.st && gc.level == P.level &&
                    gc.parent == P.parent && gc.policy == c.policy && gc.grid == c.grid &&
                    gc.heavy == c.heavy && gc.chunk == c.chunk && gc.levels == L &&
-                   gc.sel == c.sel && gc.fb == P.maintain_fb && gc.stats == P.stats;
+                   gc.sel == c.sel && gc.fb == P.maintain_fb && gc.stats == P.stats &&
+                   gc.trace == (const void *)P.trace;
         if (!hit) {
             if (gc.exec) { hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
             if (gc.graph) { hipGraphDestroy(gc.graph); gc.graph = nullptr; }
@@ -248,7 +265,7 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             for (uint32_t l = 0; l < L && e == hipSuccess; ++l) {
                 e = launch_level(P, c.grid, cap);
-                if (e == hipSuccess) e = launch_tail(P, c.grid, cap);
+                if (e == hipSuccess) e = launch_finish(P, cap);
             }
             hipGraph_t graph = nullptr;
             hipError_t e2 = hipStreamEndCapture(cap, &graph);
@@ -265,7 +282,8 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
             gc.exec = exec;
             gc.ws = P.st; gc.level = P.level; gc.parent = P.parent; gc.policy = c.policy;
             gc.grid = c.grid; gc.heavy = c.heavy; gc.chunk = c.chunk; gc.levels = L;
-            gc.sel = c.sel; gc.fb = P.maintain_fb; gc.stats = P.stats; gc.valid = true;
+            gc.sel = c.sel; gc.fb = P.maintain_fb; gc.stats = P.stats;
+            gc.trace = (const void *)P.trace; gc.valid = true;
         }
         for (uint64_t issued = 0; !done; issued += L) {
             if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
@@ -274,31 +292,46 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
             if (st != BFS_OK) return st;
         }
     } else {
-        const uint32_t L = timing ? 1u : c.per_sync;
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (timing) {
-            HIP_TRY(hipEventCreate(&ev0));
-            HIP_TRY(hipEventCreate(&ev1));
-        }
+        const bool tk = opt && opt->time_kernels;
+        const uint32_t L = c.per_sync;
+        uint32_t launched = 0;
+        auto ev = [&](uint32_t i, hipEvent_t &out) -> bfs_status {
+            while (g->events.size() <= i) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                g->events.push_back(e);
+            }
+            out = g->events[i];
+            return BFS_OK;
+        };
         for (uint64_t issued = 0; !done; issued += L) {
             if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
-            if (timing) HIP_TRY(hipEventRecord(ev0, s));
             for (uint32_t l = 0; l < L; ++l) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (tk) {
+                    bfs_status st = ev(2 * launched, e0);
+                    if (st == BFS_OK) st = ev(2 * launched + 1, e1);
+                    if (st != BFS_OK) return st;
+                    HIP_TRY(hipEventRecord(e0, s));
+                }
                 HIP_TRY(launch_level(P, c.grid, s));
-                HIP_TRY(launch_tail(P, c.grid, s));
+                if (tk) HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(launch_finish(P, s));
+                ++launched;
             }
-            if (timing) HIP_TRY(hipEventRecord(ev1, s));
             bfs_status st = read_state(P, ps.h, s, done);
             if (st != BFS_OK) return st;
-            if (timing) {
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
-                if (!done || times.size() < ps.h->level) times.push_back(ms * 1000.f);
-            }
         }
-        if (timing) {
-            hipEventDestroy(ev0);
-            hipEventDestroy(ev1);
+        if (tk) {
+            float total = 0.f;
+            for (uint32_t i = 0; i < launched; ++i) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, g->events[2 * i], g->events[2 * i + 1]));
+                total += ms * 1000.f;
+                times.push_back(ms * 1000.f);
+            }
+            opt->launches = launched;
+            opt->kernel_us = total;
         }
     }
     levels_out = ps.h->level;

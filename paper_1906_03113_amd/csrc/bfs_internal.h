@@ -10,6 +10,7 @@ namespace bfsi {
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64s)
 constexpr uint32_t kAllVertices = 0xFFFFFFFFu;
 constexpr int kRing = 4;               // per-level counter slots (level k uses k & 3)
+constexpr int kBarGroups = 16;         // arrival groups of the persistent kernel's grid barrier
 constexpr int kMlpIn = 12, kMlpH = 32, kMlpOut = 3;
 constexpr int kMlpParams = kMlpIn * kMlpH + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH * kMlpOut + kMlpOut;
 // feature normalisation constants live after the weights: mean[12], inv_std[12]
@@ -20,7 +21,7 @@ enum Variant : uint32_t { kPush = 0, kPull = 1, kBitmap = 2, kLearned = 3, kHeur
 // Device-resident search state (first bytes of every workspace).
 struct alignas(256) BfsState {
     uint32_t level;          // current level k
-    uint32_t done;           // blocks of the tail kernel that have finished
+    uint32_t done;           // blocks of the level kernel that have finished
     uint32_t variant;        // variant run at level k
     uint32_t u_buf;          // which unvisited-list buffer is current
     uint32_t u_len;          // its length; kAllVertices = the implicit list 0..n-1
@@ -28,13 +29,17 @@ struct alignas(256) BfsState {
     uint32_t visited_cnt;    // |B_k|
     uint32_t barrier;        // grid barrier counter (persistent mode)
     unsigned long long visited_deg;   // sum of out-degrees over B_k
-    uint32_t nf[kRing];                  // |F| per ring slot
-    unsigned long long heavy[kRing];     // packed: (#split columns) | (#chunks << 32)
+    uint32_t nf[kRing];                  // |F| (short columns, in the list) per ring slot
+    unsigned long long heavy[kRing];     // long columns: (#columns) | (#chunks << 32)
     unsigned long long sdf[kRing];       // sum of out-degrees over F per ring slot
     uint32_t barrier_gen;
     uint32_t pad[7];
+    // two-level grid barrier (persistent mode): one arrival counter per group
+    // of blocks, each on its own 64-byte line, then one for the groups
+    uint32_t bar_group[kBarGroups * 16];
+    uint32_t bar_top;
+    uint32_t pad2[15];
 };
-
 // Per-level record kept on the device (a trace ring of kTraceCap entries).
 struct DevLevelRec {
     uint32_t level, variant, nf, nu;
@@ -45,6 +50,12 @@ constexpr uint32_t kTraceCap = 1024;
 struct HeavyItem {
     int32_t v;
     uint32_t chunk_base;
+};
+
+// A frontier-list entry: the vertex and its column bounds, written by the
+// lane that reached it, so the next level reads them sequentially.
+struct alignas(16) QEnt {
+    int32_t v, r0, r1, pad;
 };
 
 struct LevelParams {
@@ -58,10 +69,11 @@ struct LevelParams {
     int32_t *level;
     uint32_t *parent;        // uint32 view of the int32 parent array (-1 = 0xFFFFFFFF)
     uint32_t *vb[2];         // visited bitmaps, ping-pong: vb[k&1] = B_k
-    uint32_t *fb[2];         // frontier bitmaps (kept only when maintain_fb)
-    int32_t *q[2];           // frontier lists, ping-pong
+    uint32_t *fb[3];         // frontier bitmaps, rotating: fb[k%3] = F_k (kept only when maintain_fb)
+    QEnt *q[2];              // frontier lists of short columns, ping-pong
     int32_t *ul[2];          // unvisited lists, ping-pong
-    HeavyItem *heavy;        // split-column queue for the current level
+    HeavyItem *hl[2];        // frontier lists of long (chunked) columns, ping-pong
+    uint32_t *cmap[2];       // chunk id -> position of its column in hl, ping-pong
     BfsState *st;
     DevLevelRec *trace;      // kTraceCap records, or nullptr
     const float *mlp;        // selector weights (kMlpTotal floats) or nullptr
@@ -70,7 +82,7 @@ struct LevelParams {
 };
 
 struct WsLayout {
-    size_t state, vb0, vb1, fb0, fb1, q0, q1, u0, u1, heavy, trace, total;
+    size_t state, vb0, vb1, fb0, fb1, fb2, q0, q1, u0, u1, h0, h1, c0, c1, trace, total;
 };
 WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor);
 
@@ -94,7 +106,7 @@ struct MsParams {
 hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *roots_dev,
                        int32_t single_root, hipStream_t s);
 hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s);
-hipError_t launch_tail(const LevelParams &p, uint32_t grid, hipStream_t s);
+hipError_t launch_finish(const LevelParams &p, hipStream_t s);
 hipError_t launch_persistent(const LevelParams &p, uint32_t grid, hipStream_t s);
 uint32_t persistent_max_grid(int device);
 

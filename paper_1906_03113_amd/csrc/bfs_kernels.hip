@@ -70,47 +70,68 @@ __device__ __forceinline__ unsigned long long ld_agent64(const unsigned long lon
 // same device counters)
 // ---------------------------------------------------------------------------
 
-__device__ float mlp_logtime(const float *w, const float f[kMlpIn], int out_unit) {
-    // 12 -> 32 (ReLU) -> 32 (ReLU) -> 3, row-major weights [out][in]
+// Feature i of a level (lane i of the calling wave computes feature i; the
+// selector's training code computes the same twelve numbers in float64):
+// log sizes of the frontier and of the unvisited remainder, in vertices and in
+// column entries, the level, the mean degree, and their log-ratios.
+__device__ __forceinline__ float level_feature(uint32_t i, float nf, float sdf, float nu,
+                                               float sdu, float k, float n, float nnz) {
+    switch (i) {
+        case 0: return logf(1.f + nf);
+        case 1: return logf(1.f + sdf);
+        case 2: return logf(1.f + nu);
+        case 3: return logf(1.f + sdu);
+        case 4: return k;
+        case 5: return nnz / n;
+        case 6: return logf((nf + 1.f) / n);
+        case 7: return logf((sdf + 1.f) / (nnz + 1.f));
+        case 8: return logf((nu + 1.f) / n);
+        case 9: return logf((sdu + 1.f) / (nnz + 1.f));
+        case 10: return logf((sdf + 1.f) / (sdu + 1.f));
+        case 11: return logf((nf + 1.f) / (nu + 1.f));
+        default: return 0.f;
+    }
+}
+
+// The selector network 12 -> 32 (ReLU) -> 32 (ReLU) -> 3, row-major weights
+// [out][in] followed by the biases, then the feature mean and inverse std.
+// Evaluated by one wave: lane o < 32 holds hidden unit o, inputs are passed
+// between lanes with shuffles (no arrays, so nothing spills).  Returns, in
+// every lane, the argmin of the three predicted log-times, or -1 when an
+// output is not finite.
+__device__ __forceinline__ int mlp_argmin(const float *w, float feat) {
     const float *W1 = w, *b1 = W1 + kMlpIn * kMlpH, *W2 = b1 + kMlpH,
                 *b2 = W2 + kMlpH * kMlpH, *W3 = b2 + kMlpH, *b3 = W3 + kMlpH * kMlpOut;
-    float h1[kMlpH];
-    for (int o = 0; o < kMlpH; ++o) {
-        float a = b1[o];
-        for (int i = 0; i < kMlpIn; ++i) a = fmaf(W1[o * kMlpIn + i], f[i], a);
-        h1[o] = a > 0.f ? a : 0.f;
+    const float *mean = w + kMlpParams, *istd = mean + kMlpIn;
+    const uint32_t lane = lane_id();
+    const uint32_t li = lane < (uint32_t)kMlpIn ? lane : 0u;
+    const float x = (lane < (uint32_t)kMlpIn) ? (feat - mean[li]) * istd[li] : 0.f;
+    const uint32_t o = lane & (kMlpH - 1);
+    float a = b1[o];
+    for (int i = 0; i < kMlpIn; ++i) a = fmaf(W1[o * kMlpIn + i], __shfl(x, i, 64), a);
+    const float h1 = a > 0.f ? a : 0.f;
+    float c = b2[o];
+    for (int i = 0; i < kMlpH; ++i) c = fmaf(W2[o * kMlpH + i], __shfl(h1, i, 64), c);
+    const float h2 = (c > 0.f ? c : 0.f) * (lane < (uint32_t)kMlpH ? 1.f : 0.f);
+    int best = 0;
+    float bestv = 0.f;
+    bool ok = true;
+    for (int u = 0; u < kMlpOut; ++u) {
+        float y = W3[u * kMlpH + o] * h2;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) y += __shfl_xor(y, d, 64);
+        y += b3[u];
+        if (!(y == y) || y > 1e30f || y < -1e30f) ok = false;
+        if (u == 0 || y < bestv) { bestv = y; best = u; }
     }
-    float y = b3[out_unit];
-    for (int o = 0; o < kMlpH; ++o) {
-        float a = b2[o];
-        for (int i = 0; i < kMlpH; ++i) a = fmaf(W2[o * kMlpH + i], h1[i], a);
-        a = a > 0.f ? a : 0.f;
-        y = fmaf(W3[out_unit * kMlpH + o], a, y);
-    }
-    return y;
+    return ok ? best : -1;
 }
 
-__device__ void level_features(float f[kMlpIn], float nf, float sdf, float nu, float sdu,
-                               float k, float n, float nnz) {
-    f[0] = logf(1.f + nf);
-    f[1] = logf(1.f + sdf);
-    f[2] = logf(1.f + nu);
-    f[3] = logf(1.f + sdu);
-    f[4] = k;
-    f[5] = nnz / n;
-    f[6] = logf((nf + 1.f) / n);
-    f[7] = logf((sdf + 1.f) / (nnz + 1.f));
-    f[8] = logf((nu + 1.f) / n);
-    f[9] = logf((sdu + 1.f) / (nnz + 1.f));
-    f[10] = logf((sdf + 1.f) / (sdu + 1.f));
-    f[11] = logf((nf + 1.f) / (nu + 1.f));
-}
-
-// Called by every thread; thread 0 computes, the block shares through LDS.
-__device__ uint32_t choose_variant(const LevelParams &P, uint32_t k, uint32_t nf) {
+// Called by every thread; wave 0 decides, the block shares through LDS.
+__device__ __forceinline__ uint32_t choose_variant(const LevelParams &P, uint32_t k, uint32_t nf) {
     if (P.policy == kPush || P.policy == kPull || P.policy == kBitmap) return P.policy;
     __shared__ uint32_t s_var;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
         const BfsState *st = P.st;
         const uint32_t cs = k & 3;
         const float fnf = (float)nf;
@@ -119,43 +140,171 @@ __device__ uint32_t choose_variant(const LevelParams &P, uint32_t k, uint32_t nf
         const float fsdu = (float)((unsigned long long)P.nnz - st->visited_deg);
         uint32_t v = kPush;
         if (P.policy == kHeuristic) {
-            // pull when the frontier's edges outweigh a fraction of the
-            // unvisited edges and the frontier is not tiny
-            if (fsdf * 14.f > fsdu && fnf * 24.f > (float)P.n) v = kPull;
+            // pull when the frontier's edges outweigh 1/14 of the unvisited edges
+            if (fsdf * 14.f > fsdu) v = kPull;
         } else if (P.mlp != nullptr) {
-            float f[kMlpIn];
-            level_features(f, fnf, fsdf, fnu, fsdu, (float)k, (float)P.n, (float)P.nnz);
-            const float *mean = P.mlp + kMlpParams, *istd = mean + kMlpIn;
-            for (int i = 0; i < kMlpIn; ++i) f[i] = (f[i] - mean[i]) * istd[i];
-            float best = 0.f;
-            bool ok = true;
-            for (int o = 0; o < kMlpOut; ++o) {
-                float y = mlp_logtime(P.mlp, f, o);
-                if (!(y == y) || y > 1e30f || y < -1e30f) ok = false;   // NaN / inf -> fallback
-                if (o == 0 || y < best) { best = y; v = (uint32_t)o; }
-            }
-            if (!ok) v = kPush;
+            const float f = level_feature(lane_id(), fnf, fsdf, fnu, fsdu, (float)k, (float)P.n,
+                                          (float)P.nnz);
+            const int b = mlp_argmin(P.mlp, f);
+            v = (b < 0) ? (uint32_t)kPush : (uint32_t)b;
             if (v == kBitmap && !P.maintain_fb) v = kPush;
         }
-        s_var = v;
+        if (threadIdx.x == 0) s_var = v;
     }
     __syncthreads();
     return s_var;
 }
 
 // ---------------------------------------------------------------------------
+// per-block staging of the level's output
+// ---------------------------------------------------------------------------
+//
+// Newly reached vertices are first collected in LDS and written out in
+// batches: one global atomicAdd per batch reserves room in the next frontier
+// list, instead of one per wave (a single counter hit by every wave of the grid
+// serialises at the memory-side atomic unit).
+
+// Each round adds at most one entry per thread to each buffer, so a buffer
+// flushed once it holds more than (cap - kBlock) entries never overflows.
+constexpr uint32_t kIlp = 4;           // column entries per lane per round
+constexpr uint32_t kOutCap = 512;      // short-column entries staged per block
+constexpr uint32_t kOutFlush = kOutCap - kBlock;
+constexpr uint32_t kLongCap = 320;     // long-column entries staged per block
+constexpr uint32_t kLongFlush = kLongCap - kBlock;
+constexpr uint32_t kUCap = 384;        // unvisited-list survivors staged per block (pull)
+constexpr uint32_t kUFlush = kUCap - kBlock;
+
+struct OutLds {
+    QEnt q[kOutCap];
+    int32_t lv[kLongCap];
+    uint32_t lch[kLongCap];
+    int32_t u[kUCap];
+    uint32_t qn, ln, un;
+    uint32_t qbase, lpos, lcb, ltot, ubase;
+    unsigned long long sdf;
+};
+
+struct LevelPtrs {
+    uint32_t k, cs, ns;
+    const uint32_t *vb_cur;
+    uint32_t *vb_nxt;
+    const uint32_t *fb_cur;
+    uint32_t *fb_nxt, *fb_old;
+    const QEnt *q_cur;
+    QEnt *q_nxt;
+    const HeavyItem *h_cur;
+    HeavyItem *h_nxt;
+    const uint32_t *c_cur;
+    uint32_t *c_nxt;
+    int32_t *u_nxt;
+};
+
+__device__ __forceinline__ LevelPtrs level_ptrs(const LevelParams &P, uint32_t k) {
+    LevelPtrs L;
+    L.k = k;
+    L.cs = k & 3;
+    L.ns = (k + 1) & 3;
+    // selects instead of indexing the parameter arrays with a runtime index
+    // (which would force the kernel-argument struct into scratch memory)
+    const bool odd = k & 1;
+    const uint32_t r3 = k % 3;
+    L.vb_cur = odd ? P.vb[1] : P.vb[0];
+    L.vb_nxt = odd ? P.vb[0] : P.vb[1];
+    L.fb_cur = r3 == 0 ? P.fb[0] : (r3 == 1 ? P.fb[1] : P.fb[2]);
+    L.fb_nxt = r3 == 0 ? P.fb[1] : (r3 == 1 ? P.fb[2] : P.fb[0]);
+    L.fb_old = r3 == 0 ? P.fb[2] : (r3 == 1 ? P.fb[0] : P.fb[1]);
+    L.q_cur = odd ? P.q[1] : P.q[0];
+    L.q_nxt = odd ? P.q[0] : P.q[1];
+    L.h_cur = odd ? P.hl[1] : P.hl[0];
+    L.h_nxt = odd ? P.hl[0] : P.hl[1];
+    L.c_cur = odd ? P.cmap[1] : P.cmap[0];
+    L.c_nxt = odd ? P.cmap[0] : P.cmap[1];
+    L.u_nxt = nullptr;
+    return L;
+}
+
+__device__ __forceinline__ void out_init(OutLds &O) {
+    if (threadIdx.x == 0) {
+        O.qn = 0;
+        O.ln = 0;
+        O.un = 0;
+        O.sdf = 0ull;
+    }
+    __syncthreads();
+}
+
+// Write the staged entries out.  Called by every thread of the block; `final`
+// also folds the block's degree sum into the level's counter.
+__device__ __forceinline__ void out_flush(const LevelParams &P, const LevelPtrs &L, OutLds &O, bool final) {
+    __syncthreads();
+    const uint32_t tid = threadIdx.x;
+    const uint32_t qn = O.qn, ln = O.ln, un = O.un;
+    const bool need = final || qn > kOutFlush || ln > kLongFlush || un > kUFlush;
+    if (!need) return;                                   // uniform: everyone read the same counters
+    if (ln) {                                            // chunk offsets within the batch
+        const uint32_t a0 = (2 * tid < ln) ? O.lch[2 * tid] : 0u;
+        const uint32_t a1 = (2 * tid + 1 < ln) ? O.lch[2 * tid + 1] : 0u;
+        const uint32_t lane = lane_id(), wave = tid >> 6;
+        const uint32_t incl = wave_incl_scan(a0 + a1);
+        __shared__ uint32_t s_w[kBlock / 64];
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (uint32_t w = 0; w < kBlock / 64; ++w) {
+            off += (w < wave) ? s_w[w] : 0u;
+            tot += s_w[w];
+        }
+        const uint32_t ex = off + incl - (a0 + a1);
+        if (2 * tid < ln) O.lch[2 * tid] = ex;
+        if (2 * tid + 1 < ln) O.lch[2 * tid + 1] = ex + a0;
+        if (tid == 0) O.ltot = tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (qn) O.qbase = atomicAdd(&P.st->nf[L.ns], qn);
+        if (ln) {
+            const unsigned long long old = atomicAdd(
+                &P.st->heavy[L.ns], (unsigned long long)ln | ((unsigned long long)O.ltot << 32));
+            O.lpos = (uint32_t)old;
+            O.lcb = (uint32_t)(old >> 32);
+        }
+        if (un) O.ubase = atomicAdd(&P.st->u_wr, un);
+        if (final && P.stats && O.sdf) atomicAdd(&P.st->sdf[L.ns], O.sdf);
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < qn; t += kBlock) L.q_nxt[O.qbase + t] = O.q[t];
+    for (uint32_t t = tid; t < ln; t += kBlock) {
+        HeavyItem it;
+        it.v = O.lv[t];
+        it.chunk_base = O.lcb + O.lch[t];
+        L.h_nxt[O.lpos + t] = it;
+        const uint32_t c1 = (t + 1 < ln) ? O.lch[t + 1] : O.ltot;
+        for (uint32_t c = O.lch[t]; c < c1; ++c) L.c_nxt[O.lcb + c] = O.lpos + t;   // chunk -> column
+    }
+    for (uint32_t t = tid; t < un; t += kBlock) L.u_nxt[O.ubase + t] = O.u[t];
+    __syncthreads();
+    if (tid == 0) {
+        O.qn = 0;
+        O.ln = 0;
+        O.un = 0;
+        if (final) O.sdf = 0ull;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // the per-entry step: test the row mask, min-select the parent, claim
 // ---------------------------------------------------------------------------
 
-// Returns true for exactly one (j, i) pair per newly reached i: the one whose
-// atomicMin found the parent slot still empty.  Every unmasked pair reaches
-// the atomicMin unless the slot already holds a smaller or equal vertex, so
-// the final parent is the minimum over the level's frontier in-neighbours.
-__device__ __forceinline__ bool visit(const LevelParams &P, const uint32_t *vb_cur,
-                                      int32_t i, int32_t j, uint32_t k) {
-    const uint32_t w = vb_cur[(uint32_t)i >> 5];
-    if ((w >> (i & 31)) & 1u) return false;            // row i masked (visited through level k)
-    const uint32_t p = P.parent[i];                    // may be stale: only used to skip
+// For an unmasked pair (j, i) (row i not visited through level k): returns
+// true for exactly one such pair per newly reached i, the one whose atomicMin
+// found the parent slot still empty.  Every unmasked pair reaches the
+// atomicMin unless the slot already holds a smaller or equal vertex, so the
+// final parent is the minimum over the level's frontier in-neighbours.  The
+// pre-read is a coherent (agent-scope) load, so it sees the other lanes'
+// atomics and most pairs that cannot lower the parent skip the atomic.
+__device__ __forceinline__ bool claim(const LevelParams &P, int32_t i, int32_t j, uint32_t k) {
+    const uint32_t p = ld_agent(&P.parent[i]);
     if (p <= (uint32_t)j) return false;
     const uint32_t old = atomicMin(&P.parent[i], (uint32_t)j);
     if (old != 0xFFFFFFFFu) return false;
@@ -163,30 +312,87 @@ __device__ __forceinline__ bool visit(const LevelParams &P, const uint32_t *vb_c
     return true;
 }
 
-// Wave-aggregated append of newly reached vertices to the next frontier: one
-// atomicAdd per wave, lane offsets from the ballot mask.  Must be called by
-// every lane of the wave.
-__device__ __forceinline__ void append_next(const LevelParams &P, bool owner, int32_t i,
-                                            uint32_t ns, int32_t *q_nxt, uint32_t *vb_nxt,
-                                            uint32_t *fb_nxt) {
-    const unsigned long long m = __ballot(owner);
-    if (m == 0ull) return;
+// Set one bit per active lane in a bitmap.  Lanes holding vertices of the
+// same 32-bit word are combined into one atomicOr (wave-contiguous atomics are
+// an order of magnitude cheaper than ones that collide on a word); after a few
+// distinct words the remaining lanes fall back to one atomic each.
+__device__ __forceinline__ void or_bits_grouped(uint32_t *bm, bool on, int32_t v) {
+    unsigned long long act = __ballot(on);
     const uint32_t lane = lane_id();
-    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&P.st->nf[ns], (uint32_t)__popcll(m));
-    base = __shfl(base, (int)leader, 64);
-    unsigned long long d = 0;
+    const uint32_t myw = (uint32_t)v >> 5;
+    for (int round = 0; act; ++round) {
+        if (round == 4) {
+            if (on && ((act >> lane) & 1ull)) atomicOr(&bm[myw], 1u << (v & 31));
+            break;
+        }
+        const uint32_t leader = (uint32_t)__ffsll((long long)act) - 1u;
+        const uint32_t w = __shfl(myw, (int)leader, 64);
+        const bool mine = on && myw == w;
+        const unsigned long long grp = __ballot(mine);
+        uint32_t bits = mine ? (1u << (v & 31)) : 0u;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) bits |= __shfl_xor(bits, d, 64);
+        if (lane == leader) atomicOr(&bm[w], bits);
+        act &= ~grp;
+    }
+}
+
+// A newly reached vertex joins F_{k+1}: its column bounds are read once here
+// (or passed in when the caller already has them), its bit goes into B_{k+1},
+// and it is staged for the next frontier list (short column) or for the next
+// level's chunk queue (long column).  `grouped` combines the bitmap updates of
+// lanes that hold vertices of the same word (the pull form reaches vertices in
+// ascending order).
+__device__ __forceinline__ void append_next(const LevelParams &P, const LevelPtrs &L, OutLds &O,
+                                            bool owner, int32_t i, bool grouped = false,
+                                            int32_t kr0 = -1, int32_t kr1 = -1) {
+    const unsigned long long any = __ballot(owner);
+    if (any == 0ull) return;
+    int32_t r0 = 0, r1 = 0;
     if (owner) {
-        q_nxt[base + lanes_below(m)] = i;
+        if (kr0 >= 0) {
+            r0 = kr0;
+            r1 = kr1;
+        } else {
+            r0 = P.out_ptr[i];
+            r1 = P.out_ptr[i + 1];
+        }
+    }
+    if (grouped) {
+        or_bits_grouped(L.vb_nxt, owner, i);
+        if (P.maintain_fb) or_bits_grouped(L.fb_nxt, owner, i);
+    } else if (owner) {
         const uint32_t bit = 1u << (i & 31);
-        atomicOr(&vb_nxt[(uint32_t)i >> 5], bit);
-        if (P.maintain_fb) atomicOr(&fb_nxt[(uint32_t)i >> 5], bit);
-        if (P.stats) d = (unsigned long long)(P.out_ptr[i + 1] - P.out_ptr[i]);
+        atomicOr(&L.vb_nxt[(uint32_t)i >> 5], bit);
+        if (P.maintain_fb) atomicOr(&L.fb_nxt[(uint32_t)i >> 5], bit);
+    }
+    const uint32_t deg = (uint32_t)(r1 - r0);
+    const bool longcol = owner && deg >= P.heavy_min;
+    const bool shortcol = owner && !longcol;
+    const uint32_t lane = lane_id();
+    const unsigned long long m = __ballot(shortcol);
+    if (m) {
+        const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&O.qn, (uint32_t)__popcll(m));
+        base = __shfl(base, (int)leader, 64);
+        if (shortcol) {
+            QEnt e;
+            e.v = i;
+            e.r0 = r0;
+            e.r1 = r1;
+            e.pad = 0;
+            O.q[base + lanes_below(m)] = e;
+        }
+    }
+    if (longcol) {
+        const uint32_t slot = atomicAdd(&O.ln, 1u);
+        O.lv[slot] = i;
+        O.lch[slot] = (deg + P.chunk - 1u) / P.chunk;
     }
     if (P.stats) {
-        d = wave_sum64(d);
-        if (lane == leader) atomicAdd(&P.st->sdf[ns], d);
+        const unsigned long long d = wave_sum64(owner ? (unsigned long long)deg : 0ull);
+        if (lane == 0) atomicAdd(&O.sdf, d);
     }
 }
 
@@ -197,111 +403,172 @@ struct TileLds {
     uint32_t wsum[kBlock / 64];
 };
 
-// Expand one tile of up to kBlock frontier columns (one per thread: j >= 0
+// Entry e of the tile's concatenated columns: its row index and its column.
+// `lo` only moves forward (entries are visited in increasing e).
+__device__ __forceinline__ void tile_entry(const LevelParams &P, const TileLds &T, uint32_t total,
+                                           uint32_t e, uint32_t &lo, int32_t &i, int32_t &j) {
+    if (e >= total) return;
+    uint32_t hi = kBlock - 1;                          // last slot with pre <= e
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (T.pre[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    i = P.out_idx[T.r0[lo] + (int32_t)(e - T.pre[lo])];
+    j = T.j[lo];
+}
+
+// The word of B_k holding row i (all ones for "no entry": masked).
+__device__ __forceinline__ uint32_t mask_word(const LevelPtrs &L, int32_t i) {
+    return (i >= 0) ? L.vb_cur[(uint32_t)i >> 5] : 0xFFFFFFFFu;
+}
+
+// Mask test, parent min-select and claim for one pair (j, i), then the
+// block-wide append of the vertices claimed.  Called by every thread.
+__device__ __forceinline__ void settle(const LevelParams &P, const LevelPtrs &L, OutLds &O,
+                                       int32_t i, int32_t j, uint32_t mw) {
+    const bool unmasked = (i >= 0) && !((mw >> (i & 31)) & 1u);
+    const bool owner = unmasked && claim(P, i, j, L.k);
+    append_next(P, L, O, owner, i);
+    out_flush(P, L, O, false);
+}
+
+// Expand one tile of up to kBlock short frontier columns (one per thread: j >= 0
 // with entries [r0, r0 + deg)) with every lane of the block: an exclusive scan
 // of the degrees places the tile's entries on one line, lane t takes entries
 // t, t + 256, ... and finds its column by binary search over the prefix.
 // Consecutive lanes read consecutive entries of a column: coalesced.
-__device__ void expand_tile(const LevelParams &P, TileLds &L, int32_t j, int32_t r0,
-                            uint32_t deg, uint32_t k, uint32_t ns, const uint32_t *vb_cur,
-                            int32_t *q_nxt, uint32_t *vb_nxt, uint32_t *fb_nxt) {
+__device__ __forceinline__ void expand_tile(const LevelParams &P, const LevelPtrs &L, TileLds &T, OutLds &O,
+                            int32_t j, int32_t r0, uint32_t deg) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t incl = wave_incl_scan(deg);
-    if (lane == 63) L.wsum[wave] = incl;
+    if (lane == 63) T.wsum[wave] = incl;
     __syncthreads();
     uint32_t woff = 0, total = 0;
 #pragma unroll
     for (uint32_t w = 0; w < kBlock / 64; ++w) {
-        const uint32_t s = L.wsum[w];
+        const uint32_t s = T.wsum[w];
         woff += (w < wave) ? s : 0u;
         total += s;
     }
-    L.pre[tid] = woff + incl - deg;
-    L.j[tid] = j;
-    L.r0[tid] = r0;
+    T.pre[tid] = woff + incl - deg;
+    T.j[tid] = j;
+    T.r0[tid] = r0;
     __syncthreads();
+    // kIlp (= 4) entries per lane per round, their loads issued together; the
+    // four are kept in scalars so nothing is indexed dynamically
     uint32_t lo = 0;
-    for (uint32_t base = 0; base < total; base += kBlock) {
-        const uint32_t e = base + tid;
-        bool owner = false;
-        int32_t i = -1;
-        if (e < total) {
-            uint32_t hi = kBlock - 1;                  // last slot with pre <= e
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (L.pre[mid] <= e) lo = mid; else hi = mid - 1;
-            }
-            i = P.out_idx[L.r0[lo] + (int32_t)(e - L.pre[lo])];
-            owner = visit(P, vb_cur, i, L.j[lo], k);
-        }
-        append_next(P, owner, i, ns, q_nxt, vb_nxt, fb_nxt);
+    for (uint32_t base = 0; base < total; base += kBlock * kIlp) {
+        int32_t i0 = -1, i1 = -1, i2 = -1, i3 = -1, j0 = 0, j1 = 0, j2 = 0, j3 = 0;
+        tile_entry(P, T, total, base + 0 * kBlock + tid, lo, i0, j0);
+        tile_entry(P, T, total, base + 1 * kBlock + tid, lo, i1, j1);
+        tile_entry(P, T, total, base + 2 * kBlock + tid, lo, i2, j2);
+        tile_entry(P, T, total, base + 3 * kBlock + tid, lo, i3, j3);
+        const uint32_t m0 = mask_word(L, i0), m1 = mask_word(L, i1);
+        const uint32_t m2 = mask_word(L, i2), m3 = mask_word(L, i3);
+        settle(P, L, O, i0, j0, m0);
+        settle(P, L, O, i1, j1, m1);
+        settle(P, L, O, i2, j2, m2);
+        settle(P, L, O, i3, j3, m3);
     }
-    __syncthreads();   // L is reused by the next tile
+    __syncthreads();   // T is reused by the next tile
 }
 
-// A frontier column j with out-degree >= heavy_min is not expanded in its
-// tile: it is queued with its chunk count, and the tail kernel spreads its
-// chunks over the whole grid.  One 64-bit atomic gives both the queue slot and
-// the first chunk id, so chunk ids grow with queue position (binary search).
-__device__ __forceinline__ void queue_heavy(const LevelParams &P, uint32_t cs, int32_t j,
-                                            uint32_t deg) {
-    const uint32_t nch = (deg + P.chunk - 1u) / P.chunk;
-    const unsigned long long old =
-        atomicAdd(&P.st->heavy[cs], 1ull | ((unsigned long long)nch << 32));
-    HeavyItem it;
-    it.v = j;
-    it.chunk_base = (uint32_t)(old >> 32);
-    P.heavy[(uint32_t)old] = it;
+// One chunk of a long frontier column: every lane of the block takes entries
+// of the chunk in turn.  Chunk 0 of a column also moves the column into B_{k+1}
+// (unless the level copies B_k word by word).
+__device__ __forceinline__ void expand_chunk(const LevelParams &P, const LevelPtrs &L, OutLds &O, uint32_t c,
+                             uint32_t nlong, bool carry) {
+    __shared__ HeavyItem s_it;
+    (void)nlong;
+    if (threadIdx.x == 0) s_it = L.h_cur[L.c_cur[c]];
+    __syncthreads();
+    const HeavyItem it = s_it;
+    __syncthreads();
+    const int32_t j = it.v;
+    const uint32_t part = c - it.chunk_base;
+    if (carry && part == 0 && threadIdx.x == 0) {
+        atomicOr(&L.vb_nxt[(uint32_t)j >> 5], 1u << (j & 31));
+    }
+    const int32_t r1 = P.out_ptr[j + 1];
+    const int32_t e0 = P.out_ptr[j] + (int32_t)(part * P.chunk);
+    const int32_t e1 = (r1 - e0 > (int32_t)P.chunk) ? e0 + (int32_t)P.chunk : r1;
+    for (int32_t eb = e0; eb < e1; eb += kBlock * kIlp) {
+        const int32_t e = eb + (int32_t)threadIdx.x;
+        const int32_t i0 = (e < e1) ? P.out_idx[e] : -1;
+        const int32_t i1 = (e + kBlock < e1) ? P.out_idx[e + kBlock] : -1;
+        const int32_t i2 = (e + 2 * kBlock < e1) ? P.out_idx[e + 2 * kBlock] : -1;
+        const int32_t i3 = (e + 3 * kBlock < e1) ? P.out_idx[e + 3 * kBlock] : -1;
+        const uint32_t m0 = mask_word(L, i0), m1 = mask_word(L, i1);
+        const uint32_t m2 = mask_word(L, i2), m3 = mask_word(L, i3);
+        settle(P, L, O, i0, j, m0);
+        settle(P, L, O, i1, j, m1);
+        settle(P, L, O, i2, j, m2);
+        settle(P, L, O, i3, j, m3);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // the three forms of one level
 // ---------------------------------------------------------------------------
 
-__device__ void push_level(const LevelParams &P, TileLds &L, uint32_t k, uint32_t nf,
-                           uint32_t bid, uint32_t nblocks) {
-    const uint32_t cs = k & 3, ns = (k + 1) & 3;
-    const uint32_t *vb_cur = P.vb[k & 1];
-    uint32_t *vb_nxt = P.vb[(k + 1) & 1];
-    uint32_t *fb_cur = P.fb[k & 1];
-    uint32_t *fb_nxt = P.fb[(k + 1) & 1];
-    const int32_t *q_cur = P.q[k & 1];
-    int32_t *q_nxt = P.q[(k + 1) & 1];
-    for (uint32_t tile = bid; tile * kBlock < nf; tile += nblocks) {
-        const uint32_t pos = tile * kBlock + threadIdx.x;
-        int32_t j = -1, r0 = 0;
-        uint32_t deg = 0;
-        if (pos < nf) {
-            j = q_cur[pos];
-            r0 = P.out_ptr[j];
-            deg = (uint32_t)(P.out_ptr[j + 1] - r0);
-            atomicOr(&vb_nxt[(uint32_t)j >> 5], 1u << (j & 31));   // F_k joins B_{k+1}
-            if (P.maintain_fb) fb_cur[(uint32_t)j >> 5] = 0u;      // every bit there is in F_k
-            if (deg >= P.heavy_min) {
-                queue_heavy(P, cs, j, deg);
-                deg = 0;
-            }
-        }
-        expand_tile(P, L, j, r0, deg, k, ns, vb_cur, q_nxt, vb_nxt, fb_nxt);
+// B_{k+1} must contain B_k.  For a large frontier it is cheaper to OR B_k into
+// the other buffer word by word (words / 32 of the vertex count) than to set
+// one bit per frontier vertex with an atomic.
+__device__ __forceinline__ bool word_carry(const LevelParams &P, uint32_t nf) {
+    return nf > P.words;
+}
+
+__device__ __forceinline__ void carry_words(const LevelParams &P, const LevelPtrs &L, uint32_t bid,
+                            uint32_t nblocks) {
+    for (uint32_t w = bid * kBlock + threadIdx.x; w < P.words; w += nblocks * kBlock) {
+        const uint32_t b = L.vb_cur[w];
+        if (b) atomicOr(&L.vb_nxt[w], b);
     }
 }
 
-__device__ void bitmap_level(const LevelParams &P, TileLds &L, uint32_t k, uint32_t bid,
-                             uint32_t nblocks) {
-    const uint32_t cs = k & 3, ns = (k + 1) & 3;
-    const uint32_t *vb_cur = P.vb[k & 1];
-    uint32_t *vb_nxt = P.vb[(k + 1) & 1];
-    uint32_t *fb_cur = P.fb[k & 1];
-    uint32_t *fb_nxt = P.fb[(k + 1) & 1];
-    int32_t *q_nxt = P.q[(k + 1) & 1];
-    for (uint32_t wbase = bid * kBlock; wbase < P.words; wbase += nblocks * kBlock) {
-        const uint32_t w = wbase + threadIdx.x;
-        uint32_t bits = (w < P.words) ? fb_cur[w] : 0u;
-        if (bits) {
-            fb_cur[w] = 0u;
-            atomicOr(&vb_nxt[w], bits);
+// Push: work items are the tiles of the short-column list followed by the
+// chunks of the long columns, dealt round-robin to the blocks.
+__device__ __forceinline__ void push_level(const LevelParams &P, const LevelPtrs &L, TileLds &T, OutLds &O,
+                           uint32_t nreg, uint32_t nlong, uint32_t nchunks, uint32_t bid,
+                           uint32_t nblocks) {
+    const bool wc = word_carry(P, nreg + nlong);
+    if (wc) carry_words(P, L, bid, nblocks);
+    const uint32_t ntiles = (nreg + kBlock - 1) / kBlock;
+    const uint32_t items = ntiles + nchunks;
+    for (uint32_t it = bid; it < items; it += nblocks) {
+        if (it < ntiles) {
+            const uint32_t pos = it * kBlock + threadIdx.x;
+            int32_t j = -1, r0 = 0;
+            uint32_t deg = 0;
+            if (pos < nreg) {
+                const QEnt e = L.q_cur[pos];
+                j = e.v;
+                r0 = e.r0;
+                deg = (uint32_t)(e.r1 - e.r0);
+                if (!wc) atomicOr(&L.vb_nxt[(uint32_t)j >> 5], 1u << (j & 31));   // F_k joins B_{k+1}
+            }
+            expand_tile(P, L, T, O, j, r0, deg);
+        } else {
+            expand_chunk(P, L, O, it - ntiles, nlong, !wc);
         }
-        // one frontier column per thread per round, lowest bit first
+    }
+}
+
+// Push with the frontier read from the bitmap: items are 256-word groups of
+// the frontier bitmap (one frontier column per thread per round, lowest bit
+// first) followed by the chunks of the long columns.
+__device__ __forceinline__ void bitmap_level(const LevelParams &P, const LevelPtrs &L, TileLds &T, OutLds &O,
+                             uint32_t nlong, uint32_t nchunks, uint32_t bid, uint32_t nblocks) {
+    const uint32_t ngroups = (P.words + kBlock - 1) / kBlock;
+    const uint32_t items = ngroups + nchunks;
+    for (uint32_t it = bid; it < items; it += nblocks) {
+        if (it >= ngroups) {
+            expand_chunk(P, L, O, it - ngroups, nlong, false);
+            continue;
+        }
+        const uint32_t w = it * kBlock + threadIdx.x;
+        uint32_t bits = (w < P.words) ? L.fb_cur[w] : 0u;
+        if (bits) atomicOr(&L.vb_nxt[w], bits);         // F_k joins B_{k+1}
         while (__syncthreads_or(bits != 0u)) {
             int32_t j = -1, r0 = 0;
             uint32_t deg = 0;
@@ -311,17 +578,24 @@ __device__ void bitmap_level(const LevelParams &P, TileLds &L, uint32_t k, uint3
                 j = (int32_t)(w * 32u + b);
                 r0 = P.out_ptr[j];
                 deg = (uint32_t)(P.out_ptr[j + 1] - r0);
-                if (deg >= P.heavy_min) {
-                    queue_heavy(P, cs, j, deg);
+                if (deg >= P.heavy_min) {             // a long column: done by its chunks
+                    j = -1;
                     deg = 0;
                 }
             }
-            expand_tile(P, L, j, r0, deg, k, ns, vb_cur, q_nxt, vb_nxt, fb_nxt);
+            expand_tile(P, L, T, O, j, r0, deg);
         }
     }
 }
 
 constexpr uint32_t kPullSerial = 32;     // in-neighbours a lane scans before handing off
+
+// w in F_k: the frontier bitmap when it is kept (L2-resident), else level[w] = k
+__device__ __forceinline__ bool in_frontier(const LevelParams &P, const LevelPtrs &L, int32_t w,
+                                            int32_t lk) {
+    if (P.maintain_fb) return (L.fb_cur[(uint32_t)w >> 5] >> (w & 31)) & 1u;
+    return P.level[w] == lk;
+}
 
 struct PullLds {
     int32_t lng[kBlock];
@@ -334,50 +608,50 @@ struct PullLds {
 // in-neighbour, i.e. the same min-parent the push form produces.  Rows with
 // long in-lists that are not settled by their first kPullSerial entries are
 // finished one wave per row (64 entries per step, ballot for the first hit).
-__device__ void pull_level(const LevelParams &P, PullLds &L, uint32_t k, uint32_t nf,
-                           uint32_t bid, uint32_t nblocks) {
-    const uint32_t ns = (k + 1) & 3;
-    const uint32_t *vb_cur = P.vb[k & 1];
-    uint32_t *vb_nxt = P.vb[(k + 1) & 1];
-    uint32_t *fb_cur = P.fb[k & 1];
-    uint32_t *fb_nxt = P.fb[(k + 1) & 1];
-    const int32_t *q_cur = P.q[k & 1];
-    int32_t *q_nxt = P.q[(k + 1) & 1];
+// A row with no in-neighbour can never be reached and leaves the list.
+__device__ __forceinline__ void pull_level(const LevelParams &P, LevelPtrs &L, PullLds &S, OutLds &O,
+                           uint32_t nreg, uint32_t nlong, uint32_t bid, uint32_t nblocks) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     // F_k joins B_{k+1}; its frontier bits are cleared
-    for (uint32_t pos = bid * kBlock + tid; pos < nf; pos += nblocks * kBlock) {
-        const int32_t j = q_cur[pos];
-        atomicOr(&vb_nxt[(uint32_t)j >> 5], 1u << (j & 31));
-        if (P.maintain_fb) fb_cur[(uint32_t)j >> 5] = 0u;
+    const bool wc = word_carry(P, nreg + nlong);
+    if (wc) carry_words(P, L, bid, nblocks);
+    if (!wc) {
+        for (uint32_t pos = bid * kBlock + tid; pos < nreg + nlong; pos += nblocks * kBlock) {
+            const int32_t j = (pos < nreg) ? L.q_cur[pos].v : L.h_cur[pos - nreg].v;
+            atomicOr(&L.vb_nxt[(uint32_t)j >> 5], 1u << (j & 31));
+        }
     }
     const uint32_t ub = P.st->u_buf;
     const uint32_t ulen = P.st->u_len;
     const bool all = (ulen == kAllVertices);
     const uint32_t len = all ? (uint32_t)P.n : ulen;
-    const int32_t *U = P.ul[ub];
-    int32_t *Un = P.ul[ub ^ 1u];
-    const int32_t lk = (int32_t)k;
+    const int32_t *U = ub ? P.ul[1] : P.ul[0];
+    L.u_nxt = ub ? P.ul[0] : P.ul[1];
+    const int32_t lk = (int32_t)L.k;
+    const bool undirected = (P.in_ptr == P.out_ptr);
     for (uint32_t tile = bid; tile * kBlock < len; tile += nblocks) {
-        if (tid == 0) L.nlong = 0;
+        if (tid == 0) S.nlong = 0;
         __syncthreads();
         const uint32_t pos = tile * kBlock + tid;
-        int32_t u = -1, found = -1;
+        int32_t u = -1, found = -1, ue0 = 0, ue1 = 0;
         bool keep = false;
         if (pos < len) {
             u = all ? (int32_t)pos : U[pos];
-            if (!((vb_cur[(uint32_t)u >> 5] >> (u & 31)) & 1u)) {
+            if (!((L.vb_cur[(uint32_t)u >> 5] >> (u & 31)) & 1u)) {
                 const int32_t e0 = P.in_ptr[u], e1 = P.in_ptr[u + 1];
+                ue0 = e0;
+                ue1 = e1;
                 const int32_t lim = (e1 - e0 > (int32_t)kPullSerial) ? e0 + (int32_t)kPullSerial : e1;
                 for (int32_t e = e0; e < lim; ++e) {
                     const int32_t w = P.in_idx[e];
-                    if (P.level[w] == lk) { found = w; break; }
+                    if (in_frontier(P, L, w, lk)) { found = w; break; }
                 }
                 if (found < 0) {
                     if (lim < e1) {
-                        const uint32_t slot = atomicAdd(&L.nlong, 1u);
-                        L.lng[slot] = u;
+                        const uint32_t slot = atomicAdd(&S.nlong, 1u);
+                        S.lng[slot] = u;
                     } else {
-                        keep = true;
+                        keep = e1 > e0;
                     }
                 }
             }
@@ -387,89 +661,63 @@ __device__ void pull_level(const LevelParams &P, PullLds &L, uint32_t k, uint32_
             P.parent[u] = (uint32_t)found;
             P.level[u] = lk + 1;
         }
-        append_next(P, owner, u, ns, q_nxt, vb_nxt, fb_nxt);
+        if (undirected) append_next(P, L, O, owner, u, true, ue0, ue1);
+        else append_next(P, L, O, owner, u, true);
         {   // survivors stay on the unvisited list
             const unsigned long long m = __ballot(keep);
             if (m) {
                 const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
                 uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(&P.st->u_wr, (uint32_t)__popcll(m));
+                if (lane == leader) base = atomicAdd(&O.un, (uint32_t)__popcll(m));
                 base = __shfl(base, (int)leader, 64);
-                if (keep) Un[base + lanes_below(m)] = u;
+                if (keep) O.u[base + lanes_below(m)] = u;
             }
         }
-        __syncthreads();
-        const uint32_t nlong = L.nlong;
-        for (uint32_t t = wave; t < nlong; t += kBlock / 64) {
-            const int32_t v = L.lng[t];
-            const int32_t e1 = P.in_ptr[v + 1];
-            int32_t hit = -1;
-            for (int32_t eb = P.in_ptr[v] + (int32_t)kPullSerial; eb < e1; eb += 64) {
-                const int32_t e = eb + (int32_t)lane;
-                int32_t w = -1;
-                bool f = false;
-                if (e < e1) {
-                    w = P.in_idx[e];
-                    f = (P.level[w] == lk);
-                }
-                const unsigned long long m = __ballot(f);
-                if (m) {
-                    hit = __shfl(w, __ffsll((long long)m) - 1, 64);
-                    break;
+        out_flush(P, L, O, false);
+        const uint32_t nl = S.nlong;
+        for (uint32_t t0 = 0; t0 < nl; t0 += kBlock / 64) {
+            const uint32_t t = t0 + wave;                 // one long row per wave per round
+            int32_t v = -1, hit = -1;
+            bool any = false;
+            if (t < nl) {
+                v = S.lng[t];
+                any = true;
+                const int32_t e1 = P.in_ptr[v + 1];
+                for (int32_t eb = P.in_ptr[v] + (int32_t)kPullSerial; eb < e1; eb += 64) {
+                    const int32_t e = eb + (int32_t)lane;
+                    int32_t w = -1;
+                    bool f = false;
+                    if (e < e1) {
+                        w = P.in_idx[e];
+                        f = in_frontier(P, L, w, lk);
+                    }
+                    const unsigned long long m = __ballot(f);
+                    if (m) {
+                        hit = __shfl(w, __ffsll((long long)m) - 1, 64);
+                        break;
+                    }
                 }
             }
-            const bool own = (hit >= 0) && lane == 0;
+            const bool own = any && (hit >= 0) && lane == 0;
             if (own) {
                 P.parent[v] = (uint32_t)hit;
                 P.level[v] = lk + 1;
             }
-            append_next(P, own, v, ns, q_nxt, vb_nxt, fb_nxt);
-            if (hit < 0 && lane == 0) Un[atomicAdd(&P.st->u_wr, 1u)] = v;
+            append_next(P, L, O, own, v);
+            if (any && hit < 0 && lane == 0) O.u[atomicAdd(&O.un, 1u)] = v;
+            out_flush(P, L, O, false);
         }
         __syncthreads();
     }
 }
 
-// Chunks of the columns queued by queue_heavy, spread over the grid.
-__device__ void heavy_chunks(const LevelParams &P, uint32_t k, uint32_t bid, uint32_t nblocks) {
-    const uint32_t cs = k & 3, ns = (k + 1) & 3;
-    const uint32_t *vb_cur = P.vb[k & 1];
-    uint32_t *vb_nxt = P.vb[(k + 1) & 1];
-    uint32_t *fb_nxt = P.fb[(k + 1) & 1];
-    int32_t *q_nxt = P.q[(k + 1) & 1];
-    const unsigned long long packed = P.st->heavy[cs];
-    const uint32_t count = (uint32_t)packed, chunks = (uint32_t)(packed >> 32);
-    for (uint32_t c = bid; c < chunks; c += nblocks) {
-        uint32_t lo = 0, hi = count - 1;               // last item with chunk_base <= c
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (P.heavy[mid].chunk_base <= c) lo = mid; else hi = mid - 1;
-        }
-        const HeavyItem it = P.heavy[lo];
-        const int32_t j = it.v;
-        const int32_t r1 = P.out_ptr[j + 1];
-        const int32_t e0 = P.out_ptr[j] + (int32_t)((c - it.chunk_base) * P.chunk);
-        const int32_t e1 = (r1 - e0 > (int32_t)P.chunk) ? e0 + (int32_t)P.chunk : r1;
-        for (int32_t eb = e0; eb < e1; eb += kBlock) {
-            const int32_t e = eb + (int32_t)threadIdx.x;
-            bool owner = false;
-            int32_t i = -1;
-            if (e < e1) {
-                i = P.out_idx[e];
-                owner = visit(P, vb_cur, i, j, k);
-            }
-            append_next(P, owner, i, ns, q_nxt, vb_nxt, fb_nxt);
-        }
-    }
-}
-
 // End of level k, one thread: fold the level's counters into the state and
-// advance (only if F_k was nonempty, so extra launches after the end are no-ops).
-__device__ void finish_level(const LevelParams &P, uint32_t k, uint32_t nf) {
+// advance.  Only called when F_k was nonempty, so extra launches after the
+// end of the search are no-ops.
+__device__ __forceinline__ void finish_level(const LevelParams &P, uint32_t k, uint32_t nf) {
     BfsState *st = P.st;
     const uint32_t cs = k & 3, ns = (k + 1) & 3;
-    if (nf == 0) return;
-    const uint32_t nf_next = ld_agent(&st->nf[ns]);
+    const uint32_t nf_next = ld_agent(&st->nf[ns]) + (uint32_t)ld_agent64(&st->heavy[ns]);
     const unsigned long long sdf_next = ld_agent64(&st->sdf[ns]);
     const uint32_t variant = ld_agent(&st->variant);
     if (P.trace) {
@@ -493,22 +741,37 @@ __device__ void finish_level(const LevelParams &P, uint32_t k, uint32_t nf) {
     st->level = k + 1;
 }
 
-__device__ void level_body(const LevelParams &P, uint32_t k, uint32_t nf, uint32_t bid,
-                           uint32_t nblocks) {
+__device__ __forceinline__ uint32_t frontier_size(const BfsState *st, uint32_t slot) {
+    return st->nf[slot] + (uint32_t)st->heavy[slot];
+}
+
+__device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uint32_t bid, uint32_t nblocks) {
     __shared__ TileLds tl;
     __shared__ PullLds pl;
-    const uint32_t v = choose_variant(P, k, nf);
+    __shared__ OutLds ol;
+    const BfsState *st = P.st;
+    LevelPtrs L = level_ptrs(P, k);
+    const uint32_t nreg = st->nf[L.cs];
+    const unsigned long long hp = st->heavy[L.cs];
+    const uint32_t nlong = (uint32_t)hp, nchunks = (uint32_t)(hp >> 32);
+    const uint32_t v = choose_variant(P, k, nreg + nlong);
     if (bid == 0 && threadIdx.x == 0) {
-        BfsState *st = P.st;
+        BfsState *w = P.st;
         const uint32_t fs = (k + 2) & 3;     // slot of level k+2: free since level k-2
-        st->variant = v;
-        st->nf[fs] = 0;
-        st->heavy[fs] = 0ull;
-        st->sdf[fs] = 0ull;
+        w->variant = v;
+        w->nf[fs] = 0;
+        w->heavy[fs] = 0ull;
+        w->sdf[fs] = 0ull;
     }
-    if (v == kPull) pull_level(P, pl, k, nf, bid, nblocks);
-    else if (v == kBitmap) bitmap_level(P, tl, k, bid, nblocks);
-    else push_level(P, tl, k, nf, bid, nblocks);
+    out_init(ol);
+    if (P.maintain_fb) {          // fb[(k+2)%3] held F_{k-1}: nobody reads or writes it now
+        for (uint32_t w = bid * kBlock + threadIdx.x; w < P.words; w += nblocks * kBlock)
+            L.fb_old[w] = 0u;
+    }
+    if (v == kPull) pull_level(P, L, pl, ol, nreg, nlong, bid, nblocks);
+    else if (v == kBitmap) bitmap_level(P, L, tl, ol, nlong, nchunks, bid, nblocks);
+    else push_level(P, L, tl, ol, nreg, nlong, nchunks, bid, nblocks);
+    out_flush(P, L, ol, true);
 }
 
 }  // namespace
@@ -518,10 +781,8 @@ __device__ void level_body(const LevelParams &P, uint32_t k, uint32_t nf, uint32
 // ---------------------------------------------------------------------------
 
 // Initialise outputs and state for a search from one root (single_root >= 0)
-// or from a list of roots in distinct components (multi-root: each root's
-// component gets exactly the result of a search from that root alone).
-__global__ __launch_bounds__(kBlock) void k_init(LevelParams P, int32_t nroots,
-                                                 const int32_t *roots, int32_t single_root) {
+// or from a list of roots (multi-root, completed by k_init_roots).
+__global__ __launch_bounds__(kBlock) void k_init(LevelParams P, int32_t single_root) {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t v = gid; v < (uint32_t)P.n; v += stride) {
@@ -536,6 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_init(LevelParams P, int32_t nroots,
         if (P.maintain_fb) {
             P.fb[0][w] = bits;
             P.fb[1][w] = 0u;
+            P.fb[2][w] = 0u;
         }
     }
     if (gid == 0) {
@@ -548,90 +810,123 @@ __global__ __launch_bounds__(kBlock) void k_init(LevelParams P, int32_t nroots,
         st->u_wr = 0;
         st->barrier = 0;
         st->barrier_gen = 0;
+        for (int g = 0; g < kBarGroups; ++g) st->bar_group[g * 16] = 0;
+        st->bar_top = 0;
+        st->visited_cnt = 0;
+        st->visited_deg = 0ull;
         for (int r = 0; r < kRing; ++r) {
             st->nf[r] = 0;
             st->heavy[r] = 0ull;
             st->sdf[r] = 0ull;
         }
         if (single_root >= 0) {
-            P.q[0][0] = single_root;
-            st->nf[0] = 1;
-            const unsigned long long d =
-                (unsigned long long)(P.out_ptr[single_root + 1] - P.out_ptr[single_root]);
-            st->sdf[0] = d;
+            const int32_t r0 = P.out_ptr[single_root], r1 = P.out_ptr[single_root + 1];
+            const uint32_t deg = (uint32_t)(r1 - r0);
+            if (deg >= P.heavy_min) {
+                HeavyItem it;
+                it.v = single_root;
+                it.chunk_base = 0;
+                P.hl[0][0] = it;
+                const uint32_t nch = (deg + P.chunk - 1u) / P.chunk;
+                for (uint32_t c = 0; c < nch; ++c) P.cmap[0][c] = 0;
+                st->heavy[0] = 1ull | ((unsigned long long)nch << 32);
+            } else {
+                QEnt e;
+                e.v = single_root;
+                e.r0 = r0;
+                e.r1 = r1;
+                e.pad = 0;
+                P.q[0][0] = e;
+                st->nf[0] = 1;
+            }
+            st->sdf[0] = deg;
             st->visited_cnt = 1;
-            st->visited_deg = d;
-        } else {
-            st->nf[0] = (uint32_t)nroots;
-            st->visited_cnt = (uint32_t)nroots;
-            st->visited_deg = 0ull;   // completed by k_init_roots
+            st->visited_deg = deg;
         }
     }
 }
 
-// second init pass for multi-root searches (after k_init has cleared everything)
+// second init pass for multi-root searches (after k_init has cleared everything):
+// the roots are appended to the level-0 frontier exactly as a level appends
 __global__ __launch_bounds__(kBlock) void k_init_roots(LevelParams P, int32_t nroots,
                                                        const int32_t *roots) {
+    __shared__ OutLds ol;
+    LevelPtrs L = level_ptrs(P, 0u);
+    L.vb_nxt = P.vb[0];
+    L.fb_nxt = P.fb[0];
+    L.q_nxt = P.q[0];
+    L.h_nxt = P.hl[0];
+    L.c_nxt = P.cmap[0];
+    L.ns = 0;
+    out_init(ol);
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
-    unsigned long long d = 0;
+    bool own = false;
+    int32_t r = -1;
     if (gid < (uint32_t)nroots) {
-        const int32_t r = roots[gid];
+        r = roots[gid];
         P.level[r] = 0;
         P.parent[r] = (uint32_t)r;
-        atomicOr(&P.vb[0][(uint32_t)r >> 5], 1u << (r & 31));
-        if (P.maintain_fb) atomicOr(&P.fb[0][(uint32_t)r >> 5], 1u << (r & 31));
-        P.q[0][gid] = r;
-        d = (unsigned long long)(P.out_ptr[r + 1] - P.out_ptr[r]);
+        own = true;
     }
+    append_next(P, L, ol, own, r);
+    unsigned long long d = 0;
+    if (own) d = (unsigned long long)(P.out_ptr[r + 1] - P.out_ptr[r]);
     d = wave_sum64(d);
-    if (lane_id() == 0 && d) {
-        atomicAdd(&P.st->sdf[0], d);
+    const unsigned long long c = wave_sum64(own ? 1ull : 0ull);
+    if (lane_id() == 0 && c) {
         atomicAdd(&P.st->visited_deg, d);
+        atomicAdd(&P.st->visited_cnt, (uint32_t)c);
+        if (!P.stats) atomicAdd(&P.st->sdf[0], d);
     }
+    out_flush(P, L, ol, true);
 }
 
-__global__ __launch_bounds__(kBlock) void k_level(LevelParams P) {
-    const uint32_t k = P.st->level;
-    const uint32_t nf = P.st->nf[k & 3];
-    if (nf == 0) return;
-    level_body(P, k, nf, blockIdx.x, gridDim.x);
-}
-
-__global__ __launch_bounds__(kBlock) void k_tail(LevelParams P) {
-    BfsState *st = P.st;
+__global__ __launch_bounds__(kBlock, 8) void k_level(LevelParams P) {
+    const BfsState *st = P.st;
     const uint32_t k = st->level;
-    const uint32_t nf = st->nf[k & 3];
-    if (nf != 0) heavy_chunks(P, k, blockIdx.x, gridDim.x);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(&st->done, 1u);
-        if (prev == gridDim.x - 1) {
-            __threadfence();
-            st->done = 0;
-            finish_level(P, k, nf);
-        }
-    }
+    if (frontier_size(st, k & 3) == 0) return;
+    level_body(P, k, blockIdx.x, gridDim.x);
 }
 
-// Grid barrier for the cooperative kernel.  Returns false (and raises the
-// error flag through `barrier_gen` staying put) only if the spin limit runs
-// out, which cannot happen when every block is resident.
+// One thread closes level k after the level kernel (stream order).
+__global__ void k_finish(LevelParams P) {
+    const BfsState *st = P.st;
+    const uint32_t k = st->level;
+    const uint32_t nf = frontier_size(st, k & 3);
+    if (threadIdx.x == 0 && nf != 0) finish_level(P, k, nf);
+}
+
+// Grid barrier for the cooperative kernel.  Blocks arrive on one of
+// kBarGroups counters (block b on group b % kBarGroups, each counter on its own
+// line), the last arrival of a group arrives on the top counter, and the last
+// group releases everyone by bumping the generation - arrivals serialise on
+// kBarGroups + nblocks / kBarGroups atomics instead of nblocks.  Returns false
+// only if the spin limit runs out, which cannot happen when every block is
+// resident.
 __device__ bool grid_sync(BfsState *st, uint32_t nblocks, uint32_t *s_ok) {
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t ok = 1;
+        const uint32_t groups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
+        const uint32_t g = blockIdx.x % groups;
+        const uint32_t in_group = (nblocks - g + groups - 1) / groups;
         const uint32_t gen = ld_agent(&st->barrier_gen);
         __threadfence();
-        const uint32_t arrived = atomicAdd(&st->barrier, 1u);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&st->barrier, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        if (atomicAdd(&st->bar_group[g * 16], 1u) == in_group - 1) {
+            __hip_atomic_store(&st->bar_group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (atomicAdd(&st->bar_top, 1u) == groups - 1) {
+                __hip_atomic_store(&st->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (last) {
             __threadfence();
             atomicAdd(&st->barrier_gen, 1u);
         } else {
             uint32_t spins = 0;
             while (ld_agent(&st->barrier_gen) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
                 if (++spins > (1u << 26)) { ok = 0; break; }
             }
         }
@@ -642,20 +937,18 @@ __device__ bool grid_sync(BfsState *st, uint32_t nblocks, uint32_t *s_ok) {
     return *s_ok != 0;
 }
 
-// Every level in one launch: level body, barrier, split-column chunks,
-// barrier, block 0 finishes the level, barrier.  The loop ends when the
-// frontier is empty (every block reads the same counters after a barrier).
+// Every level in one launch: level body, barrier, block 0 finishes the level,
+// barrier.  The loop ends when the frontier is empty (every block reads the
+// same counters after a barrier).
 __global__ __launch_bounds__(kBlock) void k_persistent(LevelParams P) {
     __shared__ uint32_t s_ok;
     BfsState *st = P.st;
     const uint32_t nb = gridDim.x;
     for (;;) {
         const uint32_t k = ld_agent(&st->level);
-        const uint32_t nf = ld_agent(&st->nf[k & 3]);
+        const uint32_t nf = ld_agent(&st->nf[k & 3]) + (uint32_t)ld_agent64(&st->heavy[k & 3]);
         if (nf == 0) break;
-        level_body(P, k, nf, blockIdx.x, nb);
-        if (!grid_sync(st, nb, &s_ok)) break;
-        heavy_chunks(P, k, blockIdx.x, nb);
+        level_body(P, k, blockIdx.x, nb);
         if (!grid_sync(st, nb, &s_ok)) break;
         if (blockIdx.x == 0 && threadIdx.x == 0) finish_level(P, k, nf);
         if (!grid_sync(st, nb, &s_ok)) break;
@@ -672,7 +965,7 @@ hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *root
     uint32_t grid = (work + kBlock - 1) / kBlock;
     if (grid > 4096) grid = 4096;
     if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, p, nroots, roots_dev, single_root);
+    hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, p, single_root);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || single_root >= 0) return e;
     const uint32_t g2 = ((uint32_t)nroots + kBlock - 1) / kBlock;
@@ -685,8 +978,8 @@ hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tail(const LevelParams &p, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_tail, dim3(grid), dim3(kBlock), 0, s, p);
+hipError_t launch_finish(const LevelParams &p, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
