@@ -24,6 +24,7 @@ struct GraphExecCache {
     uint32_t policy = 0, grid = 0, heavy = 0, chunk = 0, levels = 0, fb = 0, stats = 0;
     const float *sel = nullptr;
     const void *trace = nullptr;
+    const void *slot = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -152,6 +153,29 @@ WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor) {
 }
 }  // namespace bfsi
 
+namespace bfsi {
+MsLayout ms_layout(int32_t n, int32_t nq) {
+    MsLayout L{};
+    const size_t W = ((size_t)nq + 63) / 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.vis = take((size_t)n * W * 8);
+    L.m0 = take((size_t)n * W * 8);
+    L.m1 = take((size_t)n * W * 8);
+    L.m2 = take((size_t)n * W * 8);
+    L.f0 = take((size_t)n * 4);
+    L.f1 = take((size_t)n * 4);
+    L.f2 = take((size_t)n * 4);
+    L.flag = take((size_t)n * 4);
+    L.cnt = take(64);
+    L.lptr = take((size_t)nq * 8);
+    L.pptr = take((size_t)nq * 8);
+    L.src = take((size_t)nq * 4);
+    L.total = off;
+    return L;
+}
+}  // namespace bfsi
+
 namespace {
 
 constexpr uint32_t kHeavyFloor = 32;
@@ -217,45 +241,71 @@ bfs_status resolve_cfg(bfs_graph *g, const bfs_run_options *opt, RunCfg &c) {
     return BFS_OK;
 }
 
-struct PinnedState {
-    BfsState *h = nullptr;
-    PinnedState() { if (hipHostMalloc((void **)&h, sizeof(BfsState), 0) != hipSuccess) h = nullptr; }
-    ~PinnedState() { if (h) hipHostFree(h); }
+// Where the level kernels report progress to the host: a small pinned,
+// coherent host buffer per host thread, written by the device after every
+// level ([0] = current level, [1] = its frontier size).  Allocated on the
+// thread's first search and kept for the life of the process, so searches
+// themselves allocate nothing.
+struct HostSlot {
+    volatile uint32_t *h = nullptr;
+    uint32_t *d = nullptr;
 };
 
-// read the state back; returns true when the search is over
-bfs_status read_state(const LevelParams &P, BfsState *h, hipStream_t s, bool &done) {
-    HIP_TRY(hipMemcpyAsync(h, P.st, sizeof(BfsState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const uint32_t slot = h->level & 3;
-    done = (h->nf[slot] == 0 && (uint32_t)h->heavy[slot] == 0);
+bfs_status host_slot(HostSlot *&out) {
+    thread_local HostSlot slot;
+    if (!slot.h) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+            return fail(BFS_ENOMEM, "hipHostMalloc of the progress slot failed");
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess)
+            return fail(BFS_EHIP, "hipHostGetDevicePointer of the progress slot failed");
+        slot.h = (volatile uint32_t *)p;
+        slot.d = (uint32_t *)dp;
+    }
+    out = &slot;
     return BFS_OK;
 }
 
-bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipStream_t s,
+// wait for the stream, then read the progress the device left in the slot
+bfs_status wait_progress(const HostSlot *hs, hipStream_t s, bool &done, uint32_t &level) {
+    HIP_TRY(hipStreamSynchronize(s));
+    level = hs->h[0];
+    done = (hs->h[1] == 0);
+    return BFS_OK;
+}
+
+bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t s,
                       uint32_t &levels_out, bfs_run_options *opt) {
-    PinnedState ps;
-    if (!ps.h) return fail(BFS_ENOMEM, "hipHostMalloc of the state readback failed");
+    HostSlot *hs = nullptr;
+    bfs_status st0 = host_slot(hs);
+    if (st0 != BFS_OK) return st0;
+    P.host_status = hs->d;
+    hs->h[0] = 0;
+    hs->h[1] = 1;
     const uint64_t max_levels = (uint64_t)g->n + 2;
     bool done = false;
+    uint32_t level = 0;
     std::vector<float> times;
+    std::unique_lock<std::mutex> lock(g->mu, std::defer_lock);
     if (c.loop == BFS_LOOP_PERSISTENT) {
         uint32_t maxg = persistent_max_grid(g->device);
         if (maxg == 0) return fail(BFS_EHIP, "occupancy query for the persistent kernel failed");
         uint32_t grid = std::min(c.grid, maxg);
         HIP_TRY(launch_persistent(P, grid, s));
-        bfs_status st = read_state(P, ps.h, s, done);
+        bfs_status st = wait_progress(hs, s, done, level);
         if (st != BFS_OK) return st;
         if (!done) return fail(BFS_EHIP, "persistent search stopped at level %u with a nonempty frontier "
-                                         "(grid barrier spin limit)", ps.h->level);
+                                         "(grid barrier spin limit)", level);
     } else if (c.loop == BFS_LOOP_GRAPH) {
+        lock.lock();                  // the captured graph is cached per bfs_graph
         GraphExecCache &gc = g->gcache;
         const uint32_t L = c.per_sync;
         bool hit = gc.valid && gc.ws == (const void *)P.st && gc.level == P.level &&
                    gc.parent == P.parent && gc.policy == c.policy && gc.grid == c.grid &&
                    gc.heavy == c.heavy && gc.chunk == c.chunk && gc.levels == L &&
                    gc.sel == c.sel && gc.fb == P.maintain_fb && gc.stats == P.stats &&
-                   gc.trace == (const void *)P.trace;
+                   gc.trace == (const void *)P.trace && gc.slot == (const void *)P.host_status;
         if (!hit) {
             if (gc.exec) { hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
             if (gc.graph) { hipGraphDestroy(gc.graph); gc.graph = nullptr; }
@@ -283,16 +333,17 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
             gc.ws = P.st; gc.level = P.level; gc.parent = P.parent; gc.policy = c.policy;
             gc.grid = c.grid; gc.heavy = c.heavy; gc.chunk = c.chunk; gc.levels = L;
             gc.sel = c.sel; gc.fb = P.maintain_fb; gc.stats = P.stats;
-            gc.trace = (const void *)P.trace; gc.valid = true;
+            gc.trace = (const void *)P.trace; gc.slot = (const void *)P.host_status; gc.valid = true;
         }
         for (uint64_t issued = 0; !done; issued += L) {
             if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
             HIP_TRY(hipGraphLaunch(gc.exec, s));
-            bfs_status st = read_state(P, ps.h, s, done);
+            bfs_status st = wait_progress(hs, s, done, level);
             if (st != BFS_OK) return st;
         }
     } else {
         const bool tk = opt && opt->time_kernels;
+        if (tk) lock.lock();          // the event pool is per bfs_graph
         const uint32_t L = c.per_sync;
         uint32_t launched = 0;
         auto ev = [&](uint32_t i, hipEvent_t &out) -> bfs_status {
@@ -319,7 +370,7 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
                 HIP_TRY(launch_finish(P, s));
                 ++launched;
             }
-            bfs_status st = read_state(P, ps.h, s, done);
+            bfs_status st = wait_progress(hs, s, done, level);
             if (st != BFS_OK) return st;
         }
         if (tk) {
@@ -334,7 +385,7 @@ bfs_status run_levels(bfs_graph *g, const LevelParams &P, const RunCfg &c, hipSt
             opt->kernel_us = total;
         }
     }
-    levels_out = ps.h->level;
+    levels_out = level;
     if (opt && opt->trace && P.trace) {
         const uint32_t nrec = std::min<uint32_t>(std::min<uint32_t>(levels_out, kTraceCap), opt->trace_capacity);
         std::vector<DevLevelRec> recs(nrec ? nrec : 1);
@@ -492,12 +543,7 @@ size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_
     if (!g || num_queries <= 0 || run_flags != 0) return 0;
     const size_t single = ws_layout(g->n, g->nnz, kHeavyFloor).total;
     if (num_queries == 1) return single;
-    // multi-source: three masks of ceil(q/64) words per vertex, two frontier
-    // lists, a queued flag per vertex and the counters
-    const size_t w64 = ((size_t)num_queries + 63) / 64;
-    size_t ms = align256(256) + 3 * align256((size_t)g->n * w64 * 8) + 2 * align256((size_t)g->n * 4) +
-                align256((size_t)g->n * 4) + align256((size_t)num_queries * 16);
-    return std::max(single, ms);
+    return std::max(single, ms_layout(g->n, num_queries).total);
 }
 
 bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
@@ -517,7 +563,6 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
     hipStream_t s = (hipStream_t)hip_stream;
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
-    std::lock_guard<std::mutex> lock(g->mu);   // the captured-graph cache is per graph
     HIP_TRY(launch_init(P, 1, nullptr, source, s));
     uint32_t levels = 0;
     st = run_levels(g, P, c, s, levels, opt);
@@ -554,7 +599,6 @@ extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t 
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
     int32_t *roots_dev = (int32_t *)((char *)workspace + L.total);
-    std::lock_guard<std::mutex> lock(g->mu);
     HIP_TRY(hipMemcpyAsync(roots_dev, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_init(P, nroots, roots_dev, -1, s));
     uint32_t levels = 0;
@@ -569,20 +613,85 @@ extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
     return ws_layout(g->n, g->nnz, kHeavyFloor).total + align256((size_t)nroots * 4);
 }
 
+// All queries on one graph: the multi-source kernels.
+static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sources,
+                                   int32_t *const *level, int32_t *const *parent,
+                                   bfs_run_options *opt, void *workspace, hipStream_t s) {
+    const MsLayout L = ms_layout(g->n, nq);
+    char *b = (char *)workspace;
+    MsLevel p{};
+    p.n = g->n;
+    p.W = (uint32_t)(((size_t)nq + 63) / 64);
+    p.nq = (uint32_t)nq;
+    p.out_ptr = g->out_ptr;
+    p.out_idx = g->out_idx;
+    p.in_ptr = g->in_ptr;
+    p.in_idx = g->in_idx;
+    p.vis = (unsigned long long *)(b + L.vis);
+    p.m[0] = (unsigned long long *)(b + L.m0);
+    p.m[1] = (unsigned long long *)(b + L.m1);
+    p.m[2] = (unsigned long long *)(b + L.m2);
+    p.fq[0] = (int32_t *)(b + L.f0);
+    p.fq[1] = (int32_t *)(b + L.f1);
+    p.fq[2] = (int32_t *)(b + L.f2);
+    p.flag = (uint32_t *)(b + L.flag);
+    p.cnt = (uint32_t *)(b + L.cnt);
+    p.level = (int32_t *const *)(b + L.lptr);
+    p.parent = (int32_t *const *)(b + L.pptr);
+    p.sources = (const int32_t *)(b + L.src);
+    HostSlot *hs = nullptr;
+    bfs_status st = host_slot(hs);
+    if (st != BFS_OK) return st;
+    p.host_status = hs->d;
+    HIP_TRY(hipMemcpyAsync(b + L.lptr, level, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b + L.pptr, parent, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b + L.src, sources, (size_t)nq * 4, hipMemcpyHostToDevice, s));
+    uint32_t grid = (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
+    HIP_TRY(launch_ms(p, 0, 0, grid, s));
+    HIP_TRY(launch_ms(p, 1, 0, grid, s));
+    uint32_t k = 0;
+    for (;; ++k) {
+        if ((uint64_t)k > (uint64_t)g->n + 2) return fail(BFS_EHIP, "multi-source loop did not terminate");
+        HIP_TRY(launch_ms(p, 2, k, grid, s));
+        HIP_TRY(launch_ms(p, 3, k, grid, s));
+        bool done = false;
+        uint32_t lv = 0;
+        st = wait_progress(hs, s, done, lv);
+        if (st != BFS_OK) return st;
+        if (done) break;
+    }
+    if (opt) {
+        opt->levels = k + 1;
+        opt->trace_count = 0;
+    }
+    return BFS_OK;
+}
+
 extern "C" bfs_status bfs_run_batch(int32_t num_queries, bfs_graph *const *graphs,
                                     const int32_t *sources, int32_t *const *level,
                                     int32_t *const *parent, bfs_run_options *opt,
                                     void *workspace, size_t ws_bytes, void *hip_stream) {
     if (num_queries <= 0) return fail(BFS_EINVAL, "num_queries = %d", num_queries);
     if (!graphs || !sources || !level || !parent || !workspace) return fail(BFS_EINVAL, "NULL argument");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BFS_EINVAL, "workspace must be 256-byte aligned");
+    bool same = true;
     for (int32_t q = 0; q < num_queries; ++q) {
         if (!graphs[q] || !level[q] || !parent[q]) return fail(BFS_EINVAL, "query %d has a NULL pointer", q);
         if (sources[q] < 0 || sources[q] >= graphs[q]->n)
             return fail(BFS_ERANGE, "query %d: source %d outside [0, %d)", q, sources[q], graphs[q]->n);
+        same = same && graphs[q] == graphs[0];
+    }
+    if (same && num_queries > 1) {
+        const size_t need = bfs_workspace_size(graphs[0], num_queries, 0);
+        if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return run_multi_source(graphs[0], num_queries, sources, level, parent, opt, workspace,
+                                (hipStream_t)hip_stream);
     }
     for (int32_t q = 0; q < num_queries; ++q) {
         const size_t need = bfs_workspace_size(graphs[q], 1, 0);
         if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, query %d needs %zu", ws_bytes, q, need);
+    }
+    for (int32_t q = 0; q < num_queries; ++q) {
         bfs_status st = bfs_run(graphs[q], sources[q], level[q], parent[q], opt, workspace, ws_bytes, hip_stream);
         if (st != BFS_OK) return st;
     }

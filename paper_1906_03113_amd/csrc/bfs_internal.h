@@ -77,6 +77,7 @@ struct LevelParams {
     BfsState *st;
     DevLevelRec *trace;      // kTraceCap records, or nullptr
     const float *mlp;        // selector weights (kMlpTotal floats) or nullptr
+    uint32_t *host_status;   // pinned host memory: [0] level, [1] its frontier size
     uint32_t maintain_fb;
     uint32_t stats;
 };
@@ -86,21 +87,27 @@ struct WsLayout {
 };
 WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor);
 
-// Multi-source (64 sources per 64-bit word) parameters.
-struct MsParams {
+// Multi-source search (64 sources per 64-bit word per vertex).
+struct MsLevel {
     int32_t n;
-    uint32_t words64;        // 64-bit words per vertex mask (= number of 64-source groups)
-    uint32_t nq;             // number of sources
+    uint32_t W;                    // 64-bit words per vertex mask = ceil(nq / 64)
+    uint32_t nq;                   // number of sources
     const int32_t *out_ptr, *out_idx, *in_ptr, *in_idx;
-    unsigned long long *vis;   // [n][words64]: sources that have reached v through level k
-    unsigned long long *cur;   // [n][words64]: sources whose frontier holds v at level k
-    unsigned long long *nxt;   // [n][words64]: sources that reach v at level k+1
-    int32_t *fq[2];            // frontier vertex lists (vertices with any bit in cur)
-    uint32_t *flag;            // [n] per-vertex "already queued for next level" marker
-    uint32_t *cnt;             // [4]: list sizes ring + level
-    int32_t *const *level;     // per-source device outputs (device array of pointers)
+    unsigned long long *vis;       // [n][W]: sources that reached v through level k
+    unsigned long long *m[3];      // [n][W] rotating: level-k frontier masks in m[k % 3]
+    int32_t *fq[3];                // rotating lists of vertices with a nonzero frontier mask
+    uint32_t *flag;                // [n]: last level (+1) a vertex was listed for
+    uint32_t *cnt;                 // list sizes per slot
+    int32_t *const *level;         // device array of nq device pointers
     int32_t *const *parent;
+    const int32_t *sources;        // device, nq
+    uint32_t *host_status;         // pinned host: [0] level, [1] next frontier size
 };
+
+struct MsLayout {
+    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, lptr, pptr, src, total;
+};
+MsLayout ms_layout(int32_t n, int32_t nq);
 
 // launches (bfs_kernels.hip)
 hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *roots_dev,
@@ -110,9 +117,7 @@ hipError_t launch_finish(const LevelParams &p, hipStream_t s);
 hipError_t launch_persistent(const LevelParams &p, uint32_t grid, hipStream_t s);
 uint32_t persistent_max_grid(int device);
 
-hipError_t launch_ms_init(const MsParams &p, const int32_t *sources_dev, hipStream_t s);
-hipError_t launch_ms_level(const MsParams &p, uint32_t k, uint32_t grid, hipStream_t s);
-hipError_t launch_ms_parent(const MsParams &p, uint32_t grid, hipStream_t s);
+hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s);
 
 hipError_t launch_mlp_forward(const float *w, const float *x, float *y, int32_t rows, hipStream_t s);
 hipError_t launch_mlp_train_step(float *w, const float *x, const float *t, const float *mask,

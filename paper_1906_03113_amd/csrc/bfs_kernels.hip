@@ -888,12 +888,23 @@ __global__ __launch_bounds__(kBlock, 8) void k_level(LevelParams P) {
     level_body(P, k, blockIdx.x, gridDim.x);
 }
 
-// One thread closes level k after the level kernel (stream order).
+__device__ __forceinline__ void report(const LevelParams &P) {
+    const BfsState *st = P.st;
+    const uint32_t k = ld_agent(&st->level);
+    P.host_status[0] = k;
+    P.host_status[1] = ld_agent(&st->nf[k & 3]) + (uint32_t)ld_agent64(&st->heavy[k & 3]);
+    __threadfence_system();
+}
+
+// One thread closes level k after the level kernel (stream order) and tells
+// the host where the search stands.
 __global__ void k_finish(LevelParams P) {
+    if (threadIdx.x != 0) return;
     const BfsState *st = P.st;
     const uint32_t k = st->level;
     const uint32_t nf = frontier_size(st, k & 3);
-    if (threadIdx.x == 0 && nf != 0) finish_level(P, k, nf);
+    if (nf != 0) finish_level(P, k, nf);
+    report(P);
 }
 
 // Grid barrier for the cooperative kernel.  Blocks arrive on one of
@@ -953,6 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(LevelParams P) {
         if (blockIdx.x == 0 && threadIdx.x == 0) finish_level(P, k, nf);
         if (!grid_sync(st, nb, &s_ok)) break;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) report(P);
 }
 
 // ---------------------------------------------------------------------------

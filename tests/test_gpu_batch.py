@@ -1,0 +1,72 @@
+"""GPU parity of the batched entry points: many sources on one graph (64 per
+mask word), many graphs per call, and block-diagonal packs searched from one
+root per block.  Every result equals the single-source oracle bit for bit."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests.gpu_common import assert_same, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    return need_gpu()
+
+
+@pytest.mark.parametrize("name,nq", [("er", 1), ("er", 2), ("rmat", 64), ("rmat", 65),
+                                     ("rmatd", 130), ("grid", 63)])
+def test_multi_source_equals_single(P, name, nq):
+    import torch
+    g = {"er": lambda: graphgen.erdos_renyi(5000, 6, 11),
+         "rmat": lambda: graphgen.rmat(13, 16, 12),
+         "rmatd": lambda: graphgen.rmat(12, 16, 13, directed=True),
+         "grid": lambda: graphgen.grid(60, 0.85, 14)}[name]()
+    G = P.Graph.from_graphgen(g)
+    rng = np.random.default_rng(nq)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = rng.choice(cand, size=nq, replace=True)          # duplicates allowed
+    if nq > 2:
+        src[1] = src[0]
+        src[-1] = int(np.nonzero(g.out_degree() == 0)[0][0]) if np.any(g.out_degree() == 0) else src[-1]
+    say(f"[batch] {name} nq={nq}")
+    lv, pa = P.bfs_batch(G, [int(s) for s in src])
+    torch.cuda.synchronize()
+    for q, s in enumerate(src):
+        assert_same(g, int(s), (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/q{q}/s{s}")
+
+
+def test_batch_over_different_graphs(P):
+    import torch
+    gs = [graphgen.erdos_renyi(800 + 37 * i, 4 + i, 20 + i) for i in range(4)]
+    Gs = [P.Graph.from_graphgen(g) for g in gs]
+    srcs = [int(graphgen.pick_sources(g, 1, 3)[0]) for g in gs]
+    say("[batch] 4 different graphs")
+    lv, pa = P.bfs_batch(Gs, srcs)
+    torch.cuda.synchronize()
+    for g, s, l, p in zip(gs, srcs, lv, pa):
+        assert_same(g, s, (l.cpu().numpy(), p.cpu().numpy()), "multi-graph")
+
+
+def test_block_diagonal_uneven_graphs(P):
+    """Uneven ER graphs packed block-diagonally, one root per block, one search."""
+    import torch
+    gs = graphgen.er_family(count=12, lo=6, hi=12)
+    packed, offs = graphgen.block_diagonal(gs)
+    G = P.Graph.from_graphgen(packed)
+    roots = []
+    for b, g in enumerate(gs):
+        nz = np.nonzero(g.out_degree() > 0)[0]
+        roots.append(int(offs[b] + (nz[0] if len(nz) else 0)))
+    for loop in ("host", "persistent"):
+        say(f"[batch] block-diagonal x{len(gs)} loop={loop}")
+        lv, pa = P.bfs_roots(G, roots, loop=loop)
+        torch.cuda.synchronize()
+        lv, pa = lv.cpu().numpy(), pa.cpu().numpy()
+        for b, g in enumerate(gs):
+            o0, o1 = int(offs[b]), int(offs[b + 1])
+            wl, wp = oracle.bfs_graph(g, roots[b] - o0)
+            assert np.array_equal(lv[o0:o1], wl)
+            assert np.array_equal(pa[o0:o1], np.where(wp >= 0, wp + o0, -1))
