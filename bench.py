@@ -72,6 +72,7 @@ def main():
     import graphgen
     import paper_1906_03113_amd as P
 
+    torch.cuda.init()                 # the device context first, before the graph is built
     key, nsrc, sseed, desc = WORKLOADS[args.workload]
     t0 = time.time()
     log(f"[bench] building graph {key} ...")

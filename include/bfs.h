@@ -186,6 +186,63 @@ bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t *roots_host
 /* Workspace bytes for bfs_run_roots with nroots roots (0 on a bad argument). */
 size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots);
 
+/* ------------------------------------------------------------------------
+ * The variant selector.  Not part of the paper: the paper's method is the
+ * push form; these entry points serve the build's per-level choice between
+ * the three equivalent forms of the product.  None of them can change a
+ * search result.
+ *
+ * Weight blob: bfs_selector_param_count() floats, device memory:
+ *   W1[32][12] b1[32] W2[32][32] b2[32] W3[3][32] b3[3] mean[12] inv_std[12]
+ * The network maps the 12 level features (normalised by mean / inv_std) through
+ * two ReLU layers of 32 to 3 predicted log device times (push, pull,
+ * push-bitmap); BFS_VARIANT_LEARNED runs the argmin, push when an output is
+ * not finite.  Features of level k (F = frontier, U = unvisited rows, n, nnz
+ * of the graph): log(1+|F|), log(1+sumdeg F), log(1+|U|), log(1+sumdeg U), k,
+ * nnz/n, log((|F|+1)/n), log((sumdeg F+1)/(nnz+1)), log((|U|+1)/n),
+ * log((sumdeg U+1)/(nnz+1)), log((sumdeg F+1)/(sumdeg U+1)), log((|F|+1)/(|U|+1)).
+ * ------------------------------------------------------------------------ */
+
+/* Floats in a selector weight blob (including the normalisation constants). */
+int32_t bfs_selector_param_count(void);
+
+/* out[rows][3] = network(features[rows][12]); all device pointers. */
+bfs_status bfs_selector_forward(const float *weights, const float *features, float *out,
+                                int32_t rows, void *hip_stream);
+
+/*
+ * Mean-squared-error gradient: loss += inv_norm * sum(mask * (out - targets)^2)
+ * and grad[0 .. param_count-24) += its gradient (weights and biases).
+ * targets and mask are [rows][3]; inv_norm is normally 1 / sum(mask).
+ * grad and loss are device accumulators (the caller zeroes them first).
+ */
+bfs_status bfs_selector_grad(const float *weights, const float *features, const float *targets,
+                             const float *mask, int32_t rows, float inv_norm, float *grad,
+                             float *loss, void *hip_stream);
+
+/* One Adam step (beta 0.9 / 0.999) on the weights and biases; zeroes grad.
+ * m and v are device state of param_count floats, zero before step 1. */
+bfs_status bfs_selector_adam(float *weights, float *grad, float *m, float *v, int32_t step,
+                             float lr, void *hip_stream);
+
+/* Bytes of the snapshot buffer bfs_profile_levels needs (0 on a bad argument). */
+size_t bfs_profile_snapshot_size(const bfs_graph *g);
+
+/*
+ * Exhaustive per-level timing, the selector's training data: runs the search
+ * from `source`; before each level it saves the search state, times that one
+ * level under each of the three forms (push, pull, push-bitmap; best of
+ * `reps` runs, each from the restored state) and then advances with push.
+ * records (host) receives three records per level (variant 0, 1, 2 in that
+ * order, time_us = that level's device time); *count the number written.
+ * level / parent / workspace as for bfs_run; snapshot: device buffer of
+ * bfs_profile_snapshot_size(g) bytes.  The final level / parent equal bfs_run's.
+ */
+bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
+                              void *workspace, size_t ws_bytes, void *snapshot, size_t snap_bytes,
+                              int32_t reps, bfs_level_record *records, uint32_t capacity,
+                              uint32_t *count, void *hip_stream);
+
 /* Static text for a status code. */
 const char *bfs_status_string(bfs_status s);
 

@@ -34,6 +34,14 @@ def _i32_host(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
+def _device_ready():
+    """Bring up torch's device context before the library's first HIP call, so
+    both share one runtime state (torch owns the memory and streams)."""
+    t = _torch()
+    if t.cuda.is_available():
+        t.cuda.init()
+
+
 def _stream_handle(stream):
     t = _torch()
     s = stream if stream is not None else t.cuda.current_stream()
@@ -53,6 +61,7 @@ class Graph:
     def from_csr(cls, n: int, ptr, idx, in_ptr=None, in_idx=None, directed: bool = False,
                  validate_transpose: bool = False) -> "Graph":
         L = _lib.lib()
+        _device_ready()
         ptr_h, idx_h = _i32_host(ptr), _i32_host(idx)
         flags = 0
         ip = ii = None

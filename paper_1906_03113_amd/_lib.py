@@ -77,17 +77,21 @@ def lib():
 
 
 def _optional(L):
-    """Entry points of the selector's kernels (same library)."""
-    vp, i32 = ctypes.c_void_p, ctypes.c_int32
-    if hasattr(L, "bfs_mlp_forward"):
-        L.bfs_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
-        L.bfs_mlp_forward.restype = i32
-        L.bfs_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
-        L.bfs_mlp_grad.restype = i32
-        L.bfs_mlp_sgd_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp]
-        L.bfs_mlp_sgd_step.restype = i32
-        L.bfs_mlp_param_count.argtypes = []
-        L.bfs_mlp_param_count.restype = i32
+    """Entry points of the variant selector (same library)."""
+    vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    L.bfs_selector_param_count.argtypes = []
+    L.bfs_selector_param_count.restype = i32
+    L.bfs_selector_forward.argtypes = [vp, vp, vp, i32, vp]
+    L.bfs_selector_forward.restype = i32
+    L.bfs_selector_grad.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp]
+    L.bfs_selector_grad.restype = i32
+    L.bfs_selector_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
+    L.bfs_selector_adam.restype = i32
+    L.bfs_profile_snapshot_size.argtypes = [vp]
+    L.bfs_profile_snapshot_size.restype = sz
+    L.bfs_profile_levels.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, i32,
+                                     ctypes.POINTER(LevelRecord), u32, ctypes.POINTER(u32), vp]
+    L.bfs_profile_levels.restype = i32
 
 
 def check(status: int) -> None:

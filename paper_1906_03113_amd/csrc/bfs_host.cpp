@@ -697,3 +697,138 @@ extern "C" bfs_status bfs_run_batch(int32_t num_queries, bfs_graph *const *graph
     }
     return BFS_OK;
 }
+
+// ---------------------------------------------------------------------------
+// selector network and its training data
+// ---------------------------------------------------------------------------
+
+extern "C" int32_t bfs_selector_param_count(void) { return kMlpTotal; }
+
+extern "C" bfs_status bfs_selector_forward(const float *weights, const float *features, float *out,
+                                           int32_t rows, void *hip_stream) {
+    if (!weights || !features || !out || rows < 0) return fail(BFS_EINVAL, "bad selector_forward arguments");
+    HIP_TRY(launch_mlp_forward(weights, features, out, rows, (hipStream_t)hip_stream));
+    return BFS_OK;
+}
+
+extern "C" bfs_status bfs_selector_grad(const float *weights, const float *features, const float *targets,
+                                        const float *mask, int32_t rows, float inv_norm, float *grad,
+                                        float *loss, void *hip_stream) {
+    if (!weights || !features || !targets || !mask || !grad || !loss || rows < 0)
+        return fail(BFS_EINVAL, "bad selector_grad arguments");
+    HIP_TRY(launch_mlp_grad(weights, features, targets, mask, rows, inv_norm, grad, loss,
+                            (hipStream_t)hip_stream));
+    return BFS_OK;
+}
+
+extern "C" bfs_status bfs_selector_adam(float *weights, float *grad, float *m, float *v, int32_t step,
+                                        float lr, void *hip_stream) {
+    if (!weights || !grad || !m || !v || step < 1) return fail(BFS_EINVAL, "bad selector_adam arguments");
+    HIP_TRY(launch_mlp_adam(weights, grad, m, v, step, lr, (hipStream_t)hip_stream));
+    return BFS_OK;
+}
+
+extern "C" size_t bfs_profile_snapshot_size(const bfs_graph *g) {
+    if (!g) return 0;
+    return ws_layout(g->n, g->nnz, kHeavyFloor).total + 2 * align256((size_t)g->n * 4);
+}
+
+extern "C" bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
+                                         void *workspace, size_t ws_bytes, void *snapshot,
+                                         size_t snap_bytes, int32_t reps, bfs_level_record *records,
+                                         uint32_t capacity, uint32_t *count, void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (!level || !parent || !workspace || !snapshot || !records || !count)
+        return fail(BFS_EINVAL, "NULL argument");
+    if (source < 0 || source >= g->n) return fail(BFS_ERANGE, "source %d outside [0, %d)", source, g->n);
+    if (((uintptr_t)workspace & 255) != 0 || ((uintptr_t)snapshot & 255) != 0)
+        return fail(BFS_EINVAL, "workspace and snapshot must be 256-byte aligned");
+    const size_t wsz = ws_layout(g->n, g->nnz, kHeavyFloor).total;
+    if (ws_bytes < wsz) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, wsz);
+    if (snap_bytes < bfs_profile_snapshot_size(g)) return fail(BFS_EINVAL, "snapshot too small");
+    if (reps < 1 || reps > 100) return fail(BFS_EINVAL, "reps %d outside [1, 100]", reps);
+    if (!g->in_ptr) return fail(BFS_EINVAL, "pull needs the CSC");
+    hipStream_t s = (hipStream_t)hip_stream;
+    RunCfg c{};
+    bfs_status st = resolve_cfg(g, nullptr, c);
+    if (st != BFS_OK) return st;
+    c.policy = kPush;
+    LevelParams P;
+    make_params(g, level, parent, c, workspace, false, P);
+    P.maintain_fb = 1;
+    P.stats = 1;
+    HostSlot *hs = nullptr;
+    st = host_slot(hs);
+    if (st != BFS_OK) return st;
+    P.host_status = hs->d;
+    char *snap = (char *)snapshot;
+    const size_t nb = (size_t)g->n * 4;
+    char *snap_level = snap + wsz;
+    char *snap_parent = snap_level + align256(nb);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+    } guard{e0, e1};
+    auto save = [&]() -> bfs_status {
+        HIP_TRY(hipMemcpyAsync(snap, workspace, wsz, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(snap_level, level, nb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(snap_parent, parent, nb, hipMemcpyDeviceToDevice, s));
+        return BFS_OK;
+    };
+    auto restore = [&]() -> bfs_status {
+        HIP_TRY(hipMemcpyAsync(workspace, snap, wsz, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(level, snap_level, nb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(parent, snap_parent, nb, hipMemcpyDeviceToDevice, s));
+        return BFS_OK;
+    };
+    HIP_TRY(launch_init(P, 1, nullptr, source, s));
+    BfsState hst;
+    uint32_t n_out = 0;
+    for (uint32_t k = 0;; ++k) {
+        if ((uint64_t)k > (uint64_t)g->n + 2) return fail(BFS_EHIP, "profiling loop did not terminate");
+        HIP_TRY(hipMemcpyAsync(&hst, P.st, sizeof(BfsState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const uint32_t slot = hst.level & 3;
+        const uint32_t nf = hst.nf[slot] + (uint32_t)hst.heavy[slot];
+        if (nf == 0) break;
+        st = save();
+        if (st != BFS_OK) return st;
+        for (uint32_t v = 0; v < 3; ++v) {
+            float best = 1e30f;
+            for (int32_t r = 0; r < reps; ++r) {
+                st = restore();
+                if (st != BFS_OK) return st;
+                LevelParams Pv = P;
+                Pv.policy = v;
+                HIP_TRY(hipEventRecord(e0, s));
+                HIP_TRY(launch_level(Pv, c.grid, s));
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                best = std::min(best, ms * 1000.f);
+            }
+            if (n_out < capacity) {
+                bfs_level_record &o = records[n_out++];
+                o.level = (int32_t)k;
+                o.variant = (int32_t)v;
+                o.frontier = nf;
+                o.unvisited = (uint32_t)g->n - hst.visited_cnt;
+                o.frontier_edges = hst.sdf[slot];
+                o.unvisited_edges = (uint64_t)g->nnz - hst.visited_deg;
+                o.time_us = best;
+                o.reserved = 0.f;
+            }
+        }
+        st = restore();
+        if (st != BFS_OK) return st;
+        HIP_TRY(launch_level(P, c.grid, s));
+        HIP_TRY(launch_finish(P, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    *count = n_out;
+    return BFS_OK;
+}

@@ -120,9 +120,9 @@ uint32_t persistent_max_grid(int device);
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s);
 
 hipError_t launch_mlp_forward(const float *w, const float *x, float *y, int32_t rows, hipStream_t s);
-hipError_t launch_mlp_train_step(float *w, const float *x, const float *t, const float *mask,
-                                 int32_t rows, float lr, float *grad, float *loss, hipStream_t s);
 hipError_t launch_mlp_grad(const float *w, const float *x, const float *t, const float *mask,
-                           int32_t rows, float *grad, float *loss, hipStream_t s);
+                           int32_t rows, float inv_norm, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *w, float *grad, float *m, float *v, int32_t step, float lr,
+                           hipStream_t s);
 
 }  // namespace bfsi

@@ -1,0 +1,280 @@
+"""The per-level variant selector: training data, training, evaluation.
+
+Push, pull and push-bitmap are three evaluations of the same masked product;
+which is fastest depends on the level (a small frontier favours push, a
+frontier holding much of the remaining edges favours pull).  The selector is a
+12 -> 32 -> 32 -> 3 fp32 network that predicts each form's log device time from
+the level's statistics; the level kernel evaluates it on the device and runs
+the argmin.  It can never change a result: every form returns the same bits,
+and push is the fallback for missing or non-finite weights.
+
+Training data come from the method itself: bfs_profile_levels times every
+level under all three forms from the same saved state.  Training runs on the
+GPU through the library's own forward / backward / Adam kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import os
+from typing import Dict, Iterable, List, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+
+N_IN, N_H, N_OUT = 12, 32, 3
+VARIANT_ORDER = ("push", "pull", "bitmap")
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "selector_weights.json")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def param_count() -> int:
+    return int(_lib.lib().bfs_selector_param_count())
+
+
+def n_trainable() -> int:
+    return param_count() - 2 * N_IN
+
+
+def features(frontier, frontier_edges, unvisited, unvisited_edges, level, n, nnz) -> np.ndarray:
+    """The twelve level features (same definitions as the device code), float64 [rows, 12]."""
+    f = np.asarray(frontier, np.float64)
+    sf = np.asarray(frontier_edges, np.float64)
+    u = np.asarray(unvisited, np.float64)
+    su = np.asarray(unvisited_edges, np.float64)
+    k = np.asarray(level, np.float64)
+    n = np.full(f.shape, float(n)) if np.ndim(n) == 0 else np.asarray(n, np.float64)
+    nnz = np.full(f.shape, float(nnz)) if np.ndim(nnz) == 0 else np.asarray(nnz, np.float64)
+    return np.stack([np.log1p(f), np.log1p(sf), np.log1p(u), np.log1p(su), k, nnz / n,
+                     np.log((f + 1) / n), np.log((sf + 1) / (nnz + 1)), np.log((u + 1) / n),
+                     np.log((su + 1) / (nnz + 1)), np.log((sf + 1) / (su + 1)),
+                     np.log((f + 1) / (u + 1))], axis=-1)
+
+
+# ---- training data ------------------------------------------------------------------
+
+def profile(G, source: int, reps: int = 2) -> List[Dict]:
+    """Per-level times of all three forms for one search (see bfs_profile_levels)."""
+    torch = _torch()
+    from . import Workspace
+    L = _lib.lib()
+    level = torch.empty(G.n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(G.n, dtype=torch.int32, device="cuda")
+    ws = Workspace(G.workspace_size(1))
+    snap = Workspace(int(L.bfs_profile_snapshot_size(G.handle)))
+    cap = 3 * 200000
+    recs = (_lib.LevelRecord * cap)()
+    cnt = ctypes.c_uint32(0)
+    s = torch.cuda.current_stream()
+    _lib.check(L.bfs_profile_levels(G.handle, int(source), ctypes.c_void_p(level.data_ptr()),
+                                    ctypes.c_void_p(parent.data_ptr()), ws.ptr, ws.nbytes,
+                                    snap.ptr, snap.nbytes, int(reps), recs, cap, ctypes.byref(cnt),
+                                    ctypes.c_void_p(int(s.cuda_stream))))
+    out: Dict[int, Dict] = {}
+    for i in range(cnt.value):
+        r = recs[i]
+        d = out.setdefault(r.level, dict(level=r.level, frontier=r.frontier, unvisited=r.unvisited,
+                                         frontier_edges=r.frontier_edges,
+                                         unvisited_edges=r.unvisited_edges,
+                                         times=[math.nan] * 3))
+        d["times"][r.variant] = r.time_us
+    return [out[k] for k in sorted(out)]
+
+
+def dataset(levels: Sequence[Dict], n: int, nnz: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(raw features [rows,12], log-time targets [rows,3], mask [rows,3]) from profile records."""
+    if not levels:
+        return np.zeros((0, N_IN)), np.zeros((0, N_OUT)), np.zeros((0, N_OUT))
+    X = features([d["frontier"] for d in levels], [d["frontier_edges"] for d in levels],
+                 [d["unvisited"] for d in levels], [d["unvisited_edges"] for d in levels],
+                 [d["level"] for d in levels], n, nnz)
+    T = np.array([d["times"] for d in levels], dtype=np.float64)
+    M = np.isfinite(T) & (T > 0)
+    T = np.where(M, np.log(np.where(M, T, 1.0)), 0.0)
+    return X, T, M.astype(np.float64)
+
+
+# ---- training on the GPU --------------------------------------------------------------
+
+def init_weights(X: np.ndarray, seed: int = 0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, math.sqrt(2.0 / N_IN), (N_H, N_IN)), np.zeros(N_H),
+             rng.normal(0, math.sqrt(2.0 / N_H), (N_H, N_H)), np.zeros(N_H),
+             rng.normal(0, math.sqrt(1.0 / N_H), (N_OUT, N_H)), np.zeros(N_OUT)]
+    mean = X.mean(0) if len(X) else np.zeros(N_IN)
+    std = X.std(0) if len(X) else np.ones(N_IN)
+    istd = 1.0 / np.where(std > 1e-6, std, 1.0)
+    blob = np.concatenate([p.ravel() for p in parts] + [mean, istd]).astype(np.float32)
+    assert blob.size == param_count()
+    return blob
+
+
+class Trainer:
+    """Device-resident weights, Adam state and data; one call = one full-batch step."""
+
+    def __init__(self, blob: np.ndarray, X: np.ndarray, T: np.ndarray, M: np.ndarray):
+        torch = _torch()
+        self.w = torch.tensor(np.asarray(blob, np.float32), device="cuda")
+        P = param_count()
+        self.grad = torch.zeros(P, dtype=torch.float32, device="cuda")
+        self.m = torch.zeros(P, dtype=torch.float32, device="cuda")
+        self.v = torch.zeros(P, dtype=torch.float32, device="cuda")
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        self.X = torch.tensor(np.asarray(X, np.float32), device="cuda").contiguous()
+        self.T = torch.tensor(np.asarray(T, np.float32), device="cuda").contiguous()
+        self.M = torch.tensor(np.asarray(M, np.float32), device="cuda").contiguous()
+        self.inv = 1.0 / max(1.0, float(np.asarray(M).sum()))
+        self.t = 0
+
+    def _ptr(self, x):
+        return ctypes.c_void_p(x.data_ptr())
+
+    def _stream(self):
+        return ctypes.c_void_p(int(_torch().cuda.current_stream().cuda_stream))
+
+    def gradient(self) -> float:
+        """Accumulate the gradient of the current weights into self.grad; return the loss."""
+        self.loss.zero_()
+        _lib.check(_lib.lib().bfs_selector_grad(self._ptr(self.w), self._ptr(self.X), self._ptr(self.T),
+                                                self._ptr(self.M), int(self.X.shape[0]),
+                                                ctypes.c_float(self.inv), self._ptr(self.grad),
+                                                self._ptr(self.loss), self._stream()))
+        return float(self.loss.item())
+
+    def step(self, lr: float) -> float:
+        loss = self.gradient()
+        self.t += 1
+        _lib.check(_lib.lib().bfs_selector_adam(self._ptr(self.w), self._ptr(self.grad), self._ptr(self.m),
+                                                self._ptr(self.v), self.t, ctypes.c_float(lr),
+                                                self._stream()))
+        return loss
+
+    def weights(self) -> np.ndarray:
+        return self.w.detach().cpu().numpy().copy()
+
+
+def train(X, T, M, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log=None) -> np.ndarray:
+    tr = Trainer(init_weights(np.asarray(X), seed), X, T, M)
+    for i in range(steps):
+        loss = tr.step(lr if i < steps * 2 // 3 else lr * 0.2)
+        if log and (i % max(1, steps // 10) == 0 or i == steps - 1):
+            log(f"[selector] step {i} loss {loss:.5f}")
+    return tr.weights()
+
+
+def predict(blob: np.ndarray, X: np.ndarray) -> np.ndarray:
+    torch = _torch()
+    w = torch.tensor(np.asarray(blob, np.float32), device="cuda")
+    x = torch.tensor(np.asarray(X, np.float32), device="cuda").contiguous()
+    y = torch.empty((x.shape[0], N_OUT), dtype=torch.float32, device="cuda")
+    _lib.check(_lib.lib().bfs_selector_forward(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(y.data_ptr()), int(x.shape[0]),
+                                               ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))))
+    return y.cpu().numpy()
+
+
+def regret(choice: np.ndarray, T: np.ndarray, M: np.ndarray) -> Dict[str, float]:
+    """Sum over levels of (time of the chosen form - best time) / sum of best times;
+    also the push-only total relative to the best."""
+    t = np.where(M > 0, np.exp(T), np.inf)
+    best = t.min(1)
+    chosen = t[np.arange(len(t)), choice]
+    ok = np.isfinite(best)
+    return dict(regret=float((chosen[ok] - best[ok]).sum() / best[ok].sum()),
+                push_regret=float((t[ok, 0] - best[ok]).sum() / best[ok].sum()),
+                chosen_us=float(chosen[ok].sum()), best_us=float(best[ok].sum()),
+                push_us=float(t[ok, 0].sum()))
+
+
+def choose(blob: np.ndarray, X: np.ndarray) -> np.ndarray:
+    y = predict(blob, X)
+    return np.argmin(y, axis=1)
+
+
+def save_weights(path: str, blob: np.ndarray, meta: Dict = None) -> None:
+    with open(path, "w") as f:
+        json.dump({"format": "bfs-selector-mlp-12-32-32-3", "weights": [float(v) for v in blob],
+                   "meta": meta or {}}, f)
+
+
+def load_weights(path: str = DEFAULT_WEIGHTS):
+    """Weights as a cuda float32 tensor, ready for BFS_VARIANT_LEARNED."""
+    torch = _torch()
+    with open(path) as f:
+        d = json.load(f)
+    w = np.asarray(d["weights"], np.float32)
+    if w.size != param_count():
+        raise ValueError(f"{path}: {w.size} weights, expected {param_count()}")
+    return torch.tensor(w, device="cuda")
+
+
+# ---- the training recipe ----------------------------------------------------------------
+
+def training_graphs(include_large: bool = True):
+    """(name, graph builder, sources) for training and held-out evaluation; the
+    graphs are built one at a time when collected."""
+    import graphgen
+    train = [("er16k", lambda: graphgen.workload("er16k"), [0, 1, 2, 3]),
+             ("grid512", lambda: graphgen.grid(512, 0.9, 3), None),
+             ("rmatd16", lambda: graphgen.rmat(16, 16, 1, directed=True), None)]
+    if include_large:
+        train += [("rmat22", lambda: graphgen.workload("rmat22"), None),
+                  ("rmat20d", lambda: graphgen.workload("rmat20d"), None)]
+    held = [(f"rmat{s}", (lambda s=s: graphgen.rmat(s, 16, 1000 + s)), None)
+            for s in (16, 17, 18, 19, 20, 21)]
+    return train, held
+
+
+def collect(entries, per_graph: int = 3, reps: int = 2, log=None):
+    import graphgen
+    from . import Graph
+    Xs, Ts, Ms = [], [], []
+    for name, build, srcs in entries:
+        g = build() if callable(build) else build
+        G = Graph.from_graphgen(g)
+        if srcs is None:
+            srcs = graphgen.pick_sources(g, per_graph, 77)
+        for s in srcs:
+            lv = profile(G, int(s), reps)
+            X, T, M = dataset(lv, g.n, g.nnz)
+            Xs.append(X); Ts.append(T); Ms.append(M)
+            if log:
+                log(f"[selector] {name} s={s}: {len(lv)} levels")
+        G.close()
+    return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Ms)
+
+
+def main(argv=None):
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="collect per-level timings, train the selector, evaluate regret")
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--small", action="store_true", help="skip the scale-22 / scale-20 training graphs")
+    args = ap.parse_args(argv)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    torch = _torch()
+    torch.cuda.init()                 # the device context first, before any CPU-heavy setup
+    train_g, held_g = training_graphs(include_large=not args.small)
+    X, T, M = collect(train_g, log=log)
+    Xh, Th, Mh = collect(held_g, per_graph=2, log=log)
+    log(f"[selector] training rows {len(X)}, held-out rows {len(Xh)}")
+    w = train(X, T, M, steps=args.steps, log=log)
+    res_train = regret(choose(w, X), T, M)
+    res_held = regret(choose(w, Xh), Th, Mh)
+    log(f"[selector] train {res_train}")
+    log(f"[selector] held-out {res_held}")
+    save_weights(args.out, w, {"train": res_train, "held_out": res_held,
+                               "train_rows": int(len(X)), "held_rows": int(len(Xh))})
+    print(json.dumps({"train": res_train, "held_out": res_held}))
+
+
+if __name__ == "__main__":
+    main()
