@@ -58,7 +58,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-time-kernels", action="store_true")
     ap.add_argument("--plain-only", action="store_true")
-    ap.add_argument("--selector", default=None, help="selector weights file (.npz) for the learned form")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=300)
+    ap.add_argument("--selector", default=None,
+                    help="selector weights (JSON); default: the trained weights in the package")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -174,13 +177,12 @@ def main():
     modes = {"plain_push": {"gteps": round(gteps, 3), "ms_per_step": round(dt * 1e3, 4),
                             "variant": args.variant, "loop": args.loop}}
     if not args.plain_only:
-        sel_variant = "learned" if args.selector else "heuristic"
+        from paper_1906_03113_amd import selector as SEL
+        wpath = args.selector or SEL.DEFAULT_WEIGHTS
+        sel_variant = "learned" if os.path.exists(wpath) else "heuristic"
         sel_kw = dict(variant=sel_variant, loop="graph", levels_per_sync=8)
-        selw = None
-        if args.selector:
-            from paper_1906_03113_amd import selector as SEL
-            selw = SEL.load_weights(args.selector)
-            sel_kw["selector"] = selw
+        if sel_variant == "learned":
+            sel_kw["selector"] = SEL.load_weights(wpath)
         for s in sources[:2]:
             P.bfs(G, int(s), level=level, parent=parent, workspace=ws, **sel_kw)
         torch.cuda.synchronize()
@@ -214,6 +216,20 @@ def main():
             del bl, bp, wsb
     best = max(modes, key=lambda m: modes[m]["gteps"])
 
+    serving = None
+    if not args.no_serve and not args.plain_only:
+        # free this workload's buffers before the resident set comes in
+        del ws, level, parent
+        torch.cuda.empty_cache()
+        from paper_1906_03113_amd import serve as SV
+        res = SV.experiment("small", queries=args.serve_queries, rates=(0.5, 0.95), log=log)
+        serving = {"graphs": res["graphs"], "saturation_qps_plain": round(res["saturation_qps_plain"], 1),
+                   "queries_per_rate": args.serve_queries}
+        for frac, r in res["rates"].items():
+            serving[f"{frac}x_sat"] = {
+                k: {"p50_ms": round(v["p50_ms"], 3), "p99_ms": round(v["p99_ms"], 3),
+                    "achieved_qps": round(v["achieved_qps"], 1)} for k, v in r.items()}
+
     out = {
         "metric": "GTEPS on R-MAT s22 (64 sources per step): plain masked push vs the batched / "
                   "variant-selecting forms; value = the best form, every form in config.modes",
@@ -233,6 +249,7 @@ def main():
                    "edges_per_step_m_c": int(total_m), "best_mode": best, "modes": modes},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
