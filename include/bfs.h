@@ -137,7 +137,9 @@ size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_
 /*
  * One search from `source`.  level and parent are device arrays of n int32
  * (caller-owned); workspace is a device buffer of at least
- * bfs_workspace_size(g, 1, 0) bytes, 256-byte aligned.  Nothing is allocated.
+ * bfs_workspace_size(g, 1, 0) bytes, 256-byte aligned.  Nothing is allocated
+ * per call (a host thread's first search allocates a 256-byte pinned host
+ * slot through which the device reports progress; it is kept for the process).
  * Stream-ordered on hip_stream: results are valid when the stream completes;
  * the call itself returns after the last level has been issued (it reads the
  * frontier size back to find the end of the search).  opt may be NULL
