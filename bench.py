@@ -26,6 +26,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_level_rmat22_push_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1906_03113_amd", "csrc", "bfs_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_level launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel source changed since it was measured."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        fields = dict(line.split(": ", 1) for line in txt.splitlines()
+                      if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha1:")))
+        sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if fields.get("kernel_source_sha1", "").strip() != sha:
+            return None
+        return int(float(fields["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -58,6 +76,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-time-kernels", action="store_true")
     ap.add_argument("--plain-only", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=300)
     ap.add_argument("--selector", default=None,
@@ -115,6 +135,15 @@ def main():
             if info_acc is not None:
                 info_acc.append(info)
 
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del a, b
     for w in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -142,8 +171,9 @@ def main():
         avg_bytes = bytes_total / launches
         avg_us = kern_us / launches
         ach = avg_bytes / (avg_us * 1e-6) / 1e9
+        traffic = measured_traffic() if (args.workload == "rmat22" and args.variant == "push") else None
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "k_level", "launches_per_search": round(launches / (len(sources) * args.steps), 2),
                     "mean_launch_us": round(avg_us, 3),
                     "algorithmic_bytes_per_launch": round(avg_bytes),

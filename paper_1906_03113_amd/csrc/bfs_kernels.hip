@@ -127,32 +127,54 @@ __device__ __forceinline__ int mlp_argmin(const float *w, float feat) {
     return ok ? best : -1;
 }
 
-// Called by every thread; wave 0 decides, the block shares through LDS.
-__device__ __forceinline__ uint32_t choose_variant(const LevelParams &P, uint32_t k, uint32_t nf) {
+// The form level k runs, decided once per level by one full wave (all 64
+// lanes call it with the same counters) before the level's launch: the
+// forced form, the edge-ratio rule, or the network's argmin.
+__device__ __forceinline__ uint32_t decide_wave(const LevelParams &P, uint32_t k, float fnf,
+                                                float fsdf, float fnu, float fsdu) {
     if (P.policy == kPush || P.policy == kPull || P.policy == kBitmap) return P.policy;
-    __shared__ uint32_t s_var;
+    uint32_t v = kPush;
+    if (P.policy == kHeuristic) {
+        // pull when the frontier's edges outweigh 1/14 of the unvisited edges
+        if (fsdf * 14.f > fsdu) v = kPull;
+    } else if (P.mlp != nullptr) {
+        const float f = level_feature(lane_id(), fnf, fsdf, fnu, fsdu, (float)k, (float)P.n,
+                                      (float)P.nnz);
+        const int b = mlp_argmin(P.mlp, f);
+        v = (b < 0) ? (uint32_t)kPush : (uint32_t)b;
+        if (v == kBitmap && !P.maintain_fb) v = kPush;
+    }
+    return v;
+}
+
+struct LevelStats {
+    float nf, sdf, nu, sdu;
+};
+
+// The counters of the level about to run, read by one thread (coherent loads).
+__device__ __forceinline__ LevelStats level_stats(const LevelParams &P, uint32_t k) {
+    const BfsState *st = P.st;
+    const uint32_t cs = k & 3;
+    LevelStats L;
+    L.nf = (float)(ld_agent(&st->nf[cs]) + (uint32_t)ld_agent64(&st->heavy[cs]));
+    L.sdf = (float)ld_agent64(&st->sdf[cs]);
+    L.nu = (float)((uint32_t)P.n - ld_agent(&st->visited_cnt));
+    L.sdu = (float)((unsigned long long)P.nnz - ld_agent64(&st->visited_deg));
+    return L;
+}
+
+// One block of one wave: lane 0 reads the counters of level k, the wave
+// decides, lane 0 records the form in the state.
+__device__ __forceinline__ void decide_level(const LevelParams &P, uint32_t k) {
+    __shared__ LevelStats s_ls;
+    if (threadIdx.x == 0) s_ls = level_stats(P, k);
+    __syncthreads();
     if (threadIdx.x < 64) {
-        const BfsState *st = P.st;
-        const uint32_t cs = k & 3;
-        const float fnf = (float)nf;
-        const float fsdf = (float)st->sdf[cs];
-        const float fnu = (float)((uint32_t)P.n - st->visited_cnt);
-        const float fsdu = (float)((unsigned long long)P.nnz - st->visited_deg);
-        uint32_t v = kPush;
-        if (P.policy == kHeuristic) {
-            // pull when the frontier's edges outweigh 1/14 of the unvisited edges
-            if (fsdf * 14.f > fsdu) v = kPull;
-        } else if (P.mlp != nullptr) {
-            const float f = level_feature(lane_id(), fnf, fsdf, fnu, fsdu, (float)k, (float)P.n,
-                                          (float)P.nnz);
-            const int b = mlp_argmin(P.mlp, f);
-            v = (b < 0) ? (uint32_t)kPush : (uint32_t)b;
-            if (v == kBitmap && !P.maintain_fb) v = kPush;
-        }
-        if (threadIdx.x == 0) s_var = v;
+        const LevelStats L = s_ls;
+        const uint32_t v = decide_wave(P, k, L.nf, L.sdf, L.nu, L.sdu);
+        if (threadIdx.x == 0) P.st->variant = v;
     }
     __syncthreads();
-    return s_var;
 }
 
 // ---------------------------------------------------------------------------
@@ -754,11 +776,11 @@ __device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uin
     const uint32_t nreg = st->nf[L.cs];
     const unsigned long long hp = st->heavy[L.cs];
     const uint32_t nlong = (uint32_t)hp, nchunks = (uint32_t)(hp >> 32);
-    const uint32_t v = choose_variant(P, k, nreg + nlong);
+    const uint32_t v = (P.policy == kPush || P.policy == kPull || P.policy == kBitmap)
+                           ? P.policy : st->variant;      // decided before the launch
     if (bid == 0 && threadIdx.x == 0) {
         BfsState *w = P.st;
         const uint32_t fs = (k + 2) & 3;     // slot of level k+2: free since level k-2
-        w->variant = v;
         w->nf[fs] = 0;
         w->heavy[fs] = 0ull;
         w->sdf[fs] = 0ull;
@@ -899,13 +921,17 @@ __device__ __forceinline__ void report(const LevelParams &P) {
 // One thread closes level k after the level kernel (stream order) and tells
 // the host where the search stands.
 __global__ void k_finish(LevelParams P) {
-    if (threadIdx.x != 0) return;
     const BfsState *st = P.st;
     const uint32_t k = st->level;
     const uint32_t nf = frontier_size(st, k & 3);
-    if (nf != 0) finish_level(P, k, nf);
-    report(P);
+    if (threadIdx.x == 0 && nf != 0) finish_level(P, k, nf);
+    __syncthreads();
+    if (nf != 0) decide_level(P, k + 1);     // the form of the next level
+    if (threadIdx.x == 0) report(P);
 }
+
+// The form of level 0 (after the init kernels).
+__global__ void k_decide(LevelParams P) { decide_level(P, 0); }
 
 // Grid barrier for the cooperative kernel.  Blocks arrive on one of
 // kBarGroups counters (block b on group b % kBarGroups, each counter on its own
@@ -961,7 +987,11 @@ __global__ __launch_bounds__(kBlock) void k_persistent(LevelParams P) {
         if (nf == 0) break;
         level_body(P, k, blockIdx.x, nb);
         if (!grid_sync(st, nb, &s_ok)) break;
-        if (blockIdx.x == 0 && threadIdx.x == 0) finish_level(P, k, nf);
+        if (blockIdx.x == 0) {
+            if (threadIdx.x == 0) finish_level(P, k, nf);
+            __syncthreads();
+            decide_level(P, k + 1);
+        }
         if (!grid_sync(st, nb, &s_ok)) break;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) report(P);
@@ -979,10 +1009,18 @@ hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *root
     if (grid == 0) grid = 1;
     hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, s, p, single_root);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || single_root >= 0) return e;
-    const uint32_t g2 = ((uint32_t)nroots + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_init_roots, dim3(g2 ? g2 : 1), dim3(kBlock), 0, s, p, nroots, roots_dev);
-    return hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (single_root < 0) {
+        const uint32_t g2 = ((uint32_t)nroots + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_init_roots, dim3(g2 ? g2 : 1), dim3(kBlock), 0, s, p, nroots, roots_dev);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (p.policy == kLearned || p.policy == kHeuristic) {
+        hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, p);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s) {

@@ -1,0 +1,40 @@
+"""Autotuner host logic on the CPU: candidate pruning, shape keys, the cache."""
+import json
+import types
+
+from paper_1906_03113_amd import autotune as A
+
+
+def _G(n, nnz, directed=False):
+    return types.SimpleNamespace(n=n, nnz=nnz, directed=directed)
+
+
+def test_candidates_include_defaults_and_respect_budget():
+    for levels in (8, 7000):
+        c = A.candidates(levels, budget=10, seed=1)
+        assert len(c) == 10 and c[0]["grid_blocks"] == 0
+        assert all(k in c[1] for k in A.SPACE)
+        if levels > 64:
+            assert all((x["heavy_degree"], x["chunk_edges"]) in ((512, 1024), (0, 0)) for x in c)
+    assert A.candidates(8, 10, seed=1) == A.candidates(8, 10, seed=1)
+
+
+def test_shape_key_buckets():
+    a = A.shape_key(_G(1 << 22, 1 << 27), levels=8)
+    b = A.shape_key(_G((1 << 22) + 1000, (1 << 27) + 5000), levels=9)
+    c = A.shape_key(_G(1 << 22, 1 << 27), levels=5000)
+    d = A.shape_key(_G(1 << 22, 1 << 27, directed=True), levels=8)
+    assert a == b and a != c and a != d
+
+
+def test_store_and_lookup(tmp_path):
+    cache = str(tmp_path / "tune.json")
+    g = _G(1 << 16, 1 << 20)
+    assert A.lookup(g, 10, cache) == {}
+    key = A.shape_key(g, 10)
+    A.store(cache, key, {"params": {"loop": "graph", "grid_blocks": 256}, "time_s": 1.0})
+    assert A.lookup(g, 12, cache) == {"loop": "graph", "grid_blocks": 256}
+    assert A.lookup(_G(1 << 10, 1 << 12), 10, cache) == {}
+    (tmp_path / "bad.json").write_text("{not json")
+    assert A.lookup(g, 10, str(tmp_path / "bad.json")) == {}
+    assert json.load(open(cache))[key]["time_s"] == 1.0

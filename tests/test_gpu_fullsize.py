@@ -1,0 +1,75 @@
+"""Parity at the full workload sizes: R-MAT scale 22 (undirected), the 4096^2
+percolated grid (thousands of levels) and R-MAT scale 20 (directed), each in
+the launch configurations bench.py times.  Whole arrays are compared with the
+oracle (it finishes in about a second per search at these sizes)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import certify
+from tests.gpu_common import need_gpu, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(g, s, got, tag, cert=False):
+    lv, pa = got
+    wl, wp = oracle.bfs_graph(g, int(s))
+    assert np.array_equal(lv, wl), f"{tag}: level differs at {np.count_nonzero(lv != wl)} vertices"
+    assert np.array_equal(pa, wp), f"{tag}: parent differs at {np.count_nonzero(pa != wp)} vertices"
+    if cert:
+        assert certify.check(g.n, g.ptr, g.idx, int(s), lv, pa) == [], tag
+
+
+def test_rmat22():
+    P = need_gpu()
+    from paper_1906_03113_amd import selector as S
+    g = graphgen.workload("rmat22")
+    G = P.Graph.from_graphgen(g)
+    w = S.load_weights()
+    src = graphgen.pick_sources(g, 64, 22)
+    for i, s in enumerate(src[:2]):
+        for kw in (dict(variant="push"), dict(variant="learned", selector=w, loop="graph", levels_per_sync=8),
+                   dict(variant="pull"), dict(variant="bitmap")):
+            say(f"[full] rmat22 s={s} {kw.get('variant')}")
+            _check(g, s, run_gpu(P, G, s, **kw), f"rmat22/{s}/{kw.get('variant')}", cert=(i == 0 and kw["variant"] == "push"))
+
+
+def test_rmat22_batch_of_64():
+    P = need_gpu()
+    import torch
+    g = graphgen.workload("rmat22")
+    G = P.Graph.from_graphgen(g)
+    src = [int(s) for s in graphgen.pick_sources(g, 64, 22)]
+    say("[full] rmat22 multi-source x64")
+    lv, pa = P.bfs_batch(G, src)
+    torch.cuda.synchronize()
+    for q in (0, 17, 63):                     # sampled queries, whole arrays
+        _check(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"rmat22 batch q{q}")
+
+
+def test_grid4096():
+    P = need_gpu()
+    from paper_1906_03113_amd import selector as S
+    g = graphgen.workload("grid4096")
+    G = P.Graph.from_graphgen(g)
+    s = int(graphgen.pick_sources(g, 16, 31)[0])
+    w = S.load_weights()
+    for kw in (dict(variant="push"), dict(variant="learned", selector=w, loop="graph", levels_per_sync=64),
+               dict(variant="push", loop="persistent")):
+        say(f"[full] grid4096 s={s} {kw}")
+        _check(g, s, run_gpu(P, G, s, **{k: v for k, v in kw.items()}), f"grid4096/{kw}")
+
+
+def test_rmat20_directed():
+    P = need_gpu()
+    from paper_1906_03113_amd import selector as S
+    g = graphgen.workload("rmat20d")
+    G = P.Graph.from_graphgen(g)
+    w = S.load_weights()
+    for i, s in enumerate(graphgen.pick_sources(g, 16, 32)[:2]):
+        for kw in (dict(variant="push"), dict(variant="learned", selector=w, loop="graph", levels_per_sync=8),
+                   dict(variant="pull")):
+            say(f"[full] rmat20d s={s} {kw.get('variant')}")
+            _check(g, s, run_gpu(P, G, s, **kw), f"rmat20d/{s}", cert=(i == 0))
