@@ -232,11 +232,13 @@ def main():
             bl = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(nq)]
             bp = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(nq)]
             wsb = P.Workspace(G.workspace_size(nq))
-            P.bfs_batch(G, [int(s) for s in sources], levels=bl, parents=bp, workspace=wsb)
+            P.bfs_batch(G, [int(s) for s in sources], levels=bl, parents=bp, workspace=wsb,
+                        variant="heuristic")
             torch.cuda.synchronize()
             t0b = time.perf_counter()
             for k in range(args.steps):
-                P.bfs_batch(G, [int(s) for s in sources], levels=bl, parents=bp, workspace=wsb)
+                P.bfs_batch(G, [int(s) for s in sources], levels=bl, parents=bp, workspace=wsb,
+                            variant="heuristic")
             torch.cuda.synchronize()
             dtb = (time.perf_counter() - t0b) / args.steps
             modes["batch_multisource"] = {"gteps": round(total_m / dtb / 1e9, 3),

@@ -158,7 +158,11 @@ bfs_status bfs_run(bfs_graph *g, int32_t source,
  * level[q], parent[q] (device, n of that graph each).  When every query names
  * the same graph, the searches advance together, 64 sources per 64-bit mask
  * per vertex (one pass over a column serves every source whose frontier holds
- * it).  Queries on different graphs are run one after another on the stream.
+ * it).  opt->variant picks the direction per level: PUSH (default) scatters
+ * the frontier masks along out-edges; PULL lets every unsettled vertex gather
+ * its in-neighbours' masks in ascending order; HEURISTIC / LEARNED push while
+ * the union frontier holds at most n/32 vertices and pull after.  Queries on
+ * different graphs are run one after another on the stream.
  * The result for query q is bit-identical to bfs_run(graphs[q], sources[q]).
  * workspace: bfs_workspace_size(graphs[0], num_queries, 0) bytes when all
  * graphs are equal; otherwise the largest bfs_workspace_size(graphs[q], 1, 0).

@@ -649,16 +649,27 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     uint32_t grid = (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
     HIP_TRY(launch_ms(p, 0, 0, grid, s));
     HIP_TRY(launch_ms(p, 1, 0, grid, s));
-    uint32_t k = 0;
+    // direction per level: push while the union frontier is small, pull (no
+    // atomics) once it holds more than n / 32 vertices (or as forced)
+    const uint32_t pol = opt ? opt->variant : kPush;
+    uint32_t k = 0, frontier = 1;
     for (;; ++k) {
         if ((uint64_t)k > (uint64_t)g->n + 2) return fail(BFS_EHIP, "multi-source loop did not terminate");
-        HIP_TRY(launch_ms(p, 2, k, grid, s));
-        HIP_TRY(launch_ms(p, 3, k, grid, s));
+        const bool pull = (pol == kPull) || ((pol == kHeuristic || pol == kLearned) &&
+                                             (uint64_t)frontier * 32 > (uint64_t)g->n);
+        if (pull) {
+            HIP_TRY(launch_ms(p, 4, k, grid, s));
+            HIP_TRY(launch_ms(p, 5, k, grid, s));
+        } else {
+            HIP_TRY(launch_ms(p, 2, k, grid, s));
+            HIP_TRY(launch_ms(p, 3, k, grid, s));
+        }
         bool done = false;
         uint32_t lv = 0;
         st = wait_progress(hs, s, done, lv);
         if (st != BFS_OK) return st;
         if (done) break;
+        frontier = hs->h[1];
     }
     if (opt) {
         opt->levels = k + 1;

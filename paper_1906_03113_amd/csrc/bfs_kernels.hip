@@ -610,7 +610,7 @@ __device__ __forceinline__ void bitmap_level(const LevelParams &P, const LevelPt
     }
 }
 
-constexpr uint32_t kPullSerial = 32;     // in-neighbours a lane scans before handing off
+constexpr uint32_t kPullSerial = 4;      // in-neighbours a lane scans before handing off
 
 // w in F_k: the frontier bitmap when it is kept (L2-resident), else level[w] = k
 __device__ __forceinline__ bool in_frontier(const LevelParams &P, const LevelPtrs &L, int32_t w,
@@ -619,9 +619,15 @@ __device__ __forceinline__ bool in_frontier(const LevelParams &P, const LevelPtr
     return P.level[w] == lk;
 }
 
+constexpr uint32_t kPullStep = 8;        // entries per unsettled row per round afterwards
+
 struct PullLds {
-    int32_t lng[kBlock];
-    uint32_t nlong;
+    int32_t lng[kBlock];                  // rows not settled by their first kPullSerial entries
+    int32_t cur[kBlock], end[kBlock];     // their next entry and one past the last
+    int32_t hit[kBlock];                  // smallest frontier in-neighbour found this round
+    uint32_t pre[kBlock + 1];
+    uint32_t wsum[kBlock / 64];
+    uint32_t nlong, nnext;
 };
 
 // Row-wise form over the unvisited list U (or all vertices the first time):
@@ -696,38 +702,86 @@ __device__ __forceinline__ void pull_level(const LevelParams &P, LevelPtrs &L, P
             }
         }
         out_flush(P, L, O, false);
-        const uint32_t nl = S.nlong;
-        for (uint32_t t0 = 0; t0 < nl; t0 += kBlock / 64) {
-            const uint32_t t = t0 + wave;                 // one long row per wave per round
-            int32_t v = -1, hit = -1;
-            bool any = false;
-            if (t < nl) {
-                v = S.lng[t];
-                any = true;
-                const int32_t e1 = P.in_ptr[v + 1];
-                for (int32_t eb = P.in_ptr[v] + (int32_t)kPullSerial; eb < e1; eb += 64) {
-                    const int32_t e = eb + (int32_t)lane;
-                    int32_t w = -1;
-                    bool f = false;
-                    if (e < e1) {
-                        w = P.in_idx[e];
-                        f = in_frontier(P, L, w, lk);
-                    }
-                    const unsigned long long m = __ballot(f);
-                    if (m) {
-                        hit = __shfl(w, __ffsll((long long)m) - 1, 64);
-                        break;
-                    }
+        // Rows still open after their first entries: all of them advance
+        // together, kPullStep entries per row per round, the entries of the
+        // round laid out on one line (prefix scan) and shared by every lane;
+        // the smallest frontier in-neighbour of a row in the first window that
+        // has one is its first in ascending order, i.e. the min-parent.
+        uint32_t nl = S.nlong;
+        if (tid < nl) {
+            const int32_t v = S.lng[tid];
+            S.cur[tid] = P.in_ptr[v] + (int32_t)kPullSerial;
+            S.end[tid] = P.in_ptr[v + 1];
+        }
+        __syncthreads();
+        while (nl > 0) {                               // uniform: nl is read from LDS by all
+            uint32_t cnt = 0;
+            if (tid < nl) {
+                const int32_t r = S.end[tid] - S.cur[tid];
+                cnt = r < (int32_t)kPullStep ? (uint32_t)r : kPullStep;
+                S.hit[tid] = 0x7fffffff;
+            }
+            const uint32_t incl = wave_incl_scan(cnt);
+            if (lane == 63) S.wsum[wave] = incl;
+            __syncthreads();
+            uint32_t woff = 0, total = 0;
+            for (uint32_t w = 0; w < kBlock / 64; ++w) {
+                woff += (w < wave) ? S.wsum[w] : 0u;
+                total += S.wsum[w];
+            }
+            S.pre[tid] = woff + incl - cnt;
+            __syncthreads();
+            uint32_t lo = 0;
+            for (uint32_t e = tid; e < total; e += kBlock) {
+                uint32_t hi = nl - 1;                  // last row slot with pre <= e
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (S.pre[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                const int32_t w = P.in_idx[S.cur[lo] + (int32_t)(e - S.pre[lo])];
+                if (in_frontier(P, L, w, lk)) atomicMin(&S.hit[lo], w);
+            }
+            if (tid == 0) S.nnext = 0;
+            __syncthreads();
+            // settle rows with a hit; rows with entries left go round again
+            bool own = false, keep = false, again = false;
+            int32_t v = -1, h = -1, ncur = 0, nend = 0;
+            if (tid < nl) {
+                v = S.lng[tid];
+                h = S.hit[tid];
+                ncur = S.cur[tid] + (int32_t)cnt;
+                nend = S.end[tid];
+                if (h != 0x7fffffff) {
+                    own = true;
+                    P.parent[v] = (uint32_t)h;
+                    P.level[v] = lk + 1;
+                } else if (ncur < nend) {
+                    again = true;
+                } else {
+                    keep = true;
                 }
             }
-            const bool own = any && (hit >= 0) && lane == 0;
-            if (own) {
-                P.parent[v] = (uint32_t)hit;
-                P.level[v] = lk + 1;
+            __syncthreads();                           // rows are read: compact in place
+            if (again) {
+                const uint32_t slot = atomicAdd(&S.nnext, 1u);
+                S.lng[slot] = v;
+                S.cur[slot] = ncur;
+                S.end[slot] = nend;
             }
-            append_next(P, L, O, own, v);
-            if (any && hit < 0 && lane == 0) O.u[atomicAdd(&O.un, 1u)] = v;
-            out_flush(P, L, O, false);
+            append_next(P, L, O, own, v, true);
+            {
+                const unsigned long long m = __ballot(keep);
+                if (m) {
+                    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
+                    uint32_t base = 0;
+                    if (lane == leader) base = atomicAdd(&O.un, (uint32_t)__popcll(m));
+                    base = __shfl(base, (int)leader, 64);
+                    if (keep) O.u[base + lanes_below(m)] = v;
+                }
+            }
+            out_flush(P, L, O, false);                 // (has a barrier: nnext is final)
+            nl = S.nnext;
+            __syncthreads();
         }
         __syncthreads();
     }
@@ -768,8 +822,12 @@ __device__ __forceinline__ uint32_t frontier_size(const BfsState *st, uint32_t s
 }
 
 __device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uint32_t bid, uint32_t nblocks) {
-    __shared__ TileLds tl;
-    __shared__ PullLds pl;
+    __shared__ union {
+        TileLds t;                            // push / push-bitmap
+        PullLds p;                            // pull
+    } lds;
+    TileLds &tl = lds.t;
+    PullLds &pl = lds.p;
     __shared__ OutLds ol;
     const BfsState *st = P.st;
     LevelPtrs L = level_ptrs(P, k);

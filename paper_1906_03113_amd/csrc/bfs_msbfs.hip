@@ -153,12 +153,94 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
     }
 }
 
+// Level k, pull form (for large frontiers): every vertex v whose sources are
+// not all settled ORs, in ascending in-neighbour order, the frontier masks of
+// its in-neighbours restricted to the sources that have not reached it; each
+// source bit found first at u gets parent u (the smallest frontier
+// in-neighbour for that source) and level k+1.  One thread owns v, so vis and
+// the next mask are written without atomics; vertices with new bits are
+// listed (one atomicAdd per block chunk).  Also clears F_{k-1}'s masks.
+constexpr uint32_t kMsChunk = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
+    __shared__ int32_t s_list[kMsChunk];
+    __shared__ uint32_t s_n, s_base;
+    const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const unsigned long long *cur = s0 == 0 ? p.m[0] : (s0 == 1 ? p.m[1] : p.m[2]);
+    unsigned long long *nxt = s1 == 0 ? p.m[0] : (s1 == 1 ? p.m[1] : p.m[2]);
+    unsigned long long *old = s2 == 0 ? p.m[0] : (s2 == 1 ? p.m[1] : p.m[2]);
+    int32_t *fnxt = s1 == 0 ? p.fq[0] : (s1 == 1 ? p.fq[1] : p.fq[2]);
+    const int32_t *fold = s2 == 0 ? p.fq[0] : (s2 == 1 ? p.fq[1] : p.fq[2]);
+    const uint32_t nold = p.cnt[s2];
+    const uint32_t W = p.W;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t gt = blockIdx.x * kBlock + tid, gs = gridDim.x * kBlock;
+    for (uint32_t t = gt; t < nold * W; t += gs) {
+        const uint32_t u = (uint32_t)fold[t / W];
+        old[(size_t)u * W + (t % W)] = 0ull;
+    }
+    const uint32_t tail = p.nq & 63u;
+    for (uint32_t c0 = blockIdx.x * kMsChunk; c0 < (uint32_t)p.n; c0 += gridDim.x * kMsChunk) {
+        if (tid == 0) s_n = 0;
+        __syncthreads();
+        const uint32_t c1 = (c0 + kMsChunk < (uint32_t)p.n) ? c0 + kMsChunk : (uint32_t)p.n;
+        for (uint32_t vv = c0 + tid; vv < c1; vv += kBlock) {
+            const int32_t v = (int32_t)vv;
+            const int32_t e0 = p.in_ptr[v], e1 = p.in_ptr[v + 1];
+            unsigned long long *vis = row(p.vis, v, W);
+            unsigned long long *nv = row(nxt, v, W);
+            bool any = false;
+            for (uint32_t w = 0; w < W; ++w) {
+                const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+                const unsigned long long sv = vis[w];
+                unsigned long long rem = full & ~sv, found = 0ull;
+                for (int32_t e = e0; e < e1 && rem; ++e) {
+                    const int32_t u = p.in_idx[e];
+                    unsigned long long hit = row(cur, u, W)[w] & rem;
+                    if (!hit) continue;
+                    rem &= ~hit;
+                    found |= hit;
+                    while (hit) {
+                        const uint32_t b = (uint32_t)__ffsll((long long)hit) - 1u;
+                        hit &= hit - 1ull;
+                        const uint32_t q = w * 64u + b;
+                        p.level[q][v] = (int32_t)(k + 1);
+                        p.parent[q][v] = u;
+                    }
+                }
+                nv[w] = found;
+                if (found) {
+                    vis[w] = sv | found;
+                    any = true;
+                }
+            }
+            if (any) s_list[atomicAdd(&s_n, 1u)] = v;
+        }
+        __syncthreads();
+        if (tid == 0 && s_n) s_base = atomicAdd(&p.cnt[s1], s_n);
+        __syncthreads();
+        for (uint32_t i = tid; i < s_n; i += kBlock) fnxt[s_base + i] = s_list[i];
+        __syncthreads();
+    }
+}
+
+// After a pull level: the list of level k+2 starts empty; report to the host.
+__global__ void k_ms_report(MsLevel p, uint32_t k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    p.cnt[(k + 2) % 3] = 0u;
+    p.host_status[0] = k + 1;
+    p.host_status[1] = p.cnt[(k + 1) % 3];
+    __threadfence_system();
+}
+
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s) {
     switch (phase) {
         case 0: hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kBlock), 0, s, p); break;
         case 1: hipLaunchKernelGGL(k_ms_roots, dim3((p.nq + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p); break;
         case 2: hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kBlock), 0, s, p, k); break;
-        default: hipLaunchKernelGGL(k_ms_settle, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        case 3: hipLaunchKernelGGL(k_ms_settle, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        case 4: hipLaunchKernelGGL(k_ms_pull, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        default: hipLaunchKernelGGL(k_ms_report, dim3(1), dim3(64), 0, s, p, k); break;
     }
     return hipGetLastError();
 }

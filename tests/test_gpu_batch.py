@@ -16,9 +16,10 @@ def P():
     return need_gpu()
 
 
+@pytest.mark.parametrize("variant", ["push", "pull", "heuristic"])
 @pytest.mark.parametrize("name,nq", [("er", 1), ("er", 2), ("rmat", 64), ("rmat", 65),
                                      ("rmatd", 130), ("grid", 63)])
-def test_multi_source_equals_single(P, name, nq):
+def test_multi_source_equals_single(P, name, nq, variant):
     import torch
     g = {"er": lambda: graphgen.erdos_renyi(5000, 6, 11),
          "rmat": lambda: graphgen.rmat(13, 16, 12),
@@ -31,8 +32,8 @@ def test_multi_source_equals_single(P, name, nq):
     if nq > 2:
         src[1] = src[0]
         src[-1] = int(np.nonzero(g.out_degree() == 0)[0][0]) if np.any(g.out_degree() == 0) else src[-1]
-    say(f"[batch] {name} nq={nq}")
-    lv, pa = P.bfs_batch(G, [int(s) for s in src])
+    say(f"[batch] {name} nq={nq} {variant}")
+    lv, pa = P.bfs_batch(G, [int(s) for s in src], variant=variant)
     torch.cuda.synchronize()
     for q, s in enumerate(src):
         assert_same(g, int(s), (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/q{q}/s{s}")
