@@ -130,8 +130,8 @@ __device__ __forceinline__ int mlp_argmin(const float *w, float feat) {
 // The form level k runs, decided once per level by one full wave (all 64
 // lanes call it with the same counters) before the level's launch: the
 // forced form, the edge-ratio rule, or the network's argmin.
-__device__ __forceinline__ uint32_t decide_wave(const LevelParams &P, uint32_t k, float fnf,
-                                                float fsdf, float fnu, float fsdu) {
+__device__ __forceinline__ uint32_t decide_wave(const LevelParams &P, const float *w, uint32_t k,
+                                                float fnf, float fsdf, float fnu, float fsdu) {
     if (P.policy == kPush || P.policy == kPull || P.policy == kBitmap) return P.policy;
     uint32_t v = kPush;
     if (P.policy == kHeuristic) {
@@ -140,7 +140,7 @@ __device__ __forceinline__ uint32_t decide_wave(const LevelParams &P, uint32_t k
     } else if (P.mlp != nullptr) {
         const float f = level_feature(lane_id(), fnf, fsdf, fnu, fsdu, (float)k, (float)P.n,
                                       (float)P.nnz);
-        const int b = mlp_argmin(P.mlp, f);
+        const int b = mlp_argmin(w, f);
         v = (b < 0) ? (uint32_t)kPush : (uint32_t)b;
         if (v == kBitmap && !P.maintain_fb) v = kPush;
     }
@@ -165,13 +165,19 @@ __device__ __forceinline__ LevelStats level_stats(const LevelParams &P, uint32_t
 
 // One block of one wave: lane 0 reads the counters of level k, the wave
 // decides, lane 0 records the form in the state.
+// The network's weights are first staged in LDS with coalesced loads (its
+// evaluation then reads LDS only).
 __device__ __forceinline__ void decide_level(const LevelParams &P, uint32_t k) {
     __shared__ LevelStats s_ls;
+    __shared__ float s_w[kMlpTotal];
+    const bool net = (P.policy == kLearned) && P.mlp != nullptr;
     if (threadIdx.x == 0) s_ls = level_stats(P, k);
+    if (net && threadIdx.x < 64)
+        for (uint32_t i = threadIdx.x; i < (uint32_t)kMlpTotal; i += 64) s_w[i] = P.mlp[i];
     __syncthreads();
     if (threadIdx.x < 64) {
         const LevelStats L = s_ls;
-        const uint32_t v = decide_wave(P, k, L.nf, L.sdf, L.nu, L.sdu);
+        const uint32_t v = decide_wave(P, s_w, k, L.nf, L.sdf, L.nu, L.sdu);
         if (threadIdx.x == 0) P.st->variant = v;
     }
     __syncthreads();

@@ -155,7 +155,8 @@ class GpuExecutor:
     """Runs batches on resident graphs through the library (one stream per worker)."""
 
     def __init__(self, graphs: Dict[str, object], mode: str = "batched", selector=None,
-                 multi_source_max_n: int = 1 << 20, keep_results: bool = False):
+                 multi_source_max_n: int = 1 << 20, keep_results: bool = False,
+                 params: Optional[Dict[str, Dict]] = None):
         import torch
         import paper_1906_03113_amd as P
         self.P = P
@@ -165,6 +166,7 @@ class GpuExecutor:
         self.selector = selector
         self.ms_max_n = multi_source_max_n
         self.keep = keep_results
+        self.params = params or {}             # per-graph launch parameters (autotuned)
         self.local = threading.local()
 
     def footprint(self, gname: str, nq: int) -> int:
@@ -191,6 +193,7 @@ class GpuExecutor:
             else:
                 kw = dict(variant="learned", selector=self.selector) if self.selector is not None \
                     else dict(variant="heuristic")
+                kw.update(self.params.get(b.graph, {}))
                 outs = [P.bfs(G, src, stream=s, **kw) for src in srcs]
             s.synchronize()
         for q, o in zip(b.queries, outs):
@@ -310,6 +313,25 @@ def resident_set(which: str = "small"):
     return out
 
 
+def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector) -> Dict[str, Dict]:
+    """Per-graph launch parameters for the serving path: the autotuner's cached
+    choice for the graph's shape if there is one, else by diameter class - deep
+    graphs read the frontier size back every 64 levels instead of every 4."""
+    import paper_1906_03113_amd as P
+    from . import autotune as AT
+    out = {}
+    for name, G in Gs.items():
+        info = {}
+        P.bfs(G, int(srcs[name][0]), variant="learned", selector=selector, info=info)
+        levels = int(info["levels"])
+        kw = AT.lookup(G, levels)
+        kw.pop("loop", None)                   # serving keeps the host loop (no per-query capture)
+        if levels > 64:
+            kw.setdefault("levels_per_sync", 64)
+        out[name] = kw
+    return out
+
+
 def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers=4, seed=5,
                log=None, budget_bytes=64 << 30):
     """Plain (push only, one query at a time) vs batched + learned at fixed
@@ -329,8 +351,9 @@ def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers
         del g
     names = sorted(Gs)
     sel = S.load_weights()
+    params = launch_params(Gs, srcs, sel)
     plain = GpuExecutor(Gs, mode="plain")
-    fast = GpuExecutor(Gs, mode="batched", selector=sel)
+    fast = GpuExecutor(Gs, mode="batched", selector=sel, params=params)
     # saturation of the plain path: back-to-back queries, one worker
     rng = np.random.default_rng(seed)
     warm = [Query(i, names[int(rng.integers(len(names)))], 0, 0.0) for i in range(len(names))]
