@@ -286,7 +286,14 @@ def run_load(executor: GpuExecutor, graph_names: Sequence[str], sources: Dict[st
     st = latency_stats(qs)
     st.update(rate_qps=rate_qps, queries=count, wall_s=wall, achieved_qps=count / wall,
               peak_inflight_mb=srv.sched.peak_bytes / 1e6)
+    fams = sorted({family(q.graph) for q in qs})
+    st["by_family"] = {f: latency_stats([q for q in qs if family(q.graph) == f]) for f in fams}
     return st
+
+
+def family(name: str) -> str:
+    """Graph family of a resident graph's name ("rmat20_1" -> "rmat20")."""
+    return name.split("_")[0]
 
 
 # ---- the serving experiment ---------------------------------------------------------------
@@ -380,6 +387,10 @@ def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers
             log(f"[serve] {frac:.2f} x sat ({rate:.1f} q/s): plain p50 {r_plain['p50_ms']:.2f} ms "
                 f"p99 {r_plain['p99_ms']:.2f} ms | batched+learned p50 {r_fast['p50_ms']:.2f} ms "
                 f"p99 {r_fast['p99_ms']:.2f} ms")
+            for f in r_plain["by_family"]:
+                a, b = r_plain["by_family"][f], r_fast["by_family"][f]
+                log(f"[serve]    {f:9s} n={a['completed']:4d} plain p50 {a['p50_ms']:8.2f} p99 {a['p99_ms']:8.2f}"
+                    f" | batched+learned p50 {b['p50_ms']:8.2f} p99 {b['p99_ms']:8.2f}")
     for G in Gs.values():
         G.close()
     return res
