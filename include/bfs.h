@@ -204,7 +204,7 @@ size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots);
  * two ReLU layers of 32 to 3 predicted log device times (push, pull,
  * push-bitmap); BFS_VARIANT_LEARNED runs the argmin, push when an output is
  * not finite.  Features of level k (F = frontier, U = unvisited rows, n, nnz
- * of the graph): log(1+|F|), log(1+sumdeg F), log(1+|U|), log(1+sumdeg U), k,
+ * of the graph): log(1+|F|), log(1+sumdeg F), log(1+|U|), log(1+sumdeg U), log(1+k),
  * nnz/n, log((|F|+1)/n), log((sumdeg F+1)/(nnz+1)), log((|U|+1)/n),
  * log((sumdeg U+1)/(nnz+1)), log((sumdeg F+1)/(sumdeg U+1)), log((|F|+1)/(|U|+1)).
  * ------------------------------------------------------------------------ */

@@ -14,7 +14,7 @@ central finite differences.
 
 Level features (the selector's input), from the level's frontier F, the
 unvisited remainder U, the level k and the graph's n and nnz:
-  log(1+|F|), log(1+sumdeg F), log(1+|U|), log(1+sumdeg U), k, nnz/n,
+  log(1+|F|), log(1+sumdeg F), log(1+|U|), log(1+sumdeg U), log(1+k), nnz/n,
   log((|F|+1)/n), log((sumdeg F+1)/(nnz+1)), log((|U|+1)/n),
   log((sumdeg U+1)/(nnz+1)), log((sumdeg F+1)/(sumdeg U+1)), log((|F|+1)/(|U|+1))
 """
@@ -49,7 +49,7 @@ def features(frontier, frontier_edges, unvisited, unvisited_edges, level, n, nnz
     k = np.asarray(level, np.float64)
     n = np.broadcast_to(np.asarray(n, np.float64), f.shape)
     nnz = np.broadcast_to(np.asarray(nnz, np.float64), f.shape)
-    cols = [np.log1p(f), np.log1p(sf), np.log1p(u), np.log1p(su), k, nnz / n,
+    cols = [np.log1p(f), np.log1p(sf), np.log1p(u), np.log1p(su), np.log1p(k), nnz / n,
             np.log((f + 1) / n), np.log((sf + 1) / (nnz + 1)), np.log((u + 1) / n),
             np.log((su + 1) / (nnz + 1)), np.log((sf + 1) / (su + 1)), np.log((f + 1) / (u + 1))]
     return np.stack(cols, axis=-1)

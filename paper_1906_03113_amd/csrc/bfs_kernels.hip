@@ -81,7 +81,7 @@ __device__ __forceinline__ float level_feature(uint32_t i, float nf, float sdf, 
         case 1: return logf(1.f + sdf);
         case 2: return logf(1.f + nu);
         case 3: return logf(1.f + sdu);
-        case 4: return k;
+        case 4: return logf(1.f + k);
         case 5: return nnz / n;
         case 6: return logf((nf + 1.f) / n);
         case 7: return logf((sdf + 1.f) / (nnz + 1.f));

@@ -52,7 +52,7 @@ def features(frontier, frontier_edges, unvisited, unvisited_edges, level, n, nnz
     k = np.asarray(level, np.float64)
     n = np.full(f.shape, float(n)) if np.ndim(n) == 0 else np.asarray(n, np.float64)
     nnz = np.full(f.shape, float(nnz)) if np.ndim(nnz) == 0 else np.asarray(nnz, np.float64)
-    return np.stack([np.log1p(f), np.log1p(sf), np.log1p(u), np.log1p(su), k, nnz / n,
+    return np.stack([np.log1p(f), np.log1p(sf), np.log1p(u), np.log1p(su), np.log1p(k), nnz / n,
                      np.log((f + 1) / n), np.log((sf + 1) / (nnz + 1)), np.log((u + 1) / n),
                      np.log((su + 1) / (nnz + 1)), np.log((sf + 1) / (su + 1)),
                      np.log((f + 1) / (u + 1))], axis=-1)
@@ -218,21 +218,38 @@ def load_weights(path: str = DEFAULT_WEIGHTS):
 # ---- the training recipe ----------------------------------------------------------------
 
 def training_graphs(include_large: bool = True):
-    """(name, graph builder, sources) for training and held-out evaluation; the
-    graphs are built one at a time when collected."""
+    """(name, graph builder, sources) for training, and the held-out groups: R-MAT
+    graphs of scales never trained on, and a 4096^2 grid (16.8 M vertices, a
+    depth and size beyond every training graph).  Graphs are built one at a
+    time when collected."""
     import graphgen
     train = [("er16k", lambda: graphgen.workload("er16k"), [0, 1, 2, 3]),
              ("grid512", lambda: graphgen.grid(512, 0.9, 3), None),
              ("rmatd16", lambda: graphgen.rmat(16, 16, 1, directed=True), None)]
     if include_large:
         train += [("rmat22", lambda: graphgen.workload("rmat22"), None),
-                  ("rmat20d", lambda: graphgen.workload("rmat20d"), None)]
-    held = [(f"rmat{s}", (lambda s=s: graphgen.rmat(s, 16, 1000 + s)), None)
-            for s in (16, 17, 18, 19, 20, 21)]
+                  ("rmat20d", lambda: graphgen.workload("rmat20d"), None),
+                  ("grid1024", lambda: graphgen.grid(1024, 0.9, 5), [None, None]),
+                  ("grid2048", lambda: graphgen.grid(2048, 0.9, 6), [None])]
+    held = {"rmat": [(f"rmat{s}", (lambda s=s: graphgen.rmat(s, 16, 1000 + s)), None)
+                     for s in (16, 17, 18, 19, 20, 21)]}
+    if include_large:
+        held["grid4096"] = [("grid4096", lambda: graphgen.grid(4096, 0.9, 9), [None])]
     return train, held
 
 
-def collect(entries, per_graph: int = 3, reps: int = 2, log=None):
+def _spread(levels: List[Dict], cap: int) -> List[Dict]:
+    """At most `cap` of a search's levels, evenly spaced (first and last kept), so
+    that a search thousands of levels deep does not outweigh the shallow ones."""
+    if cap <= 0 or len(levels) <= cap:
+        return levels
+    keep = np.unique(np.linspace(0, len(levels) - 1, cap).round().astype(np.int64))
+    return [levels[i] for i in keep]
+
+
+def collect(entries, per_graph: int = 3, reps: int = 2, log=None, cap: int = 0):
+    """Profile every search of `entries`; a source list entry of None means a
+    seeded pick.  `cap` > 0 keeps at most that many levels of each search."""
     import graphgen
     from . import Graph
     Xs, Ts, Ms = [], [], []
@@ -241,13 +258,16 @@ def collect(entries, per_graph: int = 3, reps: int = 2, log=None):
         G = Graph.from_graphgen(g)
         if srcs is None:
             srcs = graphgen.pick_sources(g, per_graph, 77)
+        elif any(x is None for x in srcs):
+            srcs = graphgen.pick_sources(g, len(srcs), 78)
         for s in srcs:
             lv = profile(G, int(s), reps)
-            X, T, M = dataset(lv, g.n, g.nnz)
+            X, T, M = dataset(_spread(lv, cap), g.n, g.nnz)
             Xs.append(X); Ts.append(T); Ms.append(M)
             if log:
-                log(f"[selector] {name} s={s}: {len(lv)} levels")
+                log(f"[selector] {name} s={s}: {len(lv)} levels, {len(X)} rows")
         G.close()
+        del g
     return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Ms)
 
 
@@ -257,22 +277,30 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="collect per-level timings, train the selector, evaluate regret")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--small", action="store_true", help="skip the scale-22 / scale-20 training graphs")
+    ap.add_argument("--small", action="store_true", help="skip the large training graphs")
+    ap.add_argument("--cap", type=int, default=300, help="levels kept per training search")
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch = _torch()
     torch.cuda.init()                 # the device context first, before any CPU-heavy setup
     train_g, held_g = training_graphs(include_large=not args.small)
-    X, T, M = collect(train_g, log=log)
-    Xh, Th, Mh = collect(held_g, per_graph=2, log=log)
-    log(f"[selector] training rows {len(X)}, held-out rows {len(Xh)}")
+    X, T, M = collect(train_g, log=log, cap=args.cap)
+    held = {k: collect(v, per_graph=2, log=log) for k, v in held_g.items()}
+    log(f"[selector] training rows {len(X)}, held-out rows "
+        f"{ {k: len(v[0]) for k, v in held.items()} }")
     w = train(X, T, M, steps=args.steps, log=log)
     res_train = regret(choose(w, X), T, M)
-    res_held = regret(choose(w, Xh), Th, Mh)
+    res_held = {k: regret(choose(w, Xh), Th, Mh) for k, (Xh, Th, Mh) in held.items()}
     log(f"[selector] train {res_train}")
-    log(f"[selector] held-out {res_held}")
-    save_weights(args.out, w, {"train": res_train, "held_out": res_held,
-                               "train_rows": int(len(X)), "held_rows": int(len(Xh))})
+    for k, r in res_held.items():
+        log(f"[selector] held-out {k}: {r}")
+    meta = {"train": res_train, "held_out": res_held.get("rmat"),
+            "train_rows": int(len(X)), "held_rows": {k: int(len(v[0])) for k, v in held.items()},
+            "features": "log1p(k) level feature"}
+    for k, r in res_held.items():
+        if k != "rmat":
+            meta[f"held_out_{k}"] = r
+    save_weights(args.out, w, meta)
     print(json.dumps({"train": res_train, "held_out": res_held}))
 
 

@@ -71,7 +71,7 @@ def test_identity_network():
 def test_features_definition():
     f = mlp_ref.features(frontier=[9], frontier_edges=[99], unvisited=[49], unvisited_edges=[999],
                          level=[3], n=100, nnz=1000)[0]
-    want = [np.log(10), np.log(100), np.log(50), np.log(1000), 3, 10.0,
+    want = [np.log(10), np.log(100), np.log(50), np.log(1000), np.log(4), 10.0,
             np.log(0.1), np.log(100 / 1001), np.log(0.5), np.log(1000 / 1001),
             np.log(100 / 1000), np.log(10 / 50)]
     assert np.allclose(f, want)
