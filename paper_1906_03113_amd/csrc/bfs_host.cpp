@@ -154,9 +154,13 @@ WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor) {
 }  // namespace bfsi
 
 namespace bfsi {
-MsLayout ms_layout(int32_t n, int32_t nq) {
+MsLayout ms_layout(int32_t n, uint32_t nnz, int32_t nq) {
     MsLayout L{};
     const size_t W = ((size_t)nq + 63) / 64;
+    // split entries: at most nnz / kMsLong vertices reach the degree, and their
+    // chunks number at most nnz / kMsChunk plus one partial chunk each
+    L.nlong_max = std::min<size_t>((size_t)n, (size_t)nnz / kMsLong) + 1;
+    L.nchunk_max = (size_t)nnz / kMsChunk + L.nlong_max + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.vis = take((size_t)n * W * 8);
@@ -168,6 +172,13 @@ MsLayout ms_layout(int32_t n, int32_t nq) {
     L.f2 = take((size_t)n * 4);
     L.flag = take((size_t)n * 4);
     L.cnt = take(64);
+    L.lcnt = take(64);
+    for (int i = 0; i < 3; ++i) {
+        L.pl[i] = take(L.nlong_max * sizeof(MsLong));
+        L.sl[i] = take(L.nlong_max * sizeof(MsLong));
+        L.pmap[i] = take(L.nchunk_max * 4);
+        L.smap[i] = take(L.nchunk_max * 4);
+    }
     L.lptr = take((size_t)nq * 8);
     L.pptr = take((size_t)nq * 8);
     L.src = take((size_t)nq * 4);
@@ -543,7 +554,7 @@ size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_
     if (!g || num_queries <= 0 || run_flags != 0) return 0;
     const size_t single = ws_layout(g->n, g->nnz, kHeavyFloor).total;
     if (num_queries == 1) return single;
-    return std::max(single, ms_layout(g->n, num_queries).total);
+    return std::max(single, ms_layout(g->n, g->nnz, num_queries).total);
 }
 
 bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
@@ -617,7 +628,7 @@ extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
 static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sources,
                                    int32_t *const *level, int32_t *const *parent,
                                    bfs_run_options *opt, void *workspace, hipStream_t s) {
-    const MsLayout L = ms_layout(g->n, nq);
+    const MsLayout L = ms_layout(g->n, g->nnz, nq);
     char *b = (char *)workspace;
     MsLevel p{};
     p.n = g->n;
@@ -636,6 +647,13 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     p.fq[2] = (int32_t *)(b + L.f2);
     p.flag = (uint32_t *)(b + L.flag);
     p.cnt = (uint32_t *)(b + L.cnt);
+    p.lcnt = (unsigned long long *)(b + L.lcnt);
+    for (int i = 0; i < 3; ++i) {
+        p.pl[i] = (MsLong *)(b + L.pl[i]);
+        p.sl[i] = (MsLong *)(b + L.sl[i]);
+        p.pmap[i] = (uint32_t *)(b + L.pmap[i]);
+        p.smap[i] = (uint32_t *)(b + L.smap[i]);
+    }
     p.level = (int32_t *const *)(b + L.lptr);
     p.parent = (int32_t *const *)(b + L.pptr);
     p.sources = (const int32_t *)(b + L.src);

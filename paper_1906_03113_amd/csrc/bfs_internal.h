@@ -88,6 +88,16 @@ struct WsLayout {
 WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor);
 
 // Multi-source search (64 sources per 64-bit word per vertex).
+constexpr uint32_t kMsLong = 512;      // degree from which a multi-source list entry is split
+constexpr uint32_t kMsChunk = 512;     // entries per chunk of a split entry
+
+// A split entry of a multi-source work list: the vertex and the id of its
+// first chunk (chunks of one list are numbered consecutively in entry order).
+struct MsLong {
+    int32_t v;
+    uint32_t chunk_base;
+};
+
 struct MsLevel {
     int32_t n;
     uint32_t W;                    // 64-bit words per vertex mask = ceil(nq / 64)
@@ -98,6 +108,12 @@ struct MsLevel {
     int32_t *fq[3];                // rotating lists of vertices with a nonzero frontier mask
     uint32_t *flag;                // [n]: last level (+1) a vertex was listed for
     uint32_t *cnt;                 // list sizes per slot
+    // split entries per slot: pl = frontier columns with out-degree >= kMsLong
+    // (the push form's chunks), sl = newly listed vertices with in-degree >=
+    // kMsLong (the settle pass's chunks); counts packed (entries | chunks << 32)
+    MsLong *pl[3], *sl[3];
+    uint32_t *pmap[3], *smap[3];   // chunk id -> entry index
+    unsigned long long *lcnt;      // [0..2] pl, [3..5] sl
     int32_t *const *level;         // device array of nq device pointers
     int32_t *const *parent;
     const int32_t *sources;        // device, nq
@@ -105,9 +121,11 @@ struct MsLevel {
 };
 
 struct MsLayout {
-    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, lptr, pptr, src, total;
+    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, lcnt, pl[3], sl[3], pmap[3], smap[3],
+        lptr, pptr, src, total;
+    size_t nlong_max, nchunk_max;
 };
-MsLayout ms_layout(int32_t n, int32_t nq);
+MsLayout ms_layout(int32_t n, uint32_t nnz, int32_t nq);
 
 // launches (bfs_kernels.hip)
 hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *roots_dev,

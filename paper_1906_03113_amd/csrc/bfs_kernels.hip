@@ -626,6 +626,25 @@ __device__ __forceinline__ bool in_frontier(const LevelParams &P, const LevelPtr
 }
 
 constexpr uint32_t kPullStep = 8;        // entries per unsettled row per round afterwards
+constexpr uint32_t kRoundIlp = 4;        // entries a lane tests at once in those rounds
+static_assert(kPullSerial == 4, "first_hit4 covers the serial window");
+
+// The first in-neighbour, in ascending order, among in_idx[e0, e0 + cnt)
+// (1 <= cnt <= 4) that is in F_k, else -1.  The window's index loads are all
+// issued before the first frontier test, and the tests before the first use,
+// so a row costs two memory latencies instead of up to eight; positions past
+// cnt repeat the last entry, which cannot change the first hit.
+__device__ __forceinline__ int32_t first_hit4(const LevelParams &P, const LevelPtrs &L, int32_t e0,
+                                              int32_t cnt, int32_t lk) {
+    const int32_t last = e0 + cnt - 1;
+    const int32_t w0 = P.in_idx[e0];
+    const int32_t w1 = P.in_idx[e0 + 1 < last ? e0 + 1 : last];
+    const int32_t w2 = P.in_idx[e0 + 2 < last ? e0 + 2 : last];
+    const int32_t w3 = P.in_idx[last < e0 + 3 ? last : e0 + 3];
+    const bool h0 = in_frontier(P, L, w0, lk), h1 = in_frontier(P, L, w1, lk);
+    const bool h2 = in_frontier(P, L, w2, lk), h3 = in_frontier(P, L, w3, lk);
+    return h0 ? w0 : (h1 ? w1 : (h2 ? w2 : (h3 ? w3 : -1)));
+}
 
 struct PullLds {
     int32_t lng[kBlock];                  // rows not settled by their first kPullSerial entries
@@ -671,15 +690,14 @@ __device__ __forceinline__ void pull_level(const LevelParams &P, LevelPtrs &L, P
         bool keep = false;
         if (pos < len) {
             u = all ? (int32_t)pos : U[pos];
-            if (!((L.vb_cur[(uint32_t)u >> 5] >> (u & 31)) & 1u)) {
-                const int32_t e0 = P.in_ptr[u], e1 = P.in_ptr[u + 1];
+            // the mask word and the row bounds are loaded together
+            const uint32_t mw = L.vb_cur[(uint32_t)u >> 5];
+            const int32_t e0 = P.in_ptr[u], e1 = P.in_ptr[u + 1];
+            if (!((mw >> (u & 31)) & 1u)) {
                 ue0 = e0;
                 ue1 = e1;
                 const int32_t lim = (e1 - e0 > (int32_t)kPullSerial) ? e0 + (int32_t)kPullSerial : e1;
-                for (int32_t e = e0; e < lim; ++e) {
-                    const int32_t w = P.in_idx[e];
-                    if (in_frontier(P, L, w, lk)) { found = w; break; }
-                }
+                if (lim > e0) found = first_hit4(P, L, e0, lim - e0, lk);
                 if (found < 0) {
                     if (lim < e1) {
                         const uint32_t slot = atomicAdd(&S.nlong, 1u);
@@ -737,15 +755,29 @@ __device__ __forceinline__ void pull_level(const LevelParams &P, LevelPtrs &L, P
             }
             S.pre[tid] = woff + incl - cnt;
             __syncthreads();
+            // up to kRoundIlp entries per lane per pass, all loads issued first
             uint32_t lo = 0;
-            for (uint32_t e = tid; e < total; e += kBlock) {
-                uint32_t hi = nl - 1;                  // last row slot with pre <= e
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (S.pre[mid] <= e) lo = mid; else hi = mid - 1;
+            for (uint32_t e = tid; e < total; e += kRoundIlp * kBlock) {
+                uint32_t slot[kRoundIlp];
+                int32_t w[kRoundIlp];
+#pragma unroll
+                for (uint32_t t = 0; t < kRoundIlp; ++t) {
+                    const uint32_t et = e + t * kBlock;
+                    const uint32_t ec = et < total ? et : total - 1u;   // in range, ignored below
+                    uint32_t hi = nl - 1;              // last row slot with pre <= ec
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (S.pre[mid] <= ec) lo = mid; else hi = mid - 1;
+                    }
+                    slot[t] = lo;
+                    w[t] = P.in_idx[S.cur[lo] + (int32_t)(ec - S.pre[lo])];
                 }
-                const int32_t w = P.in_idx[S.cur[lo] + (int32_t)(e - S.pre[lo])];
-                if (in_frontier(P, L, w, lk)) atomicMin(&S.hit[lo], w);
+                bool h[kRoundIlp];
+#pragma unroll
+                for (uint32_t t = 0; t < kRoundIlp; ++t) h[t] = in_frontier(P, L, w[t], lk);
+#pragma unroll
+                for (uint32_t t = 0; t < kRoundIlp; ++t)
+                    if (h[t] && e + t * kBlock < total) atomicMin(&S.hit[slot[t]], w[t]);
             }
             if (tid == 0) S.nnext = 0;
             __syncthreads();
