@@ -37,6 +37,11 @@ struct bfs_graph {
     int cus = 0;
     int32_t *out_ptr = nullptr, *out_idx = nullptr, *in_ptr = nullptr, *in_idx = nullptr;
     size_t bytes = 0;
+    // split entries for the multi-source kernels (see MsLevel): long columns
+    // and long rows; for an undirected graph the two are the same arrays
+    bfsi::MsLong *lo = nullptr, *li = nullptr;
+    uint32_t *lomap = nullptr, *limap = nullptr;
+    uint32_t nlo = 0, nlo_chunks = 0, nli = 0, nli_chunks = 0;
     std::mutex mu;
     GraphExecCache gcache;
     std::vector<hipEvent_t> events;   // pool for per-launch timing
@@ -112,11 +117,35 @@ void free_graph(bfs_graph *g) {
     for (hipEvent_t e : g->events) hipEventDestroy(e);
     if (g->gcache.exec) hipGraphExecDestroy(g->gcache.exec);
     if (g->gcache.graph) hipGraphDestroy(g->gcache.graph);
+    if (g->li && g->li != g->lo) hipFree(g->li);
+    if (g->limap && g->limap != g->lomap) hipFree(g->limap);
+    if (g->lo) hipFree(g->lo);
+    if (g->lomap) hipFree(g->lomap);
     if (g->in_ptr && g->in_ptr != g->out_ptr) hipFree(g->in_ptr);
     if (g->in_idx && g->in_idx != g->out_idx) hipFree(g->in_idx);
     if (g->out_ptr) hipFree(g->out_ptr);
     if (g->out_idx) hipFree(g->out_idx);
     delete g;
+}
+
+// Entries of ptr with at least kMsLong positions, each split into chunks of
+// kMsChunk numbered consecutively; uploads the entries and chunk -> entry map.
+bfs_status build_long(int32_t n, const std::vector<int32_t> &ptr, bfsi::MsLong **ents, uint32_t **map,
+                      uint32_t &count, uint32_t &chunks, size_t &bytes) {
+    std::vector<bfsi::MsLong> e;
+    std::vector<uint32_t> m;
+    for (int32_t v = 0; v < n; ++v) {
+        const uint32_t deg = (uint32_t)(ptr[v + 1] - ptr[v]);
+        if (deg < bfsi::kMsLong) continue;
+        e.push_back(bfsi::MsLong{v, (uint32_t)m.size()});
+        const uint32_t nch = (deg + bfsi::kMsChunk - 1) / bfsi::kMsChunk;
+        for (uint32_t c = 0; c < nch; ++c) m.push_back((uint32_t)(e.size() - 1));
+    }
+    count = (uint32_t)e.size();
+    chunks = (uint32_t)m.size();
+    bfs_status st = upload(ents, e.data(), e.size(), bytes);
+    if (st == BFS_OK) st = upload(map, m.data(), m.size(), bytes);
+    return st;
 }
 
 }  // namespace
@@ -154,13 +183,9 @@ WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor) {
 }  // namespace bfsi
 
 namespace bfsi {
-MsLayout ms_layout(int32_t n, uint32_t nnz, int32_t nq) {
+MsLayout ms_layout(int32_t n, int32_t nq) {
     MsLayout L{};
     const size_t W = ((size_t)nq + 63) / 64;
-    // split entries: at most nnz / kMsLong vertices reach the degree, and their
-    // chunks number at most nnz / kMsChunk plus one partial chunk each
-    L.nlong_max = std::min<size_t>((size_t)n, (size_t)nnz / kMsLong) + 1;
-    L.nchunk_max = (size_t)nnz / kMsChunk + L.nlong_max + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.vis = take((size_t)n * W * 8);
@@ -172,13 +197,8 @@ MsLayout ms_layout(int32_t n, uint32_t nnz, int32_t nq) {
     L.f2 = take((size_t)n * 4);
     L.flag = take((size_t)n * 4);
     L.cnt = take(64);
-    L.lcnt = take(64);
-    for (int i = 0; i < 3; ++i) {
-        L.pl[i] = take(L.nlong_max * sizeof(MsLong));
-        L.sl[i] = take(L.nlong_max * sizeof(MsLong));
-        L.pmap[i] = take(L.nchunk_max * 4);
-        L.smap[i] = take(L.nchunk_max * 4);
-    }
+    L.slev = take((size_t)n * W * 64 * 4);
+    L.spar = take((size_t)n * W * 64 * 4);
     L.lptr = take((size_t)nq * 8);
     L.pptr = take((size_t)nq * 8);
     L.src = take((size_t)nq * 4);
@@ -525,6 +545,19 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
         g->in_ptr = g->out_ptr;
         g->in_idx = g->out_idx;
     }
+    try {
+        if (st == BFS_OK) st = build_long(n, ptr, &g->lo, &g->lomap, g->nlo, g->nlo_chunks, g->bytes);
+        if (st == BFS_OK && directed) {
+            st = build_long(n, iptr, &g->li, &g->limap, g->nli, g->nli_chunks, g->bytes);
+        } else if (st == BFS_OK) {
+            g->li = g->lo;
+            g->limap = g->lomap;
+            g->nli = g->nlo;
+            g->nli_chunks = g->nlo_chunks;
+        }
+    } catch (const std::bad_alloc &) {
+        st = fail(BFS_ENOMEM, "host allocation failed");
+    }
     if (st != BFS_OK) {
         std::string keep = g_detail;
         free_graph(g);
@@ -554,7 +587,7 @@ size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_
     if (!g || num_queries <= 0 || run_flags != 0) return 0;
     const size_t single = ws_layout(g->n, g->nnz, kHeavyFloor).total;
     if (num_queries == 1) return single;
-    return std::max(single, ms_layout(g->n, g->nnz, num_queries).total);
+    return std::max(single, ms_layout(g->n, num_queries).total);
 }
 
 bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
@@ -628,7 +661,7 @@ extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
 static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sources,
                                    int32_t *const *level, int32_t *const *parent,
                                    bfs_run_options *opt, void *workspace, hipStream_t s) {
-    const MsLayout L = ms_layout(g->n, g->nnz, nq);
+    const MsLayout L = ms_layout(g->n, nq);
     char *b = (char *)workspace;
     MsLevel p{};
     p.n = g->n;
@@ -647,13 +680,15 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     p.fq[2] = (int32_t *)(b + L.f2);
     p.flag = (uint32_t *)(b + L.flag);
     p.cnt = (uint32_t *)(b + L.cnt);
-    p.lcnt = (unsigned long long *)(b + L.lcnt);
-    for (int i = 0; i < 3; ++i) {
-        p.pl[i] = (MsLong *)(b + L.pl[i]);
-        p.sl[i] = (MsLong *)(b + L.sl[i]);
-        p.pmap[i] = (uint32_t *)(b + L.pmap[i]);
-        p.smap[i] = (uint32_t *)(b + L.smap[i]);
-    }
+    p.lo = g->lo;
+    p.li = g->li;
+    p.lomap = g->lomap;
+    p.limap = g->limap;
+    p.nlo_chunks = g->nlo_chunks;
+    p.nli = g->nli;
+    p.nli_chunks = g->nli_chunks;
+    p.slev = (int32_t *)(b + L.slev);
+    p.spar = (uint32_t *)(b + L.spar);
     p.level = (int32_t *const *)(b + L.lptr);
     p.parent = (int32_t *const *)(b + L.pptr);
     p.sources = (const int32_t *)(b + L.src);
@@ -677,6 +712,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
                                              (uint64_t)frontier * 32 > (uint64_t)g->n);
         if (pull) {
             HIP_TRY(launch_ms(p, 4, k, grid, s));
+            HIP_TRY(launch_ms(p, 6, k, grid, s));
             HIP_TRY(launch_ms(p, 5, k, grid, s));
         } else {
             HIP_TRY(launch_ms(p, 2, k, grid, s));
@@ -689,6 +725,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
         if (done) break;
         frontier = hs->h[1];
     }
+    HIP_TRY(launch_ms(p, 7, k, grid, s));      // staged results -> per-source arrays
     if (opt) {
         opt->levels = k + 1;
         opt->trace_count = 0;

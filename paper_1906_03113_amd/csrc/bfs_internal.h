@@ -108,12 +108,18 @@ struct MsLevel {
     int32_t *fq[3];                // rotating lists of vertices with a nonzero frontier mask
     uint32_t *flag;                // [n]: last level (+1) a vertex was listed for
     uint32_t *cnt;                 // list sizes per slot
-    // split entries per slot: pl = frontier columns with out-degree >= kMsLong
-    // (the push form's chunks), sl = newly listed vertices with in-degree >=
-    // kMsLong (the settle pass's chunks); counts packed (entries | chunks << 32)
-    MsLong *pl[3], *sl[3];
-    uint32_t *pmap[3], *smap[3];   // chunk id -> entry index
-    unsigned long long *lcnt;      // [0..2] pl, [3..5] sl
+    // the graph's split entries (fixed per graph, built at creation): columns
+    // with out-degree >= kMsLong (the push form's chunks) and rows with
+    // in-degree >= kMsLong (the settle and pull chunks); chunk id -> entry
+    const MsLong *lo, *li;
+    const uint32_t *lomap, *limap;
+    uint32_t nlo_chunks, nli, nli_chunks;
+    // results staged vertex-major while the search runs, [n][W * 64]: row v
+    // holds every source's level / parent of v (valid where vis has the bit),
+    // so the writes of one row share its 256-byte lines; k_ms_out transposes
+    // them into the callers' per-source arrays at the end
+    int32_t *slev;
+    uint32_t *spar;
     int32_t *const *level;         // device array of nq device pointers
     int32_t *const *parent;
     const int32_t *sources;        // device, nq
@@ -121,11 +127,9 @@ struct MsLevel {
 };
 
 struct MsLayout {
-    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, lcnt, pl[3], sl[3], pmap[3], smap[3],
-        lptr, pptr, src, total;
-    size_t nlong_max, nchunk_max;
+    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, slev, spar, lptr, pptr, src, total;
 };
-MsLayout ms_layout(int32_t n, uint32_t nnz, int32_t nq);
+MsLayout ms_layout(int32_t n, int32_t nq);
 
 // launches (bfs_kernels.hip)
 hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *roots_dev,

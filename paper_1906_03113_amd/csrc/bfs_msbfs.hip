@@ -58,18 +58,8 @@ __device__ __forceinline__ unsigned long long wave_or_incl(unsigned long long x,
     return x;
 }
 
-// Append vertex v with `deg` entries to a split list: one packed atomic gives
-// its entry index and first chunk id; its chunks map back to the entry.
-__device__ __forceinline__ void add_long(MsLong *ents, uint32_t *map, unsigned long long *ctr, int32_t v,
-                                         uint32_t deg) {
-    const uint32_t nch = (deg + kMsChunk - 1u) / kMsChunk;
-    const unsigned long long old = atomicAdd(ctr, 1ull | ((unsigned long long)nch << 32));
-    const uint32_t idx = (uint32_t)old, base = (uint32_t)(old >> 32);
-    MsLong e;
-    e.v = v;
-    e.chunk_base = base;
-    ents[idx] = e;
-    for (uint32_t c = 0; c < nch; ++c) map[base + c] = idx;
+__device__ __forceinline__ size_t stage(const MsLevel &p, int32_t v, uint32_t q) {
+    return (size_t)v * (p.W * 64u) + q;
 }
 
 // One step of the settle scan over in_idx[eb + lane] (lanes past e1 hold
@@ -96,16 +86,20 @@ __device__ __forceinline__ unsigned long long settle_step(const MsLevel &p, cons
         const uint32_t b = (uint32_t)__ffsll((long long)own) - 1u;
         own &= own - 1ull;
         const uint32_t q = w * 64u + b;
-        p.level[q][v] = (int32_t)lk;
-        if (owner_alone) p.parent[q][v] = u;
-        else atomicMin((uint32_t *)&p.parent[q][v], (uint32_t)u);
+        const size_t at = stage(p, v, q);
+        p.slev[at] = (int32_t)lk;
+        if (owner_alone) p.spar[at] = (uint32_t)u;
+        else atomicMin(&p.spar[at], (uint32_t)u);
     }
     return __shfl(incl, 63, 64);
 }
 
 }  // namespace
 
-// Outputs to -1 (every source, every vertex) and every mask to zero.
+// Every mask to zero; the staged parents of rows with long in-lists (the only
+// ones combined with atomicMin) to 0xFFFFFFFF.  Other staged entries are
+// written before they are read (k_ms_out reads only entries whose vis bit is
+// set), and k_ms_out writes every output.
 __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
     const size_t gid = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kBlock;
@@ -116,43 +110,41 @@ __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
         p.m[1][i] = 0ull;
         p.m[2][i] = 0ull;
     }
-    for (size_t v = gid; v < (size_t)p.n; v += stride) p.flag[v] = 0u;
-    const size_t tot = (size_t)p.n * p.nq;
-    for (size_t i = gid; i < tot; i += stride) {
-        const uint32_t q = (uint32_t)(i / (size_t)p.n);
-        const size_t v = i - (size_t)q * p.n;
-        p.level[q][v] = -1;
-        p.parent[q][v] = -1;
+    const uint32_t S = p.W * 64u;
+    for (size_t v = gid; v < (size_t)p.n; v += stride) {
+        p.flag[v] = 0u;
+        if ((uint32_t)(p.in_ptr[v + 1] - p.in_ptr[v]) >= kMsLong)
+            for (uint32_t q = 0; q < S; ++q) p.spar[v * S + q] = 0xFFFFFFFFu;
     }
     if (gid < 4) p.cnt[gid] = 0u;
-    if (gid < 6) p.lcnt[gid] = 0ull;
 }
 
 // Sources: bit q set in cur and vis of its vertex, level 0, parent itself; each
-// distinct source vertex enters the level-0 list once (and the split list of
-// long columns when its out-degree is long).
+// distinct source vertex enters the level-0 list once.
 __global__ __launch_bounds__(kBlock) void k_ms_roots(MsLevel p) {
-    const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= p.nq) return;
-    const int32_t s = p.sources[q];
-    const unsigned long long bit = 1ull << (q & 63);
-    atomicOr(&row(p.m[0], s, p.W)[q >> 6], bit);
-    atomicOr(&row(p.vis, s, p.W)[q >> 6], bit);
-    p.level[q][s] = 0;
-    p.parent[q][s] = s;
-    if (atomicMax(&p.flag[s], 1u) < 1u) {
-        p.fq[0][atomicAdd(&p.cnt[0], 1u)] = s;
-        const uint32_t od = (uint32_t)(p.out_ptr[s + 1] - p.out_ptr[s]);
-        if (od >= kMsLong) add_long(p.pl[0], p.pmap[0], &p.lcnt[0], s, od);
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
+    for (uint32_t q = gid; q < p.nq; q += gs) {
+        const int32_t s = p.sources[q];
+        const unsigned long long bit = 1ull << (q & 63);
+        atomicOr(&row(p.m[0], s, p.W)[q >> 6], bit);
+        atomicOr(&row(p.vis, s, p.W)[q >> 6], bit);
+        p.slev[stage(p, s, q)] = 0;
+        p.spar[stage(p, s, q)] = (uint32_t)s;
+        if (atomicMax(&p.flag[s], 1u) < 1u) p.fq[0][atomicAdd(&p.cnt[0], 1u)] = s;
     }
 }
 
 // Level k, push half.  Work items, one wave each: the frontier columns with
 // fewer than kMsLong entries (lanes over the entries), then the chunks of the
-// long ones.  Per entry (u, v): new = cur[u] & ~vis[v] is ORed into nxt[v], and
-// v is listed for level k+1 once (and split for the settle pass when its
-// in-list is long).  Also clears the masks of F_{k-1} (slot (k+2) % 3).
+// graph's long columns, skipped unless the column is in some frontier.  Per
+// entry (u, v): new = cur[u] & ~vis[v] is ORed into nxt[v], and v is listed
+// for level k+1 once, through a per-wave LDS buffer flushed with one atomic
+// per kMsFlush entries.  Also clears the masks of F_{k-1} (slot (k+2) % 3).
+constexpr uint32_t kMsWaveBuf = 256;
+constexpr uint32_t kMsFlush = kMsWaveBuf - 64;
+
 __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
+    __shared__ int32_t s_buf[kBlock / 64][kMsWaveBuf];
     const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
     const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s0);
     unsigned long long *nxt = pick3(p.m[0], p.m[1], p.m[2], s1);
@@ -160,13 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
     const int32_t *fcur = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s0);
     int32_t *fnxt = pick3(p.fq[0], p.fq[1], p.fq[2], s1);
     const int32_t *fold = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s2);
-    const MsLong *lcur = pick3<const MsLong *>(p.pl[0], p.pl[1], p.pl[2], s0);
-    const uint32_t *lmap = pick3<const uint32_t *>(p.pmap[0], p.pmap[1], p.pmap[2], s0);
-    MsLong *snew = pick3(p.sl[0], p.sl[1], p.sl[2], s1);
-    uint32_t *smap = pick3(p.smap[0], p.smap[1], p.smap[2], s1);
-    unsigned long long *sctr = p.lcnt + 3 + s1;
     const uint32_t ncur = p.cnt[s0], nold = p.cnt[s2];
-    const uint32_t nchunks = (uint32_t)(p.lcnt[s0] >> 32);
     const uint32_t W = p.W;
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     for (uint32_t t = gt; t < nold * W; t += gs) {
@@ -174,10 +160,19 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
         old[(size_t)u * W + (t % W)] = 0ull;
     }
     const uint32_t lane = __lane_id();
-    const uint32_t wave = gt >> 6;
-    const uint32_t nwaves = gs >> 6;
-    const uint32_t tag = k + 2;          // "listed for level k+1"
-    for (uint32_t it = wave; it < ncur + nchunks; it += nwaves) {
+    int32_t *buf = s_buf[threadIdx.x >> 6];
+    uint32_t nbuf = 0;                    // the same in every lane
+    const uint32_t tag = k + 2;           // "listed for level k+1"
+    auto flush = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&p.cnt[s1], nbuf);
+        base = __shfl(base, 0, 64);
+        for (uint32_t i = lane; i < nbuf; i += 64) fnxt[base + i] = buf[i];
+        __builtin_amdgcn_wave_barrier();
+        nbuf = 0;
+    };
+    for (uint32_t it = gt >> 6; it < ncur + p.nlo_chunks; it += gs >> 6) {
         int32_t u, e0, e1;
         if (it < ncur) {
             u = fcur[it];
@@ -186,79 +181,78 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
             if ((uint32_t)(e1 - e0) >= kMsLong) continue;        // done by its chunks
         } else {
             const uint32_t c = it - ncur;
-            const MsLong L = lcur[lmap[c]];
+            const MsLong L = p.lo[p.lomap[c]];
             u = L.v;
+            bool in_f = false;
+            for (uint32_t w = 0; w < W; ++w) in_f = in_f || row(cur, u, W)[w] != 0ull;
+            if (!in_f) continue;
             const int32_t r1 = p.out_ptr[u + 1];
             e0 = p.out_ptr[u] + (int32_t)((c - L.chunk_base) * kMsChunk);
             e1 = (e0 + (int32_t)kMsChunk < r1) ? e0 + (int32_t)kMsChunk : r1;
         }
         const unsigned long long *cu = row(cur, u, W);
-        for (int32_t e = e0 + (int32_t)lane; e < e1; e += 64) {
-            const int32_t v = p.out_idx[e];
-            const unsigned long long *vv = row(p.vis, v, W);
-            unsigned long long *nv = row(nxt, v, W);
-            bool any = false;
-            for (uint32_t w = 0; w < W; ++w) {
-                const unsigned long long nb = cu[w] & ~vv[w];
-                if (nb) {
-                    atomicOr(&nv[w], nb);
-                    any = true;
+        for (int32_t eb = e0; eb < e1; eb += 64) {       // uniform: whole waves step together
+            const int32_t e = eb + (int32_t)lane;
+            bool listed = false;
+            int32_t v = -1;
+            if (e < e1) {
+                v = p.out_idx[e];
+                const unsigned long long *vv = row(p.vis, v, W);
+                unsigned long long *nv = row(nxt, v, W);
+                if (W == 1) {
+                    // the lane whose OR turns nxt[v] nonzero lists v; a pre-read
+                    // (possibly stale: bits are only ever added) skips ORs that
+                    // would add nothing
+                    const unsigned long long nb = cu[0] & ~vv[0];
+                    if (nb && (nb & ~nv[0])) listed = atomicOr(&nv[0], nb) == 0ull;
+                } else {
+                    bool any = false;
+                    for (uint32_t w = 0; w < W; ++w) {
+                        const unsigned long long nb = cu[w] & ~vv[w];
+                        if (nb) {
+                            atomicOr(&nv[w], nb);
+                            any = true;
+                        }
+                    }
+                    listed = any && atomicMax(&p.flag[v], tag) < tag;
                 }
             }
-            const bool listed = any && atomicMax(&p.flag[v], tag) < tag;
             const unsigned long long bm = __ballot(listed);
             if (bm) {
-                const uint32_t leader = (uint32_t)__ffsll((long long)bm) - 1u;
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(&p.cnt[s1], (uint32_t)__popcll(bm));
-                base = __shfl(base, (int)leader, 64);
-                if (listed) {
-                    fnxt[base + lanes_below(bm)] = v;
-                    const uint32_t id = (uint32_t)(p.in_ptr[v + 1] - p.in_ptr[v]);
-                    if (id >= kMsLong) add_long(snew, smap, sctr, v, id);
-                }
+                if (listed) buf[nbuf + lanes_below(bm)] = v;
+                nbuf += (uint32_t)__popcll(bm);
+                if (nbuf > kMsFlush) flush();
             }
         }
     }
+    if (nbuf) flush();
 }
 
 // Level k, settle half: one wave per newly listed vertex v with a short
-// in-list, one wave per chunk of a long one.  The new bits join vis (by the
-// vertex's own item); each gets level k+1 and its parent = the first
-// in-neighbour (ascending) whose level-k frontier mask holds it.  Every
-// listed vertex with a long out-list is split for the next push.
+// in-list, then one wave per chunk of the graph's long rows (skipped unless
+// the row has new bits).  The new bits join vis (by the listed vertex's own
+// item); each gets level k+1 and its parent = the first in-neighbour
+// (ascending) whose level-k frontier mask holds it.
 __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
     const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
     const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s0);
     const unsigned long long *nxt = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s1);
     const int32_t *fnxt = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s1);
-    const MsLong *lst = pick3<const MsLong *>(p.sl[0], p.sl[1], p.sl[2], s1);
-    const uint32_t *lmap = pick3<const uint32_t *>(p.smap[0], p.smap[1], p.smap[2], s1);
-    MsLong *pnew = pick3(p.pl[0], p.pl[1], p.pl[2], s1);
-    uint32_t *pmap = pick3(p.pmap[0], p.pmap[1], p.pmap[2], s1);
-    unsigned long long *pctr = p.lcnt + s1;
     const uint32_t nnext = p.cnt[s1];
-    const uint32_t nchunks = (uint32_t)(p.lcnt[3 + s1] >> 32);
     const uint32_t W = p.W;
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     const uint32_t lane = __lane_id();
     if (gt == 0) {
-        p.cnt[s2] = 0u;                       // the lists of level k+2 start empty
-        p.lcnt[s2] = 0ull;
-        p.lcnt[3 + s2] = 0ull;
+        p.cnt[s2] = 0u;                       // the list of level k+2 starts empty
         p.host_status[0] = k + 1;
         p.host_status[1] = nnext;
         __threadfence_system();
     }
-    for (uint32_t it = gt >> 6; it < nnext + nchunks; it += gs >> 6) {
+    for (uint32_t it = gt >> 6; it < nnext + p.nli_chunks; it += gs >> 6) {
         int32_t v, e0, e1;
         bool alone;
         if (it < nnext) {
             v = fnxt[it];
-            if (lane == 0) {
-                const uint32_t od = (uint32_t)(p.out_ptr[v + 1] - p.out_ptr[v]);
-                if (od >= kMsLong) add_long(pnew, pmap, pctr, v, od);
-            }
             e0 = p.in_ptr[v];
             e1 = p.in_ptr[v + 1];
             if ((uint32_t)(e1 - e0) >= kMsLong) {      // parents by the chunks
@@ -268,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
             alone = true;
         } else {
             const uint32_t c = it - nnext;
-            const MsLong L = lst[lmap[c]];
+            const MsLong L = p.li[p.limap[c]];
             v = L.v;
             const int32_t r1 = p.in_ptr[v + 1];
             e0 = p.in_ptr[v] + (int32_t)((c - L.chunk_base) * kMsChunk);
@@ -291,10 +285,13 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
 // its in-neighbours restricted to the sources that have not reached it; each
 // source bit found first at u gets parent u (the smallest frontier
 // in-neighbour for that source) and level k+1.  Rows of up to kMsSerial
-// entries are scanned by one lane, longer ones by a wave (settle_step).  The
-// owner of v writes vis and the next mask without atomics; vertices with new
-// bits are listed (one atomicAdd per block chunk) and split for the next push
-// when their out-list is long.  Also clears F_{k-1}'s masks.
+// entries are scanned by one lane, longer ones by a wave (settle_step); the
+// owner of such a row writes vis and the next mask without atomics, and rows
+// with new bits are listed (one atomicAdd per block chunk).  The graph's long
+// rows (kMsLong entries or more) are scanned in chunks by waves across the
+// grid: each chunk gives its first hits (atomicMin on the staged parent) and
+// ORs its bits into the next mask; k_ms_fixup then folds those into vis and
+// lists the rows.  Also clears F_{k-1}'s masks.
 constexpr uint32_t kMsRows = 2048;       // rows per block chunk
 constexpr int32_t kMsSerial = 16;        // longest row one lane scans alone
 
@@ -308,9 +305,6 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
     unsigned long long *old = pick3(p.m[0], p.m[1], p.m[2], s2);
     int32_t *fnxt = pick3(p.fq[0], p.fq[1], p.fq[2], s1);
     const int32_t *fold = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s2);
-    MsLong *pnew = pick3(p.pl[0], p.pl[1], p.pl[2], s1);
-    uint32_t *pmap = pick3(p.pmap[0], p.pmap[1], p.pmap[2], s1);
-    unsigned long long *pctr = p.lcnt + s1;
     const uint32_t nold = p.cnt[s2];
     const uint32_t W = p.W;
     const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
@@ -331,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
         for (uint32_t vv = c0 + tid; vv < c1; vv += kBlock) {
             const int32_t v = (int32_t)vv;
             const int32_t e0 = p.in_ptr[v], e1 = p.in_ptr[v + 1];
-            if (e1 == e0) continue;
+            if (e1 == e0 || (uint32_t)(e1 - e0) >= kMsLong) continue;     // long rows: chunks below
             unsigned long long *vis = row(p.vis, v, W);
             bool open = false;
             for (uint32_t w = 0; w < W && !open; ++w) {
@@ -359,8 +353,9 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                         const uint32_t b = (uint32_t)__ffsll((long long)hit) - 1u;
                         hit &= hit - 1ull;
                         const uint32_t q = w * 64u + b;
-                        p.level[q][v] = (int32_t)lk;
-                        p.parent[q][v] = u;
+                        const size_t at = stage(p, v, q);
+                        p.slev[at] = (int32_t)lk;
+                        p.spar[at] = (uint32_t)u;
                     }
                 }
                 if (found) {
@@ -369,11 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                     any = true;
                 }
             }
-            if (any) {
-                s_list[atomicAdd(&s_n, 1u)] = v;
-                const uint32_t od = (uint32_t)(p.out_ptr[v + 1] - p.out_ptr[v]);
-                if (od >= kMsLong) add_long(pnew, pmap, pctr, v, od);
-            }
+            if (any) s_list[atomicAdd(&s_n, 1u)] = v;
         }
         __syncthreads();
         const uint32_t nl = s_nl;
@@ -400,17 +391,105 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                     any = true;
                 }
             }
-            if (any && lane == 0) {
-                s_list[atomicAdd(&s_n, 1u)] = v;
-                const uint32_t od = (uint32_t)(p.out_ptr[v + 1] - p.out_ptr[v]);
-                if (od >= kMsLong) add_long(pnew, pmap, pctr, v, od);
-            }
+            if (any && lane == 0) s_list[atomicAdd(&s_n, 1u)] = v;
         }
         __syncthreads();
         if (tid == 0 && s_n) s_base = atomicAdd(&p.cnt[s1], s_n);
         __syncthreads();
         for (uint32_t i = tid; i < s_n; i += kBlock) fnxt[s_base + i] = s_list[i];
         __syncthreads();
+    }
+    // chunks of the long rows, one wave each; vis is not written in this
+    // kernel for these rows, so every chunk sees the same unsettled bits
+    for (uint32_t c = gt >> 6; c < p.nli_chunks; c += gs >> 6) {
+        const MsLong L = p.li[p.limap[c]];
+        const int32_t v = L.v;
+        const int32_t r1 = p.in_ptr[v + 1];
+        const int32_t e0 = p.in_ptr[v] + (int32_t)((c - L.chunk_base) * kMsChunk);
+        const int32_t e1 = (e0 + (int32_t)kMsChunk < r1) ? e0 + (int32_t)kMsChunk : r1;
+        for (uint32_t w = 0; w < W; ++w) {
+            const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+            unsigned long long rem = full & ~row(p.vis, v, W)[w], found = 0ull;
+            for (int32_t eb = e0; eb < e1 && rem; eb += 64) {
+                const unsigned long long f = settle_step(p, cur, v, w, eb, e1, rem, lk, false);
+                rem &= ~f;
+                found |= f;
+            }
+            if (found && lane == 0) atomicOr(&row(nxt, v, W)[w], found);
+        }
+    }
+}
+
+// After a pull level, the long rows: bits their chunks found join vis, and
+// rows with any are listed.
+__global__ __launch_bounds__(kBlock) void k_ms_fixup(MsLevel p, uint32_t k) {
+    const uint32_t s1 = (k + 1) % 3;
+    const unsigned long long *nxt = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s1);
+    int32_t *fnxt = pick3(p.fq[0], p.fq[1], p.fq[2], s1);
+    const uint32_t W = p.W;
+    const uint32_t lane = __lane_id();
+    const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
+    for (uint32_t base_i = gt - lane; base_i < p.nli; base_i += gs) {     // whole waves iterate
+        const uint32_t i = base_i + lane;
+        bool any = false;
+        int32_t v = -1;
+        if (i < p.nli) {
+            v = p.li[i].v;
+            for (uint32_t w = 0; w < W; ++w) {
+                const unsigned long long f = row(nxt, v, W)[w];
+                if (f) {
+                    row(p.vis, v, W)[w] |= f;
+                    any = true;
+                }
+            }
+        }
+        const unsigned long long bm = __ballot(any);
+        if (bm) {
+            const uint32_t leader = (uint32_t)__ffsll((long long)bm) - 1u;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&p.cnt[s1], (uint32_t)__popcll(bm));
+            base = __shfl(base, (int)leader, 64);
+            if (any) fnxt[base + lanes_below(bm)] = v;
+        }
+    }
+}
+
+// The staged results into the callers' arrays: a block per 64 vertices and 64
+// sources, through an LDS tile, so that both the staged rows and the
+// per-source output rows are read and written in whole lines; entries whose
+// vis bit is clear (never reached) become -1.
+__global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
+    __shared__ int32_t t_lv[64][65];
+    __shared__ int32_t t_pa[64][65];
+    const uint32_t W = p.W, S = W * 64u, tid = threadIdx.x;
+    const uint32_t ntiles = (uint32_t)(((size_t)p.n + 63) / 64);
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int32_t v0 = (int32_t)(tile * 64u);
+        for (uint32_t w = 0; w < W; ++w) {
+            for (uint32_t i = tid; i < 64u * 64u; i += kBlock) {
+                const uint32_t vi = i >> 6, qi = i & 63u;
+                const int32_t v = v0 + (int32_t)vi;
+                const uint32_t q = w * 64u + qi;
+                int32_t lv = -1, pa = -1;
+                if (v < p.n && q < p.nq && ((row(p.vis, v, W)[w] >> qi) & 1ull)) {
+                    lv = p.slev[(size_t)v * S + q];
+                    pa = (int32_t)p.spar[(size_t)v * S + q];
+                }
+                t_lv[qi][vi] = lv;
+                t_pa[qi][vi] = pa;
+            }
+            __syncthreads();
+            for (uint32_t i = tid; i < 64u * 64u; i += kBlock) {
+                const uint32_t qi = i >> 6, vi = i & 63u;
+                const int32_t v = v0 + (int32_t)vi;
+                const uint32_t q = w * 64u + qi;
+                if (v < p.n && q < p.nq) {
+                    p.level[q][v] = t_lv[qi][vi];
+                    p.parent[q][v] = t_pa[qi][vi];
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -419,8 +498,6 @@ __global__ void k_ms_report(MsLevel p, uint32_t k) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const uint32_t s2 = (k + 2) % 3;
     p.cnt[s2] = 0u;
-    p.lcnt[s2] = 0ull;
-    p.lcnt[3 + s2] = 0ull;
     p.host_status[0] = k + 1;
     p.host_status[1] = p.cnt[(k + 1) % 3];
     __threadfence_system();
@@ -429,10 +506,12 @@ __global__ void k_ms_report(MsLevel p, uint32_t k) {
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s) {
     switch (phase) {
         case 0: hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kBlock), 0, s, p); break;
-        case 1: hipLaunchKernelGGL(k_ms_roots, dim3((p.nq + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p); break;
+        case 1: hipLaunchKernelGGL(k_ms_roots, dim3(grid), dim3(kBlock), 0, s, p); break;
         case 2: hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 3: hipLaunchKernelGGL(k_ms_settle, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 4: hipLaunchKernelGGL(k_ms_pull, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        case 6: hipLaunchKernelGGL(k_ms_fixup, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        case 7: hipLaunchKernelGGL(k_ms_out, dim3(grid), dim3(kBlock), 0, s, p); break;
         default: hipLaunchKernelGGL(k_ms_report, dim3(1), dim3(64), 0, s, p, k); break;
     }
     return hipGetLastError();
