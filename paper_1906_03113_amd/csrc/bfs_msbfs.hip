@@ -11,16 +11,17 @@
 // i.e. one read of each column serves every source whose frontier holds it.
 //
 // The parent of v for source q is, as everywhere in this library, the
-// smallest frontier in-neighbour; the settle pass finds it by scanning v's
-// in-neighbours in ascending order and giving each still-unassigned source
-// bit to the first u whose cur[u] holds it.  A wave scans 64 entries per
-// step, and an OR prefix across its lanes gives each bit to the lowest lane
-// that holds it.  Long lists (>= kMsLong entries) are split into chunks of
-// kMsChunk entries scanned by different waves, which combine with atomicMin
-// on the parent (the same minimum).  The push form splits long columns the
-// same way.  Level k's mask buffers rotate over three slots so the one that
-// held F_{k-1} can be cleared while level k runs.  Results are bit-identical
-// to single-source searches.
+// smallest frontier in-neighbour.  The push form takes it with atomicMin over
+// the entries it visits; the pull form scans v's in-neighbours in ascending
+// order and gives each still-unassigned source bit to the first u whose
+// cur[u] holds it (a wave scans 64 entries per step, and an OR prefix across
+// its lanes gives each bit to the lowest lane that holds it).  Lists of
+// kMsLong entries or more are split into chunks of kMsChunk entries handled
+// by different waves, which combine with atomicMin (the same minimum).
+// Results are staged vertex-major and written to the callers' per-source
+// arrays at the end.  Level k's mask buffers rotate over three slots so the
+// one that held F_{k-1} can be cleared while level k runs.  Results are
+// bit-identical to single-source searches.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,39 +49,36 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
     return (uint32_t)__popcll(m & ((1ull << __lane_id()) - 1ull));
 }
 
-// OR of x over lanes 0..lane (inclusive), every lane of the wave taking part
-__device__ __forceinline__ unsigned long long wave_or_incl(unsigned long long x, uint32_t lane) {
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        const unsigned long long t = __shfl_up(x, d, 64);
-        if (lane >= d) x |= t;
-    }
-    return x;
-}
-
 __device__ __forceinline__ size_t stage(const MsLevel &p, int32_t v, uint32_t q) {
     return (size_t)v * (p.W * 64u) + q;
 }
 
-// One step of the settle scan over in_idx[eb + lane] (lanes past e1 hold
+// One step of the settle scan by a group of G lanes (G = 16 or 64, aligned
+// within the wave) over in_idx[eb + lane-in-group] (lanes past e1 hold
 // nothing): each bit of rem held by some lane's cur mask goes to the lowest
 // such lane, i.e. to the smallest in-neighbour of the step.  Returns the bits
-// found (the same in every lane).
-__device__ __forceinline__ unsigned long long settle_step(const MsLevel &p, const unsigned long long *cur,
-                                                          int32_t v, uint32_t w, int32_t eb, int32_t e1,
-                                                          unsigned long long rem, uint32_t lk,
-                                                          bool owner_alone) {
-    const uint32_t lane = __lane_id();
-    const int32_t e = eb + (int32_t)lane;
+// found (the same in every lane of the group).
+template <uint32_t G>
+__device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const unsigned long long *cur,
+                                                        int32_t v, uint32_t w, int32_t eb, int32_t e1,
+                                                        unsigned long long rem, uint32_t lk,
+                                                        bool owner_alone) {
+    const uint32_t li = __lane_id() & (G - 1u);
+    const int32_t e = eb + (int32_t)li;
     int32_t u = -1;
     unsigned long long hit = 0ull;
     if (e < e1) {
         u = p.in_idx[e];
         hit = row(cur, u, p.W)[w] & rem;
     }
-    const unsigned long long incl = wave_or_incl(hit, lane);
-    unsigned long long below = __shfl_up(incl, 1u, 64);
-    if (lane == 0) below = 0ull;
+    unsigned long long incl = hit;
+#pragma unroll
+    for (uint32_t d = 1; d < G; d <<= 1) {
+        const unsigned long long t = __shfl_up(incl, d, (int)G);
+        if (li >= d) incl |= t;
+    }
+    unsigned long long below = __shfl_up(incl, 1u, (int)G);
+    if (li == 0) below = 0ull;
     unsigned long long own = hit & ~below;
     while (own) {
         const uint32_t b = (uint32_t)__ffsll((long long)own) - 1u;
@@ -91,15 +89,15 @@ __device__ __forceinline__ unsigned long long settle_step(const MsLevel &p, cons
         if (owner_alone) p.spar[at] = (uint32_t)u;
         else atomicMin(&p.spar[at], (uint32_t)u);
     }
-    return __shfl(incl, 63, 64);
+    return __shfl(incl, (int)(G - 1u), (int)G);
 }
 
 }  // namespace
 
-// Every mask to zero; the staged parents of rows with long in-lists (the only
-// ones combined with atomicMin) to 0xFFFFFFFF.  Other staged entries are
-// written before they are read (k_ms_out reads only entries whose vis bit is
-// set), and k_ms_out writes every output.
+// Every mask to zero and every staged parent to 0xFFFFFFFF (parents are
+// combined with atomicMin).  Staged levels are written before they are read
+// (k_ms_out reads only entries whose vis bit is set), and k_ms_out writes
+// every output.
 __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
     const size_t gid = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kBlock;
@@ -110,12 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
         p.m[1][i] = 0ull;
         p.m[2][i] = 0ull;
     }
-    const uint32_t S = p.W * 64u;
-    for (size_t v = gid; v < (size_t)p.n; v += stride) {
-        p.flag[v] = 0u;
-        if ((uint32_t)(p.in_ptr[v + 1] - p.in_ptr[v]) >= kMsLong)
-            for (uint32_t q = 0; q < S; ++q) p.spar[v * S + q] = 0xFFFFFFFFu;
-    }
+    for (size_t v = gid; v < (size_t)p.n; v += stride) p.flag[v] = 0u;
+    const size_t ns = (size_t)p.n * p.W * 16u;          // staged parents, 16 bytes at a time
+    for (size_t i = gid; i < ns; i += stride)
+        reinterpret_cast<uint4 *>(p.spar)[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
     if (gid < 4) p.cnt[gid] = 0u;
 }
 
@@ -137,9 +133,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_roots(MsLevel p) {
 // Level k, push half.  Work items, one wave each: the frontier columns with
 // fewer than kMsLong entries (lanes over the entries), then the chunks of the
 // graph's long columns, skipped unless the column is in some frontier.  Per
-// entry (u, v): new = cur[u] & ~vis[v] is ORed into nxt[v], and v is listed
-// for level k+1 once, through a per-wave LDS buffer flushed with one atomic
-// per kMsFlush entries.  Also clears the masks of F_{k-1} (slot (k+2) % 3).
+// entry (u, v): new = cur[u] & ~vis[v] is ORed into nxt[v], each of its bits q
+// takes atomicMin(parent_q(v), u) - over all the entries this is the smallest
+// frontier in-neighbour of v for q - and v is listed for level k+1 once,
+// through a per-wave LDS buffer flushed with one atomic per kMsFlush entries.
+// Also clears the masks of F_{k-1} (slot (k+2) % 3).
 constexpr uint32_t kMsWaveBuf = 256;
 constexpr uint32_t kMsFlush = kMsWaveBuf - 64;
 
@@ -199,23 +197,27 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
                 v = p.out_idx[e];
                 const unsigned long long *vv = row(p.vis, v, W);
                 unsigned long long *nv = row(nxt, v, W);
-                if (W == 1) {
-                    // the lane whose OR turns nxt[v] nonzero lists v; a pre-read
-                    // (possibly stale: bits are only ever added) skips ORs that
-                    // would add nothing
-                    const unsigned long long nb = cu[0] & ~vv[0];
-                    if (nb && (nb & ~nv[0])) listed = atomicOr(&nv[0], nb) == 0ull;
-                } else {
-                    bool any = false;
-                    for (uint32_t w = 0; w < W; ++w) {
-                        const unsigned long long nb = cu[w] & ~vv[w];
-                        if (nb) {
-                            atomicOr(&nv[w], nb);
-                            any = true;
-                        }
+                bool any = false;
+                for (uint32_t w = 0; w < W; ++w) {
+                    const unsigned long long nb = cu[w] & ~vv[w];
+                    if (!nb) continue;
+                    // parents only decrease, so a stale pre-read can only let
+                    // an atomic through that was not needed
+                    for (unsigned long long b = nb; b; b &= b - 1ull) {
+                        uint32_t *at = &p.spar[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)];
+                        if (*at > (uint32_t)u) atomicMin(at, (uint32_t)u);
                     }
-                    listed = any && atomicMax(&p.flag[v], tag) < tag;
+                    if (W == 1) {
+                        // the lane whose OR turns nxt[v] nonzero lists v; a
+                        // pre-read (possibly stale: bits are only ever added)
+                        // skips ORs that would add nothing
+                        if (nb & ~nv[0]) listed = atomicOr(&nv[0], nb) == 0ull;
+                    } else {
+                        atomicOr(&nv[w], nb);
+                        any = true;
+                    }
                 }
+                if (W != 1) listed = any && atomicMax(&p.flag[v], tag) < tag;
             }
             const unsigned long long bm = __ballot(listed);
             if (bm) {
@@ -228,54 +230,29 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
     if (nbuf) flush();
 }
 
-// Level k, settle half: one wave per newly listed vertex v with a short
-// in-list, then one wave per chunk of the graph's long rows (skipped unless
-// the row has new bits).  The new bits join vis (by the listed vertex's own
-// item); each gets level k+1 and its parent = the first in-neighbour
-// (ascending) whose level-k frontier mask holds it.
+// Level k, settle half, one lane per newly listed vertex v: the new bits
+// (nxt[v]) join vis and get level k+1 (their parents were set by the push).
 __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
-    const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
-    const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s0);
+    const uint32_t s1 = (k + 1) % 3, s2 = (k + 2) % 3;
     const unsigned long long *nxt = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s1);
     const int32_t *fnxt = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s1);
     const uint32_t nnext = p.cnt[s1];
     const uint32_t W = p.W;
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
-    const uint32_t lane = __lane_id();
     if (gt == 0) {
         p.cnt[s2] = 0u;                       // the list of level k+2 starts empty
         p.host_status[0] = k + 1;
         p.host_status[1] = nnext;
         __threadfence_system();
     }
-    for (uint32_t it = gt >> 6; it < nnext + p.nli_chunks; it += gs >> 6) {
-        int32_t v, e0, e1;
-        bool alone;
-        if (it < nnext) {
-            v = fnxt[it];
-            e0 = p.in_ptr[v];
-            e1 = p.in_ptr[v + 1];
-            if ((uint32_t)(e1 - e0) >= kMsLong) {      // parents by the chunks
-                for (uint32_t w = lane; w < W; w += 64) row(p.vis, v, W)[w] |= row(nxt, v, W)[w];
-                continue;
-            }
-            alone = true;
-        } else {
-            const uint32_t c = it - nnext;
-            const MsLong L = p.li[p.limap[c]];
-            v = L.v;
-            const int32_t r1 = p.in_ptr[v + 1];
-            e0 = p.in_ptr[v] + (int32_t)((c - L.chunk_base) * kMsChunk);
-            e1 = (e0 + (int32_t)kMsChunk < r1) ? e0 + (int32_t)kMsChunk : r1;
-            alone = false;
-        }
+    for (uint32_t i = gt; i < nnext; i += gs) {
+        const int32_t v = fnxt[i];
         for (uint32_t w = 0; w < W; ++w) {
             const unsigned long long nb = row(nxt, v, W)[w];
             if (!nb) continue;
-            if (alone && lane == 0) row(p.vis, v, W)[w] |= nb;      // one writer per (v, w)
-            unsigned long long rem = nb;
-            for (int32_t eb = e0; eb < e1 && rem; eb += 64)
-                rem &= ~settle_step(p, cur, v, w, eb, e1, rem, k + 1, alone);
+            row(p.vis, v, W)[w] |= nb;
+            for (unsigned long long b = nb; b; b &= b - 1ull)
+                p.slev[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)] = (int32_t)(k + 1);
         }
     }
 }
@@ -285,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
 // its in-neighbours restricted to the sources that have not reached it; each
 // source bit found first at u gets parent u (the smallest frontier
 // in-neighbour for that source) and level k+1.  Rows of up to kMsSerial
-// entries are scanned by one lane, longer ones by a wave (settle_step); the
+// entries are scanned by one lane, longer ones by a wave (scan_step); the
 // owner of such a row writes vis and the next mask without atomics, and rows
 // with new bits are listed (one atomicAdd per block chunk).  The graph's long
 // rows (kMsLong entries or more) are scanned in chunks by waves across the
@@ -343,19 +320,28 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                 const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
                 const unsigned long long sv = vis[w];
                 unsigned long long rem = full & ~sv, found = 0ull;
-                for (int32_t e = e0; e < e1 && rem; ++e) {
-                    const int32_t u = p.in_idx[e];
-                    unsigned long long hit = row(cur, u, W)[w] & rem;
-                    if (!hit) continue;
-                    rem &= ~hit;
-                    found |= hit;
-                    while (hit) {
-                        const uint32_t b = (uint32_t)__ffsll((long long)hit) - 1u;
-                        hit &= hit - 1ull;
-                        const uint32_t q = w * 64u + b;
-                        const size_t at = stage(p, v, q);
-                        p.slev[at] = (int32_t)lk;
-                        p.spar[at] = (uint32_t)u;
+                // four entries at a time: their index and mask loads are all
+                // issued before the first is used; positions past e1 repeat
+                // the last entry, whose bits are then already taken
+                for (int32_t e = e0; e < e1 && rem; e += 4) {
+                    int32_t uu[4];
+                    unsigned long long mm[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) uu[j] = p.in_idx[e + j < e1 ? e + j : e1 - 1];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) mm[j] = row(cur, uu[j], W)[w];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        unsigned long long hit = mm[j] & rem;
+                        rem &= ~hit;
+                        found |= hit;
+                        while (hit) {
+                            const uint32_t b = (uint32_t)__ffsll((long long)hit) - 1u;
+                            hit &= hit - 1ull;
+                            const size_t at = stage(p, v, w * 64u + b);
+                            p.slev[at] = (int32_t)lk;
+                            p.spar[at] = (uint32_t)uu[j];
+                        }
                     }
                 }
                 if (found) {
@@ -379,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                 const unsigned long long sv = vis[w];
                 unsigned long long rem = full & ~sv, found = 0ull;
                 for (int32_t eb = e0; eb < e1 && rem; eb += 64) {
-                    const unsigned long long f = settle_step(p, cur, v, w, eb, e1, rem, lk, true);
+                    const unsigned long long f = scan_step<64>(p, cur, v, w, eb, e1, rem, lk, true);
                     rem &= ~f;
                     found |= f;
                 }
@@ -411,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
             const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
             unsigned long long rem = full & ~row(p.vis, v, W)[w], found = 0ull;
             for (int32_t eb = e0; eb < e1 && rem; eb += 64) {
-                const unsigned long long f = settle_step(p, cur, v, w, eb, e1, rem, lk, false);
+                const unsigned long long f = scan_step<64>(p, cur, v, w, eb, e1, rem, lk, false);
                 rem &= ~f;
                 found |= f;
             }
@@ -456,36 +442,62 @@ __global__ __launch_bounds__(kBlock) void k_ms_fixup(MsLevel p, uint32_t k) {
 
 // The staged results into the callers' arrays: a block per 64 vertices and 64
 // sources, through an LDS tile, so that both the staged rows and the
-// per-source output rows are read and written in whole lines; entries whose
-// vis bit is clear (never reached) become -1.
+// per-source output rows move in whole lines; each lane reads 4 sources of a
+// staged row and writes 4 vertices of an output row (16 bytes, or 4 scalar
+// stores where the caller's array is not 16-byte aligned or at the tail).
+// Entries whose vis bit is clear (never reached) become -1.
 __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
     __shared__ int32_t t_lv[64][65];
     __shared__ int32_t t_pa[64][65];
     const uint32_t W = p.W, S = W * 64u, tid = threadIdx.x;
     const uint32_t ntiles = (uint32_t)(((size_t)p.n + 63) / 64);
+    const uint32_t g4 = (tid & 15u) * 4u;          // first of this lane's 4 columns
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int32_t v0 = (int32_t)(tile * 64u);
         for (uint32_t w = 0; w < W; ++w) {
-            for (uint32_t i = tid; i < 64u * 64u; i += kBlock) {
-                const uint32_t vi = i >> 6, qi = i & 63u;
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {            // staged rows -> tile[source][vertex]
+                const uint32_t vi = (tid >> 4) + 16u * r;
                 const int32_t v = v0 + (int32_t)vi;
-                const uint32_t q = w * 64u + qi;
-                int32_t lv = -1, pa = -1;
-                if (v < p.n && q < p.nq && ((row(p.vis, v, W)[w] >> qi) & 1ull)) {
-                    lv = p.slev[(size_t)v * S + q];
-                    pa = (int32_t)p.spar[(size_t)v * S + q];
+                int4 lv = make_int4(-1, -1, -1, -1), pa = lv;
+                uint32_t bits = 0;
+                if (v < p.n) bits = (uint32_t)(row(p.vis, v, W)[w] >> g4) & 15u;
+                if (bits) {
+                    const size_t at = (size_t)v * S + w * 64u + g4;
+                    lv = *reinterpret_cast<const int4 *>(p.slev + at);
+                    pa = *reinterpret_cast<const int4 *>(p.spar + at);
                 }
-                t_lv[qi][vi] = lv;
-                t_pa[qi][vi] = pa;
+                t_lv[g4 + 0][vi] = (bits & 1u) ? lv.x : -1;
+                t_lv[g4 + 1][vi] = (bits & 2u) ? lv.y : -1;
+                t_lv[g4 + 2][vi] = (bits & 4u) ? lv.z : -1;
+                t_lv[g4 + 3][vi] = (bits & 8u) ? lv.w : -1;
+                t_pa[g4 + 0][vi] = (bits & 1u) ? pa.x : -1;
+                t_pa[g4 + 1][vi] = (bits & 2u) ? pa.y : -1;
+                t_pa[g4 + 2][vi] = (bits & 4u) ? pa.z : -1;
+                t_pa[g4 + 3][vi] = (bits & 8u) ? pa.w : -1;
             }
             __syncthreads();
-            for (uint32_t i = tid; i < 64u * 64u; i += kBlock) {
-                const uint32_t qi = i >> 6, vi = i & 63u;
-                const int32_t v = v0 + (int32_t)vi;
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {            // tile rows -> output rows
+                const uint32_t qi = (tid >> 4) + 16u * r;
                 const uint32_t q = w * 64u + qi;
-                if (v < p.n && q < p.nq) {
-                    p.level[q][v] = t_lv[qi][vi];
-                    p.parent[q][v] = t_pa[qi][vi];
+                if (q >= p.nq) continue;
+                int32_t *lo = p.level[q] + v0 + g4;
+                int32_t *po = p.parent[q] + v0 + g4;
+                const int4 a = make_int4(t_lv[qi][g4], t_lv[qi][g4 + 1], t_lv[qi][g4 + 2], t_lv[qi][g4 + 3]);
+                const int4 b = make_int4(t_pa[qi][g4], t_pa[qi][g4 + 1], t_pa[qi][g4 + 2], t_pa[qi][g4 + 3]);
+                const bool full = v0 + (int32_t)g4 + 3 < p.n;
+                if (full && ((reinterpret_cast<uintptr_t>(lo) | reinterpret_cast<uintptr_t>(po)) & 15u) == 0) {
+                    *reinterpret_cast<int4 *>(lo) = a;
+                    *reinterpret_cast<int4 *>(po) = b;
+                } else {
+                    const int32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (v0 + (int32_t)g4 + j < p.n) {
+                            lo[j] = av[j];
+                            po[j] = bv[j];
+                        }
                 }
             }
             __syncthreads();
