@@ -241,9 +241,16 @@ def main():
                             variant="heuristic")
             torch.cuda.synchronize()
             dtb = (time.perf_counter() - t0b) / args.steps
+            # the per-search algorithmic bytes of the plain form, summed over the
+            # batch's searches, over the batch's wall time: what separate
+            # searches would have to move, so above-peak values are possible
+            # (one read of a column serves every source whose frontier holds it)
+            b_step = float(sum(4 * nz + 24 * nc for nz, nc in zip(nnz_c, n_c)))
             modes["batch_multisource"] = {"gteps": round(total_m / dtb / 1e9, 3),
                                           "ms_per_step": round(dtb * 1e3, 4),
-                                          "searches_per_call": nq}
+                                          "searches_per_call": nq,
+                                          "plain_bytes_per_step": round(b_step),
+                                          "plain_bytes_rate_GBps": round(b_step / dtb / 1e9, 1)}
             log(f"[bench] multi-source batch: {dtb * 1e3:.3f} ms/step, {total_m / dtb / 1e9:.2f} GTEPS")
             del bl, bp, wsb
     best = max(modes, key=lambda m: modes[m]["gteps"])
