@@ -269,12 +269,15 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
 // grid: each chunk gives its first hits (atomicMin on the staged parent) and
 // ORs its bits into the next mask; k_ms_fixup then folds those into vis and
 // lists the rows.  Also clears F_{k-1}'s masks.
-constexpr uint32_t kMsRows = 2048;       // rows per block chunk
+constexpr uint32_t kMsRows = 1024;       // rows per block chunk
 constexpr int32_t kMsSerial = 16;        // longest row one lane scans alone
 
 __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
     __shared__ int32_t s_list[kMsRows];
     __shared__ int32_t s_long[kMsRows];
+    __shared__ uint32_t s_off[kBlock][9];          // a row's found bits: entry offset, 4 bits each
+    __shared__ unsigned long long s_fnd[kBlock];   // a row's found bits (one word)
+    __shared__ int32_t s_e0[kBlock];
     __shared__ uint32_t s_n, s_nl, s_base;
     const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
     const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s0);
@@ -299,56 +302,90 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
         }
         __syncthreads();
         const uint32_t c1 = (c0 + kMsRows < (uint32_t)p.n) ? c0 + kMsRows : (uint32_t)p.n;
-        for (uint32_t vv = c0 + tid; vv < c1; vv += kBlock) {
+        // Rows of up to kMsSerial entries, one lane each, 256 at a time.  A
+        // lane records, per found bit, the offset of the entry that gave it
+        // (LDS); then each wave writes its lanes' rows, one row at a time
+        // with the 64 sources of the word on the 64 lanes, so the staged
+        // results of a row go out as one 256-byte store.
+        for (uint32_t r0 = c0; r0 < c1; r0 += kBlock) {
+            const uint32_t vv = r0 + tid;
             const int32_t v = (int32_t)vv;
-            const int32_t e0 = p.in_ptr[v], e1 = p.in_ptr[v + 1];
-            if (e1 == e0 || (uint32_t)(e1 - e0) >= kMsLong) continue;     // long rows: chunks below
-            unsigned long long *vis = row(p.vis, v, W);
-            bool open = false;
-            for (uint32_t w = 0; w < W && !open; ++w) {
-                const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
-                open = (full & ~vis[w]) != 0ull;
-            }
-            if (!open) continue;                         // every source has reached v
-            if (e1 - e0 > kMsSerial) {
-                s_long[atomicAdd(&s_nl, 1u)] = v;
-                continue;
-            }
-            unsigned long long *nv = row(nxt, v, W);
-            bool any = false;
-            for (uint32_t w = 0; w < W; ++w) {
-                const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
-                const unsigned long long sv = vis[w];
-                unsigned long long rem = full & ~sv, found = 0ull;
-                // four entries at a time: their index and mask loads are all
-                // issued before the first is used; positions past e1 repeat
-                // the last entry, whose bits are then already taken
-                for (int32_t e = e0; e < e1 && rem; e += 4) {
-                    int32_t uu[4];
-                    unsigned long long mm[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) uu[j] = p.in_idx[e + j < e1 ? e + j : e1 - 1];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) mm[j] = row(cur, uu[j], W)[w];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        unsigned long long hit = mm[j] & rem;
-                        rem &= ~hit;
-                        found |= hit;
-                        while (hit) {
-                            const uint32_t b = (uint32_t)__ffsll((long long)hit) - 1u;
-                            hit &= hit - 1ull;
-                            const size_t at = stage(p, v, w * 64u + b);
-                            p.slev[at] = (int32_t)lk;
-                            p.spar[at] = (uint32_t)uu[j];
-                        }
+            int32_t e0 = 0, e1 = 0;
+            bool mine = false;
+            if (vv < c1) {
+                e0 = p.in_ptr[v];
+                e1 = p.in_ptr[v + 1];
+                if (e1 > e0 && (uint32_t)(e1 - e0) < kMsLong) {        // long rows: chunks below
+                    const unsigned long long *vis = row(p.vis, v, W);
+                    bool open = false;
+                    for (uint32_t w = 0; w < W && !open; ++w) {
+                        const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+                        open = (full & ~vis[w]) != 0ull;
+                    }
+                    if (open) {                      // else every source has reached v
+                        if (e1 - e0 > kMsSerial) s_long[atomicAdd(&s_nl, 1u)] = v;
+                        else mine = true;
                     }
                 }
-                if (found) {
-                    nv[w] = found;
-                    vis[w] = sv | found;
-                    any = true;
+            }
+            s_e0[tid] = e0;
+            bool any = false;
+            for (uint32_t w = 0; w < W; ++w) {
+                unsigned long long found = 0ull;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) s_off[tid][i] = 0u;
+                if (mine) {
+                    unsigned long long *vis = row(p.vis, v, W);
+                    const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+                    const unsigned long long sv = vis[w];
+                    unsigned long long rem = full & ~sv;
+                    // four entries at a time: their index and mask loads are
+                    // all issued before the first is used; positions past e1
+                    // repeat the last entry, whose bits are then already taken
+                    for (int32_t e = e0; e < e1 && rem; e += 4) {
+                        int32_t uu[4];
+                        unsigned long long mm[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) uu[j] = p.in_idx[e + j < e1 ? e + j : e1 - 1];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) mm[j] = row(cur, uu[j], W)[w];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            unsigned long long hit = mm[j] & rem;
+                            rem &= ~hit;
+                            found |= hit;
+                            const uint32_t off = (uint32_t)(e - e0 + j);
+                            while (hit) {
+                                const uint32_t b = (uint32_t)__ffsll((long long)hit) - 1u;
+                                hit &= hit - 1ull;
+                                s_off[tid][b >> 3] |= off << ((b & 7u) * 4u);
+                            }
+                        }
+                    }
+                    if (found) {
+                        row(nxt, v, W)[w] = found;
+                        vis[w] = sv | found;
+                        any = true;
+                    }
                 }
+                s_fnd[tid] = found;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // this wave's lanes' rows that found something, one at a time
+                for (unsigned long long rows = __ballot(found != 0ull); rows; rows &= rows - 1ull) {
+                    const uint32_t rr = (tid & ~63u) + (uint32_t)__ffsll((long long)rows) - 1u;
+                    const unsigned long long fm = s_fnd[rr];
+                    if ((fm >> lane) & 1ull) {
+                        const uint32_t j = (s_off[rr][lane >> 3] >> ((lane & 7u) * 4u)) & 15u;
+                        const size_t at = stage(p, (int32_t)(r0 + rr), w * 64u + lane);
+                        p.slev[at] = (int32_t)lk;
+                        p.spar[at] = (uint32_t)p.in_idx[s_e0[rr] + (int32_t)j];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
             if (any) s_list[atomicAdd(&s_n, 1u)] = v;
         }
