@@ -238,7 +238,9 @@ size_t bfs_profile_snapshot_size(const bfs_graph *g);
  * Exhaustive per-level timing, the selector's training data: runs the search
  * from `source`; before each level it saves the search state, times that one
  * level under each of the three forms (push, pull, push-bitmap; best of
- * `reps` runs, each from the restored state) and then advances with push.
+ * `reps` runs, each from the restored state) and then advances with the
+ * fastest of the three (so later levels start from the state a good per-level
+ * choice produces, e.g. the unvisited list compacted by earlier pull levels).
  * records (host) receives three records per level (variant 0, 1, 2 in that
  * order, time_us = that level's device time); *count the number written.
  * level / parent / workspace as for bfs_run; snapshot: device buffer of

@@ -862,6 +862,8 @@ extern "C" bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *
         if (nf == 0) break;
         st = save();
         if (st != BFS_OK) return st;
+        uint32_t fastest = 0;
+        float fastest_us = 1e30f;
         for (uint32_t v = 0; v < 3; ++v) {
             float best = 1e30f;
             for (int32_t r = 0; r < reps; ++r) {
@@ -888,11 +890,21 @@ extern "C" bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *
                 o.time_us = best;
                 o.reserved = 0.f;
             }
+            if (best < fastest_us) {
+                fastest_us = best;
+                fastest = v;
+            }
         }
+        // the search goes on with the fastest form, so that the state later
+        // levels start from (e.g. the unvisited list a pull level compacts)
+        // is the one a good per-level choice produces
         st = restore();
         if (st != BFS_OK) return st;
-        HIP_TRY(launch_level(P, c.grid, s));
-        HIP_TRY(launch_finish(P, s));
+        HIP_TRY(hipMemcpy(&P.st->variant, &fastest, sizeof fastest, hipMemcpyHostToDevice));
+        LevelParams Pc = P;
+        Pc.policy = fastest;
+        HIP_TRY(launch_level(Pc, c.grid, s));
+        HIP_TRY(launch_finish(Pc, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     *count = n_out;

@@ -160,8 +160,25 @@ class Trainer:
         return self.w.detach().cpu().numpy().copy()
 
 
-def train(X, T, M, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log=None) -> np.ndarray:
-    tr = Trainer(init_weights(np.asarray(X), seed), X, T, M)
+def level_weights(T: np.ndarray, M: np.ndarray, lo: float = 0.25, hi: float = 4.0) -> np.ndarray:
+    """Per-row loss weights: sqrt(best time / median best time), clipped to
+    [lo, hi], so that the levels that cost the most device time (what the
+    regret sums) count more than the many cheap levels of deep searches."""
+    t = np.where(M > 0, np.exp(T), np.inf)
+    best = t.min(1)
+    ok = np.isfinite(best)
+    if not ok.any():
+        return np.ones(len(T))
+    w = np.sqrt(np.where(ok, best, 0.0) / np.median(best[ok]))
+    return np.where(ok, np.clip(w, lo, hi), 0.0)
+
+
+def train(X, T, M, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log=None,
+          weighted: bool = True) -> np.ndarray:
+    """Full-batch Adam on the masked squared error of the log-times; rows
+    weighted by level_weights unless weighted=False."""
+    Mw = np.asarray(M, np.float64) * (level_weights(T, M)[:, None] if weighted else 1.0)
+    tr = Trainer(init_weights(np.asarray(X), seed), X, T, Mw)
     for i in range(steps):
         loss = tr.step(lr if i < steps * 2 // 3 else lr * 0.2)
         if log and (i % max(1, steps // 10) == 0 or i == steps - 1):
@@ -229,6 +246,8 @@ def training_graphs(include_large: bool = True):
     if include_large:
         train += [("rmat22", lambda: graphgen.workload("rmat22"), None),
                   ("rmat20d", lambda: graphgen.workload("rmat20d"), None),
+                  ("rmat19", lambda: graphgen.rmat(19, 16, 7), None),
+                  ("rmat21", lambda: graphgen.rmat(21, 16, 8), None),
                   ("grid1024", lambda: graphgen.grid(1024, 0.9, 5), [None, None]),
                   ("grid2048", lambda: graphgen.grid(2048, 0.9, 6), [None])]
     held = {"rmat": [(f"rmat{s}", (lambda s=s: graphgen.rmat(s, 16, 1000 + s)), None)
