@@ -39,6 +39,9 @@ struct alignas(256) BfsState {
     uint32_t bar_group[kBarGroups * 16];
     uint32_t bar_top;
     uint32_t pad2[15];
+    // per-group release generations (one line each): the top release is
+    // watched by the groups' last arrivals only, everyone else watches its group
+    uint32_t bar_gen_group[kBarGroups * 16];
 };
 // Per-level record kept on the device (a trace ring of kTraceCap entries).
 struct DevLevelRec {

@@ -1029,52 +1029,85 @@ __global__ void k_finish(LevelParams P) {
 // The form of level 0 (after the init kernels).
 __global__ void k_decide(LevelParams P) { decide_level(P, 0); }
 
-// Grid barrier for the cooperative kernel.  Blocks arrive on one of
-// kBarGroups counters (block b on group b % kBarGroups, each counter on its own
-// line), the last arrival of a group arrives on the top counter, and the last
-// group releases everyone by bumping the generation - arrivals serialise on
-// kBarGroups + nblocks / kBarGroups atomics instead of nblocks.  Returns false
-// only if the spin limit runs out, which cannot happen when every block is
-// resident.
-__device__ bool grid_sync(BfsState *st, uint32_t nblocks, uint32_t *s_ok) {
+// Grid barrier for the cooperative kernel, with the level's closing work done
+// inside it.  Blocks arrive on one of kBarGroups counters (block b on group
+// b % kBarGroups, each counter on its own line); the last arrival of a group
+// arrives on the top counter.  The block of the very last arrival closes level
+// k (finish_level, then the next level's form) and bumps the top generation;
+// the other groups' last arrivals wait for that and each then releases its
+// group by bumping the group's own generation, which the rest of the group
+// watches.  Arrivals serialise on kBarGroups + nblocks / kBarGroups atomics
+// instead of nblocks, and at most nblocks / kBarGroups blocks poll any one
+// line.  Returns false only if a spin limit runs out, which cannot happen when
+// every block is resident.
+__device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, uint32_t nf, uint32_t nblocks,
+                              uint32_t *s_role) {
+    BfsState *st = P.st;
+    const uint32_t groups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
+    const uint32_t g = blockIdx.x % groups;
+    const uint32_t in_group = (nblocks - g + groups - 1) / groups;
+    uint32_t *ggen = &st->bar_gen_group[g * 16];
+    uint32_t gen = 0, tgen = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t ok = 1;
-        const uint32_t groups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
-        const uint32_t g = blockIdx.x % groups;
-        const uint32_t in_group = (nblocks - g + groups - 1) / groups;
-        const uint32_t gen = ld_agent(&st->barrier_gen);
+        uint32_t role = 0;                                   // 0 member, 1 group's last, 2 very last
+        gen = ld_agent(ggen);
         __threadfence();
-        bool last = false;
         if (atomicAdd(&st->bar_group[g * 16], 1u) == in_group - 1) {
             __hip_atomic_store(&st->bar_group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tgen = ld_agent(&st->barrier_gen);
+            __threadfence();
+            role = 1;
             if (atomicAdd(&st->bar_top, 1u) == groups - 1) {
                 __hip_atomic_store(&st->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                last = true;
+                role = 2;
             }
         }
-        if (last) {
+        *s_role = role;
+    }
+    __syncthreads();
+    const uint32_t role = *s_role;
+    if (role == 2) {                                         // every block is done with level k
+        __threadfence();
+        if (threadIdx.x == 0) finish_level(P, k, nf);
+        __syncthreads();
+        decide_level(P, k + 1);
+    }
+    __syncthreads();
+    uint32_t ok = 1;
+    if (threadIdx.x == 0) {
+        if (role == 2) {
             __threadfence();
             atomicAdd(&st->barrier_gen, 1u);
-        } else {
+        } else if (role == 1) {
             uint32_t spins = 0;
-            while (ld_agent(&st->barrier_gen) == gen) {
+            while (ld_agent(&st->barrier_gen) == tgen) {
                 __builtin_amdgcn_s_sleep(1);
                 if (++spins > (1u << 26)) { ok = 0; break; }
             }
         }
+        if (role != 0) {
+            __threadfence();
+            atomicAdd(ggen, 1u);                             // release this group
+        } else {
+            uint32_t spins = 0;
+            while (ld_agent(ggen) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1u << 26)) { ok = 0; break; }
+            }
+        }
         __threadfence();
-        *s_ok = ok;
+        *s_role = ok;
     }
     __syncthreads();
-    return *s_ok != 0;
+    return *s_role != 0;
 }
 
-// Every level in one launch: level body, barrier, block 0 finishes the level,
-// barrier.  The loop ends when the frontier is empty (every block reads the
-// same counters after a barrier).
+// Every level in one launch: level body, then the level barrier (whose last
+// arrival closes the level).  The loop ends when the frontier is empty (every
+// block reads the same counters after a barrier).
 __global__ __launch_bounds__(kBlock) void k_persistent(LevelParams P) {
-    __shared__ uint32_t s_ok;
+    __shared__ uint32_t s_role;
     BfsState *st = P.st;
     const uint32_t nb = gridDim.x;
     for (;;) {
@@ -1082,13 +1115,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(LevelParams P) {
         const uint32_t nf = ld_agent(&st->nf[k & 3]) + (uint32_t)ld_agent64(&st->heavy[k & 3]);
         if (nf == 0) break;
         level_body(P, k, blockIdx.x, nb);
-        if (!grid_sync(st, nb, &s_ok)) break;
-        if (blockIdx.x == 0) {
-            if (threadIdx.x == 0) finish_level(P, k, nf);
-            __syncthreads();
-            decide_level(P, k + 1);
-        }
-        if (!grid_sync(st, nb, &s_ok)) break;
+        if (!level_barrier(P, k, nf, nb, &s_role)) break;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) report(P);
 }

@@ -1,0 +1,182 @@
+"""The batching measurements: many sources on one graph in one call, and many
+uneven graphs in one launch.
+
+    python -m paper_1906_03113_amd.experiments [--only sources|graphs] [--out FILE]
+
+* sources: directed R-MAT scale 20 (edgefactor 16, out-edges), 256 sources of
+  nonzero out-degree (seed 41) in one bfs_run_batch call (4 mask words per
+  vertex), against the same 256 searches one at a time (plain push, and the
+  fixed-rule direction choice with the graph loop).
+* graphs: 64 undirected ER graphs, n_g = round(2^U(10,18)), average degree
+  U(4,32), graph g seeded 1000+g, packed block-diagonally, the lowest-index
+  vertex of nonzero degree of each block as its root: one search from the 64
+  roots (persistent kernel, and the graph loop), against 64 separate searches
+  on the separate graphs (plain push with the defaults, and with each graph's
+  launch parameters from the tuning cache when one is given).
+
+Throughput is GTEPS = sum over the searches of m_c (edges of the reached
+component; each undirected edge once, each directed edge once) / wall time,
+every graph resident and every output buffer allocated before the timed part.
+"""
+from __future__ import annotations
+
+import json
+import sys
+import time
+from typing import Dict, List
+
+import numpy as np
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _edges_reached(g, level: np.ndarray) -> int:
+    deg = np.diff(g.ptr.astype(np.int64))
+    nz = int(deg[level >= 0].sum())
+    return nz if g.directed else nz // 2
+
+
+def _timed(fn, reps: int = 3) -> float:
+    """Best wall time (s) of reps calls after one warm-up call."""
+    torch = _torch()
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def many_sources(count: int = 256, seed: int = 41, log=print) -> Dict:
+    import graphgen
+    import paper_1906_03113_amd as P
+    torch = _torch()
+    g = graphgen.workload("rmat20d")
+    src = [int(s) for s in graphgen.pick_sources(g, count, seed)]
+    G = P.Graph.from_graphgen(g)
+    n = g.n
+    lv = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in src]
+    pa = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in src]
+    wsb = P.Workspace(G.workspace_size(len(src)))
+    P.bfs_batch(G, src, levels=lv, parents=pa, workspace=wsb, variant="heuristic")
+    torch.cuda.synchronize()
+    m = sum(_edges_reached(g, l.cpu().numpy()) for l in lv)
+    t_batch = _timed(lambda: P.bfs_batch(G, src, levels=lv, parents=pa, workspace=wsb, variant="heuristic"))
+    log(f"[sources] {len(src)} sources in one call: {t_batch * 1e3:.2f} ms, {m / t_batch / 1e9:.2f} GTEPS")
+    del lv, pa, wsb
+    torch.cuda.empty_cache()
+    l1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    p1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = P.Workspace(G.workspace_size(1))
+    res = {"graph": "R-MAT scale 20, edgefactor 16, directed", "n": n, "nnz": g.nnz,
+           "sources": len(src), "edges_m_c": m,
+           "one_call": {"ms": t_batch * 1e3, "gteps": m / t_batch / 1e9}}
+    for name, kw in (("one_at_a_time_push", dict(variant="push")),
+                     ("one_at_a_time_heuristic_graph_loop",
+                      dict(variant="heuristic", loop="graph", levels_per_sync=8))):
+        def run(kw=kw):
+            for s in src:
+                P.bfs(G, s, level=l1, parent=p1, workspace=ws, **kw)
+        t = _timed(run, reps=2)
+        res[name] = {"ms": t * 1e3, "gteps": m / t / 1e9}
+        log(f"[sources] {name}: {t * 1e3:.2f} ms, {m / t / 1e9:.2f} GTEPS")
+    G.close()
+    return res
+
+
+def many_graphs(count: int = 64, tune_cache: str = "", log=print) -> Dict:
+    import graphgen
+    import paper_1906_03113_amd as P
+    torch = _torch()
+    gs = graphgen.er_family(count=count, lo=10, hi=18, dmin=4, dmax=32)
+    packed, offs = graphgen.block_diagonal(gs)
+    roots, m = [], 0
+    for b, g in enumerate(gs):
+        nz = np.nonzero(g.out_degree() > 0)[0]
+        roots.append(int(offs[b] + (nz[0] if len(nz) else 0)))
+    Gp = P.Graph.from_graphgen(packed)
+    lv = torch.empty(packed.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty(packed.n, dtype=torch.int32, device="cuda")
+    wsr = P.Workspace(Gp.roots_workspace_size(len(roots)))
+    P.bfs_roots(Gp, roots, level=lv, parent=pa, workspace=wsr, loop="persistent")
+    torch.cuda.synchronize()
+    m = _edges_reached(packed, lv.cpu().numpy())
+    res = {"graphs": count, "n_total": packed.n, "nnz_total": packed.nnz, "edges_m_c": m,
+           "n_range": [min(g.n for g in gs), max(g.n for g in gs)]}
+    for name, kw in (("one_launch_persistent", dict(loop="persistent")),
+                     ("one_search_graph_loop", dict(loop="graph", levels_per_sync=16)),
+                     ("one_search_host_loop", dict(loop="host"))):
+        t = _timed(lambda kw=kw: P.bfs_roots(Gp, roots, level=lv, parent=pa, workspace=wsr, **kw))
+        res[name] = {"ms": t * 1e3, "gteps": m / t / 1e9}
+        log(f"[graphs] {name}: {t * 1e3:.2f} ms, {m / t / 1e9:.2f} GTEPS")
+    Gp.close()
+    del lv, pa, wsr
+    torch.cuda.empty_cache()
+    # the same 64 searches on the 64 separate graphs
+    Gs = [P.Graph.from_graphgen(g) for g in gs]
+    outs = [(torch.empty(g.n, dtype=torch.int32, device="cuda"),
+             torch.empty(g.n, dtype=torch.int32, device="cuda"),
+             P.Workspace(G.workspace_size(1))) for g, G in zip(gs, Gs)]
+    local = [int(r - offs[b]) for b, r in enumerate(roots)]
+    params: List[Dict] = [{} for _ in gs]
+    if tune_cache:
+        from . import autotune as AT
+        for b, (g, G) in enumerate(zip(gs, Gs)):
+            info = {}
+            P.bfs(G, local[b], info=info)
+            params[b] = AT.lookup(G, int(info["levels"]), tune_cache)
+
+    def separate(tuned: bool):
+        for b, G in enumerate(Gs):
+            l, p, w = outs[b]
+            P.bfs(G, local[b], level=l, parent=p, workspace=w, **(params[b] if tuned else {}))
+
+    t = _timed(lambda: separate(False))
+    res["separate_searches_push"] = {"ms": t * 1e3, "gteps": m / t / 1e9}
+    log(f"[graphs] 64 separate searches (push, defaults): {t * 1e3:.2f} ms, {m / t / 1e9:.2f} GTEPS")
+    if tune_cache:
+        t = _timed(lambda: separate(True))
+        res["separate_searches_tuned"] = {"ms": t * 1e3, "gteps": m / t / 1e9}
+        log(f"[graphs] 64 separate searches (tuned parameters): {t * 1e3:.2f} ms, {m / t / 1e9:.2f} GTEPS")
+    # one multi-graph call (the library runs the queries one after another)
+    lvs = [o[0] for o in outs]
+    pas = [o[1] for o in outs]
+    wsm = P.Workspace(max(G.workspace_size(1) for G in Gs))
+    t = _timed(lambda: P.bfs_batch(Gs, local, levels=lvs, parents=pas, workspace=wsm))
+    res["multi_graph_call"] = {"ms": t * 1e3, "gteps": m / t / 1e9}
+    log(f"[graphs] one bfs_run_batch over the 64 graphs: {t * 1e3:.2f} ms, {m / t / 1e9:.2f} GTEPS")
+    for G in Gs:
+        G.close()
+    return res
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="batching measurements (many sources, many graphs)")
+    ap.add_argument("--only", choices=["sources", "graphs"], default=None)
+    ap.add_argument("--tune-cache", default="", help="autotune cache for per-graph parameters")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)
+    torch = _torch()
+    torch.cuda.init()
+    out = {}
+    if a.only in (None, "sources"):
+        out["many_sources"] = many_sources(log=log)
+    if a.only in (None, "graphs"):
+        out["many_graphs"] = many_graphs(tune_cache=a.tune_cache, log=log)
+    txt = json.dumps(out)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+    print(txt)
+
+
+if __name__ == "__main__":
+    main()
