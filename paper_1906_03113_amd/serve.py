@@ -155,8 +155,8 @@ class GpuExecutor:
     """Runs batches on resident graphs through the library (one stream per worker)."""
 
     def __init__(self, graphs: Dict[str, object], mode: str = "batched", selector=None,
-                 multi_source_max_n: int = 1 << 20, keep_results: bool = False,
-                 params: Optional[Dict[str, Dict]] = None):
+                 multi_source_max_n: int = 1 << 23, keep_results: bool = False,
+                 params: Optional[Dict[str, Dict]] = None, shallow: Optional[Dict[str, bool]] = None):
         import torch
         import paper_1906_03113_amd as P
         self.P = P
@@ -167,11 +167,19 @@ class GpuExecutor:
         self.ms_max_n = multi_source_max_n
         self.keep = keep_results
         self.params = params or {}             # per-graph launch parameters (autotuned)
+        # graphs whose searches take few levels: their batches run as one
+        # multi-source search (which reads the frontier size back every level)
+        self.shallow = shallow if shallow is not None else {k: True for k in graphs}
         self.local = threading.local()
+
+    def multi_source(self, gname: str, nq: int) -> bool:
+        G = self.graphs[gname]
+        return (self.mode != "plain" and nq > 1 and G.n <= self.ms_max_n
+                and self.shallow.get(gname, False))
 
     def footprint(self, gname: str, nq: int) -> int:
         G = self.graphs[gname]
-        ws = G.workspace_size(nq if (nq > 1 and G.n <= self.ms_max_n) else 1)
+        ws = G.workspace_size(nq if self.multi_source(gname, nq) else 1)
         return int(ws) + 8 * G.n * nq
 
     def _stream(self):
@@ -187,8 +195,8 @@ class GpuExecutor:
         with torch.cuda.stream(s):
             if self.mode == "plain":
                 outs = [P.bfs(G, src, variant="push", stream=s) for src in srcs]
-            elif len(srcs) > 1 and G.n <= self.ms_max_n:
-                lv, pa = P.bfs_batch(G, srcs, stream=s)
+            elif self.multi_source(b.graph, len(srcs)):
+                lv, pa = P.bfs_batch(G, srcs, stream=s, variant="heuristic")
                 outs = list(zip(lv, pa))
             else:
                 kw = dict(variant="learned", selector=self.selector) if self.selector is not None \
@@ -320,13 +328,15 @@ def resident_set(which: str = "small"):
     return out
 
 
-def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector) -> Dict[str, Dict]:
-    """Per-graph launch parameters for the serving path: the autotuner's cached
-    choice for the graph's shape if there is one, else by diameter class - deep
-    graphs read the frontier size back every 64 levels instead of every 4."""
+def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector):
+    """Per-graph launch parameters for the serving path, from one probe search
+    per graph: the autotuner's cached choice for the graph's shape if there is
+    one, else by diameter class - deep graphs read the frontier size back every
+    64 levels instead of every 4.  Also whether the graph is shallow (at most 64
+    levels), which lets its batches run as one multi-source search."""
     import paper_1906_03113_amd as P
     from . import autotune as AT
-    out = {}
+    out, shallow = {}, {}
     for name, G in Gs.items():
         info = {}
         P.bfs(G, int(srcs[name][0]), variant="learned", selector=selector, info=info)
@@ -336,7 +346,8 @@ def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector) 
         if levels > 64:
             kw.setdefault("levels_per_sync", 64)
         out[name] = kw
-    return out
+        shallow[name] = levels <= 64
+    return out, shallow
 
 
 def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers=4, seed=5,
@@ -358,9 +369,9 @@ def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers
         del g
     names = sorted(Gs)
     sel = S.load_weights()
-    params = launch_params(Gs, srcs, sel)
+    params, shallow = launch_params(Gs, srcs, sel)
     plain = GpuExecutor(Gs, mode="plain")
-    fast = GpuExecutor(Gs, mode="batched", selector=sel, params=params)
+    fast = GpuExecutor(Gs, mode="batched", selector=sel, params=params, shallow=shallow)
     # saturation of the plain path: back-to-back queries, one worker
     rng = np.random.default_rng(seed)
     warm = [Query(i, names[int(rng.integers(len(names)))], 0, 0.0) for i in range(len(names))]
