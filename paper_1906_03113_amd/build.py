@@ -32,7 +32,8 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         cmd = [HIPCC, *HIP_FLAGS, "-c", src, "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-value", "-Wno-unused-result", "-c", src, "-o", obj]
+            # host code only (no kernels); the offload target keeps hipcc on gfx950
+            cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -114,17 +114,18 @@ bfs_status upload(T **dst, const T *src, size_t count, size_t &bytes) {
 
 void free_graph(bfs_graph *g) {
     if (!g) return;
-    for (hipEvent_t e : g->events) hipEventDestroy(e);
-    if (g->gcache.exec) hipGraphExecDestroy(g->gcache.exec);
-    if (g->gcache.graph) hipGraphDestroy(g->gcache.graph);
-    if (g->li && g->li != g->lo) hipFree(g->li);
-    if (g->limap && g->limap != g->lomap) hipFree(g->limap);
-    if (g->lo) hipFree(g->lo);
-    if (g->lomap) hipFree(g->lomap);
-    if (g->in_ptr && g->in_ptr != g->out_ptr) hipFree(g->in_ptr);
-    if (g->in_idx && g->in_idx != g->out_idx) hipFree(g->in_idx);
-    if (g->out_ptr) hipFree(g->out_ptr);
-    if (g->out_idx) hipFree(g->out_idx);
+    // teardown: errors here have nowhere to go, the memory is released either way
+    for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+    if (g->gcache.exec) (void)hipGraphExecDestroy(g->gcache.exec);
+    if (g->gcache.graph) (void)hipGraphDestroy(g->gcache.graph);
+    if (g->li && g->li != g->lo) (void)hipFree(g->li);
+    if (g->limap && g->limap != g->lomap) (void)hipFree(g->limap);
+    if (g->lo) (void)hipFree(g->lo);
+    if (g->lomap) (void)hipFree(g->lomap);
+    if (g->in_ptr && g->in_ptr != g->out_ptr) (void)hipFree(g->in_ptr);
+    if (g->in_idx && g->in_idx != g->out_idx) (void)hipFree(g->in_idx);
+    if (g->out_ptr) (void)hipFree(g->out_ptr);
+    if (g->out_idx) (void)hipFree(g->out_idx);
     delete g;
 }
 
@@ -338,8 +339,8 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
                    gc.sel == c.sel && gc.fb == P.maintain_fb && gc.stats == P.stats &&
                    gc.trace == (const void *)P.trace && gc.slot == (const void *)P.host_status;
         if (!hit) {
-            if (gc.exec) { hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
-            if (gc.graph) { hipGraphDestroy(gc.graph); gc.graph = nullptr; }
+            if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
+            if (gc.graph) { (void)hipGraphDestroy(gc.graph); gc.graph = nullptr; }
             gc.valid = false;
             hipStream_t cap;
             HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -350,13 +351,13 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
             }
             hipGraph_t graph = nullptr;
             hipError_t e2 = hipStreamEndCapture(cap, &graph);
-            hipStreamDestroy(cap);
+            (void)hipStreamDestroy(cap);
             if (e != hipSuccess || e2 != hipSuccess)
                 return fail(BFS_EHIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
             hipGraphExec_t exec = nullptr;
             e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             if (e != hipSuccess) {
-                hipGraphDestroy(graph);
+                (void)hipGraphDestroy(graph);
                 return fail(BFS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
             }
             gc.graph = graph;
@@ -535,7 +536,8 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
     g->nnz = (uint32_t)ptr[n];
     g->directed = directed;
     if (hipGetDevice(&g->device) != hipSuccess) { delete g; return fail(BFS_EHIP, "hipGetDevice failed"); }
-    hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, g->device);
+    if (hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess)
+        g->cus = 0;                           // launch sizes then assume 256 compute units
     bfs_status st = upload(&g->out_ptr, ptr.data(), ptr.size(), g->bytes);
     if (st == BFS_OK) st = upload(&g->out_idx, idx.data(), idx.size(), g->bytes);
     if (st == BFS_OK && directed) {
@@ -836,7 +838,7 @@ extern "C" bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *
     HIP_TRY(hipEventCreate(&e1));
     struct EvGuard {
         hipEvent_t a, b;
-        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } guard{e0, e1};
     auto save = [&]() -> bfs_status {
         HIP_TRY(hipMemcpyAsync(snap, workspace, wsz, hipMemcpyDeviceToDevice, s));
