@@ -38,3 +38,25 @@ def test_store_and_lookup(tmp_path):
     (tmp_path / "bad.json").write_text("{not json")
     assert A.lookup(g, 10, str(tmp_path / "bad.json")) == {}
     assert json.load(open(cache))[key]["time_s"] == 1.0
+
+
+def test_selector_level_weights_and_spread():
+    """Training-row weights grow with the level's best time (sqrt, clipped) and
+    ignore levels with no measurement; a deep search keeps evenly spaced
+    levels, first and last included."""
+    import numpy as np
+    from paper_1906_03113_amd import selector as S
+    T = np.log(np.array([[1.0, 2.0, 3.0], [4.0, 4.0, 4.0], [100.0, 50.0, 80.0], [1e-3, 1.0, 1.0],
+                         [1.0, 1.0, 1.0]]))
+    M = np.ones_like(T)
+    M[4] = 0.0                                            # no measurement at all
+    w = S.level_weights(T, M)
+    best = np.array([1.0, 4.0, 50.0, 1e-3])
+    med = np.median(best)
+    want = np.clip(np.sqrt(best / med), 0.25, 4.0)
+    assert np.allclose(w[:4], want) and w[4] == 0.0
+    lv = [{"level": i} for i in range(1000)]
+    kept = S._spread(lv, 300)
+    assert len(kept) == 300 and kept[0]["level"] == 0 and kept[-1]["level"] == 999
+    assert all(a["level"] < b["level"] for a, b in zip(kept, kept[1:]))
+    assert S._spread(lv[:10], 300) == lv[:10]
