@@ -271,6 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
 // lists the rows.  Also clears F_{k-1}'s masks.
 constexpr uint32_t kMsRows = 1024;       // rows per block chunk
 constexpr int32_t kMsSerial = 16;        // longest row one lane scans alone
+constexpr uint32_t kMsGroupRow = 64;     // longest row a group of 16 lanes scans
 
 __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
     __shared__ int32_t s_list[kMsRows];
@@ -390,31 +391,66 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
             if (any) s_list[atomicAdd(&s_n, 1u)] = v;
         }
         __syncthreads();
+        // rows longer than kMsSerial: four at a time per wave, a group of 16
+        // lanes each for rows of up to kMsGroupRow entries, then the longer
+        // ones of the four by the whole wave
         const uint32_t nl = s_nl;
-        for (uint32_t i = wave; i < nl; i += kBlock / 64) {           // long rows: a wave each
-            const int32_t v = s_long[i];
-            const int32_t e0 = p.in_ptr[v], e1 = p.in_ptr[v + 1];
-            unsigned long long *vis = row(p.vis, v, W);
-            unsigned long long *nv = row(nxt, v, W);
-            bool any = false;
-            for (uint32_t w = 0; w < W; ++w) {
-                const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
-                const unsigned long long sv = vis[w];
-                unsigned long long rem = full & ~sv, found = 0ull;
-                for (int32_t eb = e0; eb < e1 && rem; eb += 64) {
-                    const unsigned long long f = scan_step<64>(p, cur, v, w, eb, e1, rem, lk, true);
-                    rem &= ~f;
-                    found |= f;
-                }
-                if (found) {
-                    if (lane == 0) {
-                        nv[w] = found;
-                        vis[w] = sv | found;
+        for (uint32_t i0 = wave * 4u; i0 < nl; i0 += (kBlock / 64) * 4u) {
+            const uint32_t gi = i0 + (lane >> 4), gl = lane & 15u;
+            int32_t v = -1, e0 = 0, e1 = 0;
+            bool wide = false;
+            if (gi < nl) {                                   // uniform in the group
+                v = s_long[gi];
+                e0 = p.in_ptr[v];
+                e1 = p.in_ptr[v + 1];
+                wide = (uint32_t)(e1 - e0) > kMsGroupRow;
+                if (!wide) {
+                    unsigned long long *vis = row(p.vis, v, W);
+                    bool any = false;
+                    for (uint32_t w = 0; w < W; ++w) {
+                        const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+                        const unsigned long long sv = vis[w];
+                        unsigned long long rem = full & ~sv, found = 0ull;
+                        for (int32_t eb = e0; eb < e1 && rem; eb += 16) {
+                            const unsigned long long f = scan_step<16>(p, cur, v, w, eb, e1, rem, lk, true);
+                            rem &= ~f;
+                            found |= f;
+                        }
+                        if (found) {
+                            if (gl == 0) {
+                                row(nxt, v, W)[w] = found;
+                                vis[w] = sv | found;
+                            }
+                            any = true;
+                        }
                     }
-                    any = true;
+                    if (any && gl == 0) s_list[atomicAdd(&s_n, 1u)] = v;
                 }
             }
-            if (any && lane == 0) s_list[atomicAdd(&s_n, 1u)] = v;
+            for (unsigned long long wm = __ballot(wide && gl == 0); wm; wm &= wm - 1ull) {   // uniform
+                const int src = (int)__ffsll((long long)wm) - 1;
+                const int32_t wv = __shfl(v, src, 64), we0 = __shfl(e0, src, 64), we1 = __shfl(e1, src, 64);
+                unsigned long long *vis = row(p.vis, wv, W);
+                bool any = false;
+                for (uint32_t w = 0; w < W; ++w) {
+                    const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+                    const unsigned long long sv = vis[w];
+                    unsigned long long rem = full & ~sv, found = 0ull;
+                    for (int32_t eb = we0; eb < we1 && rem; eb += 64) {
+                        const unsigned long long f = scan_step<64>(p, cur, wv, w, eb, we1, rem, lk, true);
+                        rem &= ~f;
+                        found |= f;
+                    }
+                    if (found) {
+                        if (lane == 0) {
+                            row(nxt, wv, W)[w] = found;
+                            vis[w] = sv | found;
+                        }
+                        any = true;
+                    }
+                }
+                if (any && lane == 0) s_list[atomicAdd(&s_n, 1u)] = wv;
+            }
         }
         __syncthreads();
         if (tid == 0 && s_n) s_base = atomicAdd(&p.cnt[s1], s_n);
