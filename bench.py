@@ -207,6 +207,29 @@ def main():
     modes = {"plain_push": {"gteps": round(gteps, 3), "ms_per_step": round(dt * 1e3, 4),
                             "variant": args.variant, "loop": args.loop}}
     if not args.plain_only:
+        # Theorem 2's short-circuit push (one claim per reached vertex, parents
+        # set by a row pass after the last level); level-kernel time from events
+        sc_kw = dict(kw, variant="short_circuit")
+        P.bfs(G, int(sources[0]), level=level, parent=parent, workspace=ws, **sc_kw)
+        sc_infos = []
+        torch.cuda.synchronize()
+        t0c = time.perf_counter()
+        for k in range(args.steps):
+            for s in sources:
+                info = {}
+                P.bfs(G, int(s), level=level, parent=parent, workspace=ws, info=info,
+                      time_kernels=timek, **sc_kw)
+                sc_infos.append(info)
+        torch.cuda.synchronize()
+        dtc = (time.perf_counter() - t0c) / args.steps
+        modes["push_short_circuit"] = {"gteps": round(total_m / dtc / 1e9, 3),
+                                       "ms_per_step": round(dtc * 1e3, 4), "loop": args.loop}
+        if timek:
+            kus = sum(i["kernel_us"] for i in sc_infos) / (len(sources) * args.steps)
+            modes["push_short_circuit"]["level_kernel_us_per_search"] = round(kus, 2)
+            b_avg = float(sum(4 * nz + 24 * nc for nz, nc in zip(nnz_c, n_c))) / len(sources)
+            modes["push_short_circuit"]["level_kernel_frac_of_hbm"] = round(b_avg / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        log(f"[bench] push, short-circuit: {dtc * 1e3:.3f} ms/step, {total_m / dtc / 1e9:.2f} GTEPS")
         from paper_1906_03113_amd import selector as SEL
         wpath = args.selector or SEL.DEFAULT_WEIGHTS
         sel_variant = "learned" if os.path.exists(wpath) else "heuristic"

@@ -61,7 +61,12 @@ enum {
     BFS_VARIANT_PULL = 1,        /* row-wise over the remaining unvisited rows (first hit)     */
     BFS_VARIANT_PUSH_BITMAP = 2, /* gather the frontier's columns, frontier held as a bitmap  */
     BFS_VARIANT_LEARNED = 3,     /* per level, the selector network's argmin; push fallback   */
-    BFS_VARIANT_HEURISTIC = 4    /* per level, a fixed edge-ratio rule (push <-> pull)        */
+    BFS_VARIANT_HEURISTIC = 4,   /* per level, a fixed edge-ratio rule (push <-> pull)        */
+    BFS_VARIANT_SHORT_CIRCUIT = 5 /* push where the first frontier column to reach a row claims
+                                    it (one bitmap atomicOr, no parent atomic): every reached
+                                    vertex is claimed exactly once (the paper's Theorem 2);
+                                    a row pass after the last level sets each parent to the
+                                    smallest in-neighbour one level up (same results)       */
 };
 
 /* level-loop modes */

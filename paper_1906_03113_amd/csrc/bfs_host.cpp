@@ -251,7 +251,8 @@ bfs_status make_params(bfs_graph *g, int32_t *level, int32_t *parent, const RunC
     P.trace = trace ? (DevLevelRec *)(b + L.trace) : nullptr;
     P.mlp = c.sel;
     P.maintain_fb = (c.policy == kBitmap || c.policy == kLearned || c.policy == kHeuristic) ? 1u : 0u;
-    P.stats = (c.policy == kLearned || c.policy == kHeuristic || trace) ? 1u : 0u;
+    // the level sums also pick the short-circuit levels
+    P.stats = (c.policy == kLearned || c.policy == kHeuristic || c.policy == kShortCircuit || trace) ? 1u : 0u;
     return BFS_OK;
 }
 
@@ -263,7 +264,7 @@ bfs_status resolve_cfg(bfs_graph *g, const bfs_run_options *opt, RunCfg &c) {
     c.heavy = (opt && opt->heavy_degree) ? opt->heavy_degree : 512u;
     c.chunk = (opt && opt->chunk_edges) ? opt->chunk_edges : 1024u;
     c.sel = opt ? opt->selector : nullptr;
-    if (c.policy > kHeuristic) return fail(BFS_EINVAL, "unknown variant %u", c.policy);
+    if (c.policy > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", c.policy);
     if (c.loop > BFS_LOOP_PERSISTENT) return fail(BFS_EINVAL, "unknown loop mode %u", c.loop);
     if (c.heavy < kHeavyFloor) return fail(BFS_EINVAL, "heavy_degree %u below %u", c.heavy, kHeavyFloor);
     if (c.chunk < kChunkFloor || c.chunk > (1u << 20))
@@ -418,6 +419,7 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
         }
     }
     levels_out = level;
+    if (c.policy == kShortCircuit) HIP_TRY(launch_parents(P, c.grid, s));     // the parents, after the levels
     if (opt && opt->trace && P.trace) {
         const uint32_t nrec = std::min<uint32_t>(std::min<uint32_t>(levels_out, kTraceCap), opt->trace_capacity);
         std::vector<DevLevelRec> recs(nrec ? nrec : 1);

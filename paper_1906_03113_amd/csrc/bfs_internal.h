@@ -16,7 +16,7 @@ constexpr int kMlpParams = kMlpIn * kMlpH + kMlpH + kMlpH * kMlpH + kMlpH + kMlp
 // feature normalisation constants live after the weights: mean[12], inv_std[12]
 constexpr int kMlpTotal = kMlpParams + 2 * kMlpIn;
 
-enum Variant : uint32_t { kPush = 0, kPull = 1, kBitmap = 2, kLearned = 3, kHeuristic = 4 };
+enum Variant : uint32_t { kPush = 0, kPull = 1, kBitmap = 2, kLearned = 3, kHeuristic = 4, kShortCircuit = 5 };
 
 // Device-resident search state (first bytes of every workspace).
 struct alignas(256) BfsState {
@@ -139,6 +139,7 @@ hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *root
                        int32_t single_root, hipStream_t s);
 hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s);
 hipError_t launch_finish(const LevelParams &p, hipStream_t s);
+hipError_t launch_parents(const LevelParams &p, uint32_t grid, hipStream_t s);
 hipError_t launch_persistent(const LevelParams &p, uint32_t grid, hipStream_t s);
 uint32_t persistent_max_grid(int device);
 

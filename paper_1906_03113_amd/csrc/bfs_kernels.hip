@@ -133,6 +133,7 @@ __device__ __forceinline__ int mlp_argmin(const float *w, float feat) {
 __device__ __forceinline__ uint32_t decide_wave(const LevelParams &P, const float *w, uint32_t k,
                                                 float fnf, float fsdf, float fnu, float fsdu) {
     if (P.policy == kPush || P.policy == kPull || P.policy == kBitmap) return P.policy;
+    if (P.policy == kShortCircuit) return kPush;
     uint32_t v = kPush;
     if (P.policy == kHeuristic) {
         // pull when the frontier's edges outweigh 1/14 of the unvisited edges
@@ -214,6 +215,7 @@ struct OutLds {
 
 struct LevelPtrs {
     uint32_t k, cs, ns;
+    bool sc;                  // this level claims rows short-circuit (parents set afterwards)
     const uint32_t *vb_cur;
     uint32_t *vb_nxt;
     const uint32_t *fb_cur;
@@ -248,6 +250,7 @@ __device__ __forceinline__ LevelPtrs level_ptrs(const LevelParams &P, uint32_t k
     L.c_cur = odd ? P.cmap[1] : P.cmap[0];
     L.c_nxt = odd ? P.cmap[0] : P.cmap[1];
     L.u_nxt = nullptr;
+    L.sc = false;
     return L;
 }
 
@@ -331,7 +334,18 @@ __device__ __forceinline__ void out_flush(const LevelParams &P, const LevelPtrs 
 // final parent is the minimum over the level's frontier in-neighbours.  The
 // pre-read is a coherent (agent-scope) load, so it sees the other lanes'
 // atomics and most pairs that cannot lower the parent skip the atomic.
-__device__ __forceinline__ bool claim(const LevelParams &P, int32_t i, int32_t j, uint32_t k) {
+//
+// On a short-circuit level (Theorem 2) the first frontier column to reach row
+// i claims it by turning level[i] from -1 to k + 1, so each reached vertex
+// takes exactly one claim and no parent atomic; k_parents sets those parents
+// after the search.  The coherent pre-read of level[i] sees other XCDs'
+// claims, so most losing pairs skip the atomic.
+__device__ __forceinline__ bool claim(const LevelParams &P, const LevelPtrs &L, int32_t i, int32_t j,
+                                      uint32_t k) {
+    if (L.sc) {
+        if (__hip_atomic_load(&P.level[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1) return false;
+        return atomicCAS(&P.level[i], -1, (int32_t)(k + 1)) == -1;
+    }
     const uint32_t p = ld_agent(&P.parent[i]);
     if (p <= (uint32_t)j) return false;
     const uint32_t old = atomicMin(&P.parent[i], (uint32_t)j);
@@ -455,7 +469,7 @@ __device__ __forceinline__ uint32_t mask_word(const LevelPtrs &L, int32_t i) {
 __device__ __forceinline__ void settle(const LevelParams &P, const LevelPtrs &L, OutLds &O,
                                        int32_t i, int32_t j, uint32_t mw) {
     const bool unmasked = (i >= 0) && !((mw >> (i & 31)) & 1u);
-    const bool owner = unmasked && claim(P, i, j, L.k);
+    const bool owner = unmasked && claim(P, L, i, j, L.k);
     append_next(P, L, O, owner, i);
     out_flush(P, L, O, false);
 }
@@ -869,10 +883,15 @@ __device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uin
     __shared__ OutLds ol;
     const BfsState *st = P.st;
     LevelPtrs L = level_ptrs(P, k);
+    // short-circuit claims on the levels whose frontier columns hold at least
+    // n / 8 entries (there atomics bound the level, and the rows they reach
+    // find their parent one level up quickly); the min-select elsewhere
+    L.sc = (P.policy == kShortCircuit) && st->sdf[L.cs] * 8ull >= (unsigned long long)P.n;
     const uint32_t nreg = st->nf[L.cs];
     const unsigned long long hp = st->heavy[L.cs];
     const uint32_t nlong = (uint32_t)hp, nchunks = (uint32_t)(hp >> 32);
-    const uint32_t v = (P.policy == kPush || P.policy == kPull || P.policy == kBitmap)
+    const uint32_t v = (P.policy == kShortCircuit) ? (uint32_t)kPush
+                       : (P.policy == kPush || P.policy == kPull || P.policy == kBitmap)
                            ? P.policy : st->variant;      // decided before the launch
     if (bid == 0 && threadIdx.x == 0) {
         BfsState *w = P.st;
@@ -1120,6 +1139,71 @@ __global__ __launch_bounds__(kBlock) void k_persistent(LevelParams P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) report(P);
 }
 
+// After a short-circuit search: every reached vertex v whose parent is still
+// empty (claimed on a short-circuit level) gets its smallest in-neighbour one
+// level up - the first, in ascending order, with level[u] = level[v] - 1 (one
+// exists: the column that claimed v).  A lane scans the first kParentSerial
+// entries (four loads in flight at a time, positions past the end repeating
+// the last entry); rows not settled by then go to a wave, 64 entries a step,
+// the lowest lane with a hit giving the first.
+constexpr int32_t kParentSerial = 16;
+
+__global__ __launch_bounds__(kBlock) void k_parents(LevelParams P) {
+    __shared__ int32_t s_v[kBlock];
+    __shared__ uint32_t s_n;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    for (uint32_t base = blockIdx.x * kBlock; base < (uint32_t)P.n; base += gridDim.x * kBlock) {
+        if (tid == 0) s_n = 0;
+        __syncthreads();
+        const uint32_t v = base + tid;
+        if (v < (uint32_t)P.n) {
+            const int32_t lv = P.level[v];
+            if (lv > 0 && P.parent[v] == 0xFFFFFFFFu) {
+                const int32_t e0 = P.in_ptr[v], e1 = P.in_ptr[v + 1];
+                const int32_t lim = (e1 - e0 > kParentSerial) ? e0 + kParentSerial : e1;
+                int32_t found = -1;
+                for (int32_t e = e0; e < lim && found < 0; e += 4) {
+                    const int32_t last = lim - 1;
+                    int32_t u[4], l[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) u[t] = P.in_idx[e + t < last ? e + t : last];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) l[t] = P.level[u[t]];
+#pragma unroll
+                    for (int t = 3; t >= 0; --t)
+                        if (l[t] == lv - 1) found = u[t];    // the lowest position wins
+                }
+                if (found >= 0) P.parent[v] = (uint32_t)found;
+                else s_v[atomicAdd(&s_n, 1u)] = (int32_t)v;
+            }
+        }
+        __syncthreads();
+        const uint32_t nl = s_n;
+        for (uint32_t i = wave; i < nl; i += kBlock / 64) {
+            const int32_t w = s_v[i];
+            const int32_t lv = P.level[w];
+            const int32_t e1 = P.in_ptr[w + 1];
+            for (int32_t eb = P.in_ptr[w] + kParentSerial; eb < e1; eb += 64) {   // uniform
+                const int32_t e = eb + (int32_t)lane;
+                int32_t u = -1;
+                bool hit = false;
+                if (e < e1) {
+                    u = P.in_idx[e];
+                    hit = P.level[u] == lv - 1;
+                }
+                const unsigned long long m = __ballot(hit);
+                if (m) {
+                    const int first = (int)__ffsll((long long)m) - 1;
+                    const int32_t uf = __shfl(u, first, 64);
+                    if (lane == 0) P.parent[w] = (uint32_t)uf;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
@@ -1153,6 +1237,11 @@ hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s) {
 
 hipError_t launch_finish(const LevelParams &p, hipStream_t s) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_parents(const LevelParams &p, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_parents, dim3(grid), dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 

@@ -61,9 +61,10 @@ def test_block_diagonal_uneven_graphs(P):
     for b, g in enumerate(gs):
         nz = np.nonzero(g.out_degree() > 0)[0]
         roots.append(int(offs[b] + (nz[0] if len(nz) else 0)))
-    for loop in ("host", "persistent"):
-        say(f"[batch] block-diagonal x{len(gs)} loop={loop}")
-        lv, pa = P.bfs_roots(G, roots, loop=loop)
+    for loop, variant in (("host", "push"), ("persistent", "push"), ("host", "short_circuit"),
+                          ("graph", "short_circuit")):
+        say(f"[batch] block-diagonal x{len(gs)} loop={loop} variant={variant}")
+        lv, pa = P.bfs_roots(G, roots, loop=loop, variant=variant)
         torch.cuda.synchronize()
         lv, pa = lv.cpu().numpy(), pa.cpu().numpy()
         for b, g in enumerate(gs):

@@ -31,7 +31,7 @@ def test_rmat22():
     src = graphgen.pick_sources(g, 64, 22)
     for i, s in enumerate(src[:2]):
         for kw in (dict(variant="push"), dict(variant="learned", selector=w, loop="graph", levels_per_sync=8),
-                   dict(variant="pull"), dict(variant="bitmap")):
+                   dict(variant="pull"), dict(variant="bitmap"), dict(variant="short_circuit")):
             say(f"[full] rmat22 s={s} {kw.get('variant')}")
             _check(g, s, run_gpu(P, G, s, **kw), f"rmat22/{s}/{kw.get('variant')}", cert=(i == 0 and kw["variant"] == "push"))
 
@@ -70,6 +70,6 @@ def test_rmat20_directed():
     w = S.load_weights()
     for i, s in enumerate(graphgen.pick_sources(g, 16, 32)[:2]):
         for kw in (dict(variant="push"), dict(variant="learned", selector=w, loop="graph", levels_per_sync=8),
-                   dict(variant="pull")):
+                   dict(variant="pull"), dict(variant="short_circuit")):
             say(f"[full] rmat20d s={s} {kw.get('variant')}")
             _check(g, s, run_gpu(P, G, s, **kw), f"rmat20d/{s}", cert=(i == 0))

@@ -15,7 +15,7 @@ from tests.gpu_common import assert_same, need_gpu, run_gpu, say
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["push", "pull", "bitmap", "heuristic"]
+VARIANTS = ["push", "pull", "bitmap", "heuristic", "short_circuit"]
 
 
 def _graphs():
@@ -70,7 +70,7 @@ def test_loop_modes(P, graphs, loop):
         g = graphs[name]
         G = P.Graph.from_graphgen(g)
         for s in graphgen.pick_sources(g, 2, 23):
-            for v in ("push", "heuristic"):
+            for v in ("push", "heuristic", "short_circuit"):
                 say(f"[parity] {name} s={s} loop={loop} variant={v}")
                 assert_same(g, s, run_gpu(P, G, s, variant=v, loop=loop, levels_per_sync=3),
                             f"{name}/{s}/{loop}/{v}")
@@ -82,7 +82,7 @@ def test_split_columns_and_grid_shapes(P, graphs):
     G = P.Graph.from_graphgen(g)
     s = int(graphgen.pick_sources(g, 1, 5)[0])
     for heavy, chunk, grid in ((32, 64, 1), (32, 64, 7), (64, 1024, 333), (100000, 1024, 2048)):
-        for v in ("push", "bitmap"):
+        for v in ("push", "bitmap", "short_circuit"):
             say(f"[parity] rmat14 s={s} heavy={heavy} chunk={chunk} grid={grid} {v}")
             assert_same(g, s, run_gpu(P, G, s, variant=v, heavy_degree=heavy, chunk_edges=chunk,
                                       grid_blocks=grid), f"split/{heavy}/{chunk}/{grid}")
