@@ -126,11 +126,19 @@ def many_graphs(count: int = 64, tune_cache: str = "", log=print) -> Dict:
     local = [int(r - offs[b]) for b, r in enumerate(roots)]
     params: List[Dict] = [{} for _ in gs]
     if tune_cache:
+        # each distinct graph shape tuned once (on its first graph), then looked up
         from . import autotune as AT
+        tuned_keys = set()
         for b, (g, G) in enumerate(zip(gs, Gs)):
             info = {}
             P.bfs(G, local[b], info=info)
+            key = AT.shape_key(G, int(info["levels"]))
+            if key not in tuned_keys:
+                AT.tune(G, [local[b]], budget=10, cache=tune_cache, variant_kw={"variant": "push"})
+                tuned_keys.add(key)
             params[b] = AT.lookup(G, int(info["levels"]), tune_cache)
+        res["tuned_shapes"] = len(tuned_keys)
+        log(f"[graphs] tuned {len(tuned_keys)} graph shapes")
 
     def separate(tuned: bool):
         for b, G in enumerate(Gs):
