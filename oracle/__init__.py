@@ -16,6 +16,9 @@ Contents
   * ``brute``       (O-D, numpy): levels from Boolean matrix powers.
   * ``certify``     (I1-I4): a complete O(n + nnz) certificate for (level, parent).
   * ``mlp_ref``     float64 reference of the variant-selector network.
+  * ``compare``     the searches the Experiments section compares against
+                    (SpMV-BFS, SpMSpV-BFS, SpMmSpV-BFS) and the method, step by
+                    step, with their algebraic operation counts (Table 2).
 
 The result every function returns (Theorem 1 gives the levels; the parent tie
 rule picks the smallest frontier in-neighbour):
