@@ -348,7 +348,6 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             for (uint32_t l = 0; l < L && e == hipSuccess; ++l) {
                 e = launch_level(P, c.grid, cap);
-                if (e == hipSuccess) e = launch_finish(P, cap);
             }
             hipGraph_t graph = nullptr;
             hipError_t e2 = hipStreamEndCapture(cap, &graph);
@@ -400,7 +399,6 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
                 }
                 HIP_TRY(launch_level(P, c.grid, s));
                 if (tk) HIP_TRY(hipEventRecord(e1, s));
-                HIP_TRY(launch_finish(P, s));
                 ++launched;
             }
             bfs_status st = wait_progress(hs, s, done, level);
@@ -904,11 +902,9 @@ extern "C" bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *
         // is the one a good per-level choice produces
         st = restore();
         if (st != BFS_OK) return st;
-        HIP_TRY(hipMemcpy(&P.st->variant, &fastest, sizeof fastest, hipMemcpyHostToDevice));
         LevelParams Pc = P;
         Pc.policy = fastest;
         HIP_TRY(launch_level(Pc, c.grid, s));
-        HIP_TRY(launch_finish(Pc, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     *count = n_out;

@@ -138,7 +138,6 @@ MsLayout ms_layout(int32_t n, int32_t nq);
 hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *roots_dev,
                        int32_t single_root, hipStream_t s);
 hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s);
-hipError_t launch_finish(const LevelParams &p, hipStream_t s);
 hipError_t launch_parents(const LevelParams &p, uint32_t grid, hipStream_t s);
 hipError_t launch_persistent(const LevelParams &p, uint32_t grid, hipStream_t s);
 uint32_t persistent_max_grid(int device);

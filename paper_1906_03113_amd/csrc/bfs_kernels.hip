@@ -164,24 +164,28 @@ __device__ __forceinline__ LevelStats level_stats(const LevelParams &P, uint32_t
     return L;
 }
 
-// One block of one wave: lane 0 reads the counters of level k, the wave
-// decides, lane 0 records the form in the state.
-// The network's weights are first staged in LDS with coalesced loads (its
-// evaluation then reads LDS only).
-__device__ __forceinline__ void decide_level(const LevelParams &P, uint32_t k) {
-    __shared__ LevelStats s_ls;
-    __shared__ float s_w[kMlpTotal];
+// The form of level k from its counters L, by the first wave of the calling
+// block (every thread of the block calls it), recorded in the state.  The
+// network's weights are first staged in the LDS buffer s_w (kMlpTotal floats)
+// with coalesced loads by the whole block; its evaluation then reads LDS only.
+__device__ __forceinline__ void decide_level(const LevelParams &P, uint32_t k, const LevelStats &L,
+                                             float *s_w) {
     const bool net = (P.policy == kLearned) && P.mlp != nullptr;
-    if (threadIdx.x == 0) s_ls = level_stats(P, k);
-    if (net && threadIdx.x < 64)
-        for (uint32_t i = threadIdx.x; i < (uint32_t)kMlpTotal; i += 64) s_w[i] = P.mlp[i];
+    if (net)
+        for (uint32_t i = threadIdx.x; i < (uint32_t)kMlpTotal; i += blockDim.x) s_w[i] = P.mlp[i];
     __syncthreads();
     if (threadIdx.x < 64) {
-        const LevelStats L = s_ls;
         const uint32_t v = decide_wave(P, s_w, k, L.nf, L.sdf, L.nu, L.sdu);
         if (threadIdx.x == 0) P.st->variant = v;
     }
     __syncthreads();
+}
+
+// The form level k runs: the forced one, or the one decided before it.
+__device__ __forceinline__ uint32_t level_form(const LevelParams &P, uint32_t decided) {
+    if (P.policy == kShortCircuit) return kPush;
+    if (P.policy == kPush || P.policy == kPull || P.policy == kBitmap) return P.policy;
+    return decided;
 }
 
 // ---------------------------------------------------------------------------
@@ -839,27 +843,35 @@ __device__ __forceinline__ void pull_level(const LevelParams &P, LevelPtrs &L, P
     }
 }
 
-// End of level k, one thread: fold the level's counters into the state and
-// advance.  Only called when F_k was nonempty, so extra launches after the
-// end of the search are no-ops.
-__device__ __forceinline__ void finish_level(const LevelParams &P, uint32_t k, uint32_t nf) {
+// The counters of level k + 1 as the close of level k leaves them.
+struct Closed {
+    LevelStats s;
+    uint32_t nf;              // |F_{k+1}| (list entries plus long columns)
+};
+
+// End of level k, one thread: fold the level's counters into the state,
+// advance, and return the next level's counters.  Only called when F_k was
+// nonempty, so launches after the end of the search change nothing.
+__device__ __forceinline__ Closed finish_level(const LevelParams &P, uint32_t k, uint32_t nf) {
     BfsState *st = P.st;
     const uint32_t cs = k & 3, ns = (k + 1) & 3;
     const uint32_t nf_next = ld_agent(&st->nf[ns]) + (uint32_t)ld_agent64(&st->heavy[ns]);
     const unsigned long long sdf_next = ld_agent64(&st->sdf[ns]);
-    const uint32_t variant = ld_agent(&st->variant);
+    const uint32_t variant = level_form(P, ld_agent(&st->variant));
+    const uint32_t vc = ld_agent(&st->visited_cnt);
+    const unsigned long long vd = ld_agent64(&st->visited_deg);
     if (P.trace) {
         DevLevelRec r;
         r.level = k;
         r.variant = variant;
         r.nf = nf;
-        r.nu = (uint32_t)P.n - st->visited_cnt;
-        r.sdf = st->sdf[cs];
-        r.sdu = (unsigned long long)P.nnz - st->visited_deg;
+        r.nu = (uint32_t)P.n - vc;
+        r.sdf = ld_agent64(&st->sdf[cs]);
+        r.sdu = (unsigned long long)P.nnz - vd;
         P.trace[k % kTraceCap] = r;
     }
-    st->visited_cnt += nf_next;
-    st->visited_deg += sdf_next;
+    st->visited_cnt = vc + nf_next;
+    st->visited_deg = vd + sdf_next;
     if (variant == kPull) {
         st->u_buf ^= 1u;
         st->u_len = ld_agent(&st->u_wr);
@@ -867,17 +879,29 @@ __device__ __forceinline__ void finish_level(const LevelParams &P, uint32_t k, u
     st->u_wr = 0;
     __threadfence();
     st->level = k + 1;
+    Closed c;
+    c.nf = nf_next;
+    c.s.nf = (float)nf_next;
+    c.s.sdf = (float)sdf_next;
+    c.s.nu = (float)((uint32_t)P.n - (vc + nf_next));
+    c.s.sdu = (float)((unsigned long long)P.nnz - (vd + sdf_next));
+    return c;
 }
 
 __device__ __forceinline__ uint32_t frontier_size(const BfsState *st, uint32_t slot) {
     return st->nf[slot] + (uint32_t)st->heavy[slot];
 }
 
-__device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uint32_t bid, uint32_t nblocks) {
-    __shared__ union {
-        TileLds t;                            // push / push-bitmap
-        PullLds p;                            // pull
-    } lds;
+// The level kernels' LDS: one level's tiles, or, once the level is done, the
+// network's weights for the next level's decision.
+union LevelLds {
+    TileLds t;                                // push / push-bitmap
+    PullLds p;                                // pull
+    float w[kMlpTotal];                       // decision of the next level's form
+};
+
+__device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uint32_t bid, uint32_t nblocks,
+                                           LevelLds &lds) {
     TileLds &tl = lds.t;
     PullLds &pl = lds.p;
     __shared__ OutLds ol;
@@ -890,9 +914,7 @@ __device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uin
     const uint32_t nreg = st->nf[L.cs];
     const unsigned long long hp = st->heavy[L.cs];
     const uint32_t nlong = (uint32_t)hp, nchunks = (uint32_t)(hp >> 32);
-    const uint32_t v = (P.policy == kShortCircuit) ? (uint32_t)kPush
-                       : (P.policy == kPush || P.policy == kPull || P.policy == kBitmap)
-                           ? P.policy : st->variant;      // decided before the launch
+    const uint32_t v = level_form(P, st->variant);     // decided before the launch
     if (bid == 0 && threadIdx.x == 0) {
         BfsState *w = P.st;
         const uint32_t fs = (k + 2) & 3;     // slot of level k+2: free since level k-2
@@ -1018,35 +1040,89 @@ __global__ __launch_bounds__(kBlock) void k_init_roots(LevelParams P, int32_t nr
     out_flush(P, L, ol, true);
 }
 
+// s_waitcnt immediate (gfx9 encoding) that waits for vmcnt = 0 only:
+// vmcnt bits [3:0] and [15:14] zero, expcnt [6:4] = 7 and lgkmcnt [11:8] = 15
+// (no wait on those).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// The block that arrives last at the end of a level launch.  Blocks arrive
+// on one of kBarGroups counters (block b on b % kBarGroups, each counter on its
+// own line), the last of each group on the top counter; the block completing
+// the top counter has seen every block of the launch finish its part of the
+// level.  Nobody waits, and every counter is back at zero afterwards.
+// What the closing block reads are counters that the level's blocks changed
+// with atomics, so an arrival only has to come after its block's atomics have
+// been performed: every wave drains its outstanding memory operations
+// (s_waitcnt vmcnt(0)) before the block barrier, and no cache fence is needed
+// on the way in (a device-scope fence per block would write back and
+// invalidate the L2 under every other block still running).  The level's
+// other writes reach the next level at the launch boundary.
+__device__ __forceinline__ bool last_to_arrive(BfsState *st, uint32_t nblocks) {
+    __shared__ uint32_t s_last;
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t groups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
+        const uint32_t g = blockIdx.x % groups;
+        const uint32_t in_group = (nblocks - g + groups - 1) / groups;
+        uint32_t last = 0;
+        if (atomicAdd(&st->bar_group[g * 16], 1u) == in_group - 1) {
+            __hip_atomic_store(&st->bar_group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (atomicAdd(&st->bar_top, 1u) == groups - 1) {
+                __hip_atomic_store(&st->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = 1;
+            }
+        }
+        s_last = last;
+    }
+    __syncthreads();
+    return s_last != 0;
+}
+
+// Progress for the host: the level the search stands at and its frontier
+// size (0 once the search is over).
+__device__ __forceinline__ void report_status(const LevelParams &P, uint32_t level, uint32_t nf) {
+    P.host_status[0] = level;
+    P.host_status[1] = nf;
+}
+
+// Close level k (every block of the level is done): fold the counters, decide
+// the next level's form, report.  Called by every thread of one block; s_w is
+// that block's LDS (kMlpTotal floats), free by now.
+__device__ __forceinline__ void close_level(const LevelParams &P, uint32_t k, uint32_t nf, float *s_w) {
+    __shared__ Closed s_c;
+    if (threadIdx.x == 0) {
+        __threadfence();                                     // see every block's part
+        s_c = finish_level(P, k, nf);
+    }
+    __syncthreads();
+    const Closed c = s_c;
+    if (c.nf != 0 && (P.policy == kLearned || P.policy == kHeuristic)) decide_level(P, k + 1, c.s, s_w);
+    if (threadIdx.x == 0) report_status(P, k + 1, c.nf);
+}
+
+// One level: the level body on every block, then the last block to finish
+// closes the level, so a level is one launch.  Launches after the end of the
+// search (empty frontier) return at once.
 __global__ __launch_bounds__(kBlock, 8) void k_level(LevelParams P) {
-    const BfsState *st = P.st;
-    const uint32_t k = st->level;
-    if (frontier_size(st, k & 3) == 0) return;
-    level_body(P, k, blockIdx.x, gridDim.x);
-}
-
-__device__ __forceinline__ void report(const LevelParams &P) {
-    const BfsState *st = P.st;
-    const uint32_t k = ld_agent(&st->level);
-    P.host_status[0] = k;
-    P.host_status[1] = ld_agent(&st->nf[k & 3]) + (uint32_t)ld_agent64(&st->heavy[k & 3]);
-    __threadfence_system();
-}
-
-// One thread closes level k after the level kernel (stream order) and tells
-// the host where the search stands.
-__global__ void k_finish(LevelParams P) {
-    const BfsState *st = P.st;
+    __shared__ LevelLds lds;
+    BfsState *st = P.st;
     const uint32_t k = st->level;
     const uint32_t nf = frontier_size(st, k & 3);
-    if (threadIdx.x == 0 && nf != 0) finish_level(P, k, nf);
-    __syncthreads();
-    if (nf != 0) decide_level(P, k + 1);     // the form of the next level
-    if (threadIdx.x == 0) report(P);
+    if (nf == 0) return;
+    level_body(P, k, blockIdx.x, gridDim.x, lds);
+    if (last_to_arrive(st, gridDim.x)) close_level(P, k, nf, lds.w);
 }
 
 // The form of level 0 (after the init kernels).
-__global__ void k_decide(LevelParams P) { decide_level(P, 0); }
+__global__ void k_decide(LevelParams P) {
+    __shared__ LevelStats s_ls;
+    __shared__ float s_w[kMlpTotal];
+    if (threadIdx.x == 0) s_ls = level_stats(P, 0);
+    __syncthreads();
+    const LevelStats L = s_ls;
+    decide_level(P, 0, L, s_w);
+}
 
 // Grid barrier for the cooperative kernel, with the level's closing work done
 // inside it.  Blocks arrive on one of kBarGroups counters (block b on group
@@ -1060,7 +1136,7 @@ __global__ void k_decide(LevelParams P) { decide_level(P, 0); }
 // line.  Returns false only if a spin limit runs out, which cannot happen when
 // every block is resident.
 __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, uint32_t nf, uint32_t nblocks,
-                              uint32_t *s_role) {
+                              uint32_t *s_role, float *s_w) {
     BfsState *st = P.st;
     const uint32_t groups = nblocks < (uint32_t)kBarGroups ? nblocks : (uint32_t)kBarGroups;
     const uint32_t g = blockIdx.x % groups;
@@ -1086,12 +1162,7 @@ __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, 
     }
     __syncthreads();
     const uint32_t role = *s_role;
-    if (role == 2) {                                         // every block is done with level k
-        __threadfence();
-        if (threadIdx.x == 0) finish_level(P, k, nf);
-        __syncthreads();
-        decide_level(P, k + 1);
-    }
+    if (role == 2) close_level(P, k, nf, s_w);               // every block is done with level k
     __syncthreads();
     uint32_t ok = 1;
     if (threadIdx.x == 0) {
@@ -1127,16 +1198,20 @@ __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, 
 // block reads the same counters after a barrier).
 __global__ __launch_bounds__(kBlock) void k_persistent(LevelParams P) {
     __shared__ uint32_t s_role;
+    __shared__ LevelLds lds;
     BfsState *st = P.st;
     const uint32_t nb = gridDim.x;
     for (;;) {
         const uint32_t k = ld_agent(&st->level);
         const uint32_t nf = ld_agent(&st->nf[k & 3]) + (uint32_t)ld_agent64(&st->heavy[k & 3]);
         if (nf == 0) break;
-        level_body(P, k, blockIdx.x, nb);
-        if (!level_barrier(P, k, nf, nb, &s_role)) break;
+        level_body(P, k, blockIdx.x, nb, lds);
+        if (!level_barrier(P, k, nf, nb, &s_role, lds.w)) break;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) report(P);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t k = ld_agent(&st->level);
+        report_status(P, k, ld_agent(&st->nf[k & 3]) + (uint32_t)ld_agent64(&st->heavy[k & 3]));
+    }
 }
 
 // After a short-circuit search: every reached vertex v whose parent is still
@@ -1232,11 +1307,6 @@ hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *root
 
 hipError_t launch_level(const LevelParams &p, uint32_t grid, hipStream_t s) {
     hipLaunchKernelGGL(k_level, dim3(grid), dim3(kBlock), 0, s, p);
-    return hipGetLastError();
-}
-
-hipError_t launch_finish(const LevelParams &p, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
