@@ -256,6 +256,48 @@ bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *level, int3
                               int32_t reps, bfs_level_record *records, uint32_t capacity,
                               uint32_t *count, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * The comparison searches (Experiments section, Table 2).  Not the method:
+ * the searches the paper measures its algebraic operation count against,
+ * each with a device count of its operations (two per nonzero multiplied;
+ * one step per level, the last step reaching nothing).  They compute the same
+ * level / parent as bfs_run.
+ *   BFS_COMPARE_SPMV    SpMV-BFS: every nonzero of A^T is multiplied at every
+ *                       step with the dense frontier indicator (row form over
+ *                       the graph's CSC).
+ *                       ops = 2 nnz (eccentricity(s) + 1).
+ *   BFS_COMPARE_SPMSPV  SpMSpV-BFS: the vector is not masked, x_{k+1} = A^T x_k
+ *                       over all of supp(x_k) (the vertices a walk of exactly k
+ *                       edges reaches from s); visited vertices only decide
+ *                       levels.
+ *   BFS_COMPARE_SPMMSPV SpMmSpV-BFS: the frontier's columns are multiplied in
+ *                       full and the visited test follows the product.
+ *                       ops = 2 nnz_c.
+ * (The method itself multiplies once per reached vertex: 2 (n_c - 1).)
+ * ------------------------------------------------------------------------ */
+enum {
+    BFS_COMPARE_SPMV = 0,
+    BFS_COMPARE_SPMSPV = 1,
+    BFS_COMPARE_SPMMSPV = 2
+};
+
+/* Workspace bytes for bfs_run_compare (0 when g is NULL); about 20 n bytes. */
+size_t bfs_compare_workspace_size(const bfs_graph *g);
+
+/*
+ * One comparison search from `source` (Experiments section).  level / parent:
+ * device int32[n], caller-owned, results as bfs_run.  workspace: device, at
+ * least bfs_compare_workspace_size(g) bytes, 256-byte aligned.  ops / steps:
+ * host pointers (either may be NULL) that receive the operation count and the
+ * number of steps.  The call waits for hip_stream (it reads the device's
+ * progress after every eight steps).
+ * Errors: BFS_EINVAL (NULL argument, unknown method, small or misaligned
+ * workspace), BFS_ERANGE (source outside [0, n)), BFS_EHIP.
+ */
+bfs_status bfs_run_compare(bfs_graph *g, int32_t source, uint32_t method, int32_t *level,
+                           int32_t *parent, void *workspace, size_t ws_bytes, uint64_t *ops,
+                           uint32_t *steps, void *hip_stream);
+
 /* Static text for a status code. */
 const char *bfs_status_string(bfs_status s);
 

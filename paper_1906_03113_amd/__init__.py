@@ -18,7 +18,7 @@ import numpy as np
 from . import _lib
 from ._lib import BfsError, LOOPS, VARIANTS, VARIANT_NAMES, LevelRecord, RunOptions
 
-__all__ = ["Graph", "bfs", "bfs_batch", "bfs_roots", "BfsError", "VARIANTS", "LOOPS",
+__all__ = ["Graph", "bfs", "bfs_batch", "bfs_roots", "bfs_compare", "compare_workspace_size", "BfsError", "VARIANTS", "LOOPS",
            "Workspace", "make_options"]
 
 
@@ -234,3 +234,29 @@ def bfs_batch(graphs, sources: Sequence[int], variant="push", loop="host", level
     _lib.check(_lib.lib().bfs_run_batch(nq, H, S, Lp, Pp, ctypes.byref(o), workspace.ptr,
                                         workspace.nbytes, _stream_handle(stream)))
     return levels, parents
+
+
+def compare_workspace_size(g: Graph) -> int:
+    return int(_lib.lib().bfs_compare_workspace_size(g.handle))
+
+
+def bfs_compare(g: Graph, source: int, method: str, level=None, parent=None,
+                workspace: Optional[Workspace] = None, stream=None):
+    """One of the Experiments section's comparison searches ("spmv", "spmspv",
+    "spmmspv").  Returns (level, parent, ops, steps); waits for the stream."""
+    t = _torch()
+    if level is None:
+        level = t.empty(g.n, dtype=t.int32, device="cuda")
+    if parent is None:
+        parent = t.empty(g.n, dtype=t.int32, device="cuda")
+    need = compare_workspace_size(g)
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need)
+    ops = ctypes.c_uint64(0)
+    steps = ctypes.c_uint32(0)
+    _lib.check(_lib.lib().bfs_run_compare(g.handle, int(source), _lib.COMPARE[method],
+                                          ctypes.c_void_p(level.data_ptr()),
+                                          ctypes.c_void_p(parent.data_ptr()), workspace.ptr,
+                                          workspace.nbytes, ctypes.byref(ops), ctypes.byref(steps),
+                                          _stream_handle(stream)))
+    return level, parent, int(ops.value), int(steps.value)

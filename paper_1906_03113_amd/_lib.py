@@ -13,6 +13,7 @@ BFS_DIRECTED, BFS_INPUT_ON_DEVICE, BFS_VALIDATE_TRANSPOSE = 1, 2, 4
 VARIANTS = {"push": 0, "pull": 1, "bitmap": 2, "learned": 3, "heuristic": 4, "short_circuit": 5}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 LOOPS = {"host": 0, "graph": 1, "persistent": 2}
+COMPARE = {"spmv": 0, "spmspv": 1, "spmmspv": 2}
 
 
 class LevelRecord(ctypes.Structure):
@@ -92,6 +93,11 @@ def _optional(L):
     L.bfs_profile_levels.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, i32,
                                      ctypes.POINTER(LevelRecord), u32, ctypes.POINTER(u32), vp]
     L.bfs_profile_levels.restype = i32
+    L.bfs_compare_workspace_size.argtypes = [vp]
+    L.bfs_compare_workspace_size.restype = sz
+    L.bfs_run_compare.argtypes = [vp, i32, u32, vp, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(u32), vp]
+    L.bfs_run_compare.restype = i32
 
 
 def check(status: int) -> None:

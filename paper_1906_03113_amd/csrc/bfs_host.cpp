@@ -910,3 +910,74 @@ extern "C" bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *
     *count = n_out;
     return BFS_OK;
 }
+
+// ---------------------------------------------------------------------------
+// The comparison searches of the Experiments section
+// ---------------------------------------------------------------------------
+
+extern "C" size_t bfs_compare_workspace_size(const bfs_graph *g) {
+    if (!g) return 0;
+    return cmp_layout(g->n).total;
+}
+
+extern "C" bfs_status bfs_run_compare(bfs_graph *g, int32_t source, uint32_t method, int32_t *level,
+                                      int32_t *parent, void *workspace, size_t ws_bytes,
+                                      uint64_t *ops, uint32_t *steps, void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (!level || !parent || !workspace) return fail(BFS_EINVAL, "level/parent/workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BFS_EINVAL, "workspace must be 256-byte aligned");
+    if (method > kCmpSpmmspv) return fail(BFS_EINVAL, "unknown comparison method %u", method);
+    if (source < 0 || source >= g->n) return fail(BFS_ERANGE, "source %d outside [0, %d)", source, g->n);
+    const CmpLayout L = cmp_layout(g->n);
+    if (ws_bytes < L.total) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    HostSlot *hs = nullptr;
+    bfs_status st0 = host_slot(hs);
+    if (st0 != BFS_OK) return st0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *b = (char *)workspace;
+    CmpParams P{};
+    P.n = g->n;
+    P.words = (uint32_t)(((size_t)g->n + 31) / 32);
+    P.method = method;
+    P.out_ptr = g->out_ptr;
+    P.out_idx = g->out_idx;
+    P.in_ptr = g->in_ptr;
+    P.in_idx = g->in_idx;
+    P.lo = g->lo;
+    P.li = g->li;
+    P.lomap = g->lomap;
+    P.limap = g->limap;
+    P.nlo_chunks = g->nlo_chunks;
+    P.nli_chunks = g->nli_chunks;
+    P.level = level;
+    P.parent = parent;
+    P.y = (unsigned long long *)(b + L.y);
+    P.list[0] = (int32_t *)(b + L.l0);
+    P.list[1] = (int32_t *)(b + L.l1);
+    P.touched = (int32_t *)(b + L.touched);
+    P.xb[0] = (uint32_t *)(b + L.x0);
+    P.xb[1] = (uint32_t *)(b + L.x1);
+    P.st = (CmpState *)(b + L.state);
+    P.host_status = hs->d;
+    hs->h[0] = 0;
+    hs->h[1] = 1;
+    const uint32_t grid = (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
+    HIP_TRY(launch_cmp_init(P, source, s));
+    // steps are launched eight at a time between progress checks; steps after
+    // the one that reaches nothing return at once
+    const uint64_t max_steps = (uint64_t)g->n + 2;
+    bool done = false;
+    for (uint64_t issued = 0; !done; issued += 8) {
+        if (issued > max_steps) return fail(BFS_EHIP, "comparison search did not terminate");
+        for (int l = 0; l < 8; ++l) HIP_TRY(launch_cmp_step(P, grid, s));
+        uint32_t lv = 0;
+        bfs_status st = wait_progress(hs, s, done, lv);
+        if (st != BFS_OK) return st;
+    }
+    CmpState hst;
+    HIP_TRY(hipMemcpyAsync(&hst, P.st, sizeof hst, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ops) *ops = (uint64_t)hst.ops;
+    if (steps) *steps = hst.k;
+    return BFS_OK;
+}

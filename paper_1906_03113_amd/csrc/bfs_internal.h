@@ -144,6 +144,43 @@ uint32_t persistent_max_grid(int device);
 
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s);
 
+// The comparison searches of the Experiments section (bfs_compare.hip).
+enum CmpMethod : uint32_t { kCmpSpmv = 0, kCmpSpmspv = 1, kCmpSpmmspv = 2 };
+
+struct alignas(256) CmpState {
+    uint32_t k;                    // step
+    uint32_t nlist;                // entries of the step's vector list
+    uint32_t ntouched;             // rows first touched by the step's product
+    uint32_t nnext;                // rows reached by the step
+    uint32_t done;                 // set once a step reaches nothing
+    uint32_t pad;
+    unsigned long long ops;        // algebraic operations so far (two per nonzero multiplied)
+};
+
+struct CmpParams {
+    int32_t n;
+    uint32_t words;                // 32-bit words per bitmap
+    uint32_t method;               // CmpMethod
+    const int32_t *out_ptr, *out_idx, *in_ptr, *in_idx;
+    const MsLong *lo, *li;         // the graph's split long columns / rows
+    const uint32_t *lomap, *limap;
+    uint32_t nlo_chunks, nli_chunks;
+    int32_t *level, *parent;
+    unsigned long long *y;         // [n] the product, step-keyed (see bfs_compare.hip)
+    int32_t *list[2];              // vector lists, step k reads list[k & 1]
+    int32_t *touched;              // the product's support (SpMmSpV, SpMV long rows)
+    uint32_t *xb[2];               // vector membership bitmaps, step k reads xb[k & 1]
+    CmpState *st;
+    uint32_t *host_status;         // pinned: [0] steps done, [1] rows reached by the last step
+};
+
+struct CmpLayout {
+    size_t state, y, l0, l1, touched, x0, x1, total;
+};
+CmpLayout cmp_layout(int32_t n);
+hipError_t launch_cmp_init(const CmpParams &p, int32_t source, hipStream_t s);
+hipError_t launch_cmp_step(const CmpParams &p, uint32_t grid, hipStream_t s);
+
 hipError_t launch_mlp_forward(const float *w, const float *x, float *y, int32_t rows, hipStream_t s);
 hipError_t launch_mlp_grad(const float *w, const float *x, const float *t, const float *mask,
                            int32_t rows, float inv_norm, float *grad, float *loss, hipStream_t s);

@@ -1,7 +1,7 @@
 """The batching measurements: many sources on one graph in one call, and many
 uneven graphs in one launch.
 
-    python -m paper_1906_03113_amd.experiments [--only sources|graphs] [--out FILE]
+    python -m paper_1906_03113_amd.experiments [--only sources|graphs|compare] [--out FILE]
 
 * sources: directed R-MAT scale 20 (edgefactor 16, out-edges), 256 sources of
   nonzero out-degree (seed 41) in one bfs_run_batch call (4 mask words per
@@ -13,6 +13,10 @@ uneven graphs in one launch.
   roots (persistent kernel, and the graph loop), against 64 separate searches
   on the separate graphs (plain push with the defaults, and with each graph's
   launch parameters from the tuning cache when one is given).
+
+* compare: the Experiments section's comparison searches (SpMV-BFS, SpMSpV-BFS,
+  SpMmSpV-BFS) against the method on ER n=16,384, directed R-MAT s20, R-MAT
+  s22 and 1024^2 / 4096^2 grids: operation counts and time per search.
 
 Throughput is GTEPS = sum over the searches of m_c (edges of the reached
 component; each undirected edge once, each directed edge once) / wall time,
@@ -164,10 +168,55 @@ def many_graphs(count: int = 64, tune_cache: str = "", log=print) -> Dict:
     return res
 
 
+def compare(workloads=("er16k", "rmat20d", "rmat22", "grid1024", "grid4096"), log=print) -> Dict:
+    """The comparison searches of the Experiments section against the method
+    (plain push, and the short-circuit form), one source per graph (the first
+    of pick_sources(g, 1, 22)): device operation counts (Table 2's
+    convention) and wall time per search, best of 3 after a warm-up.  The
+    unmasked SpMSpV-BFS is left out on the 4096^2 grid (its vector covers the
+    component within a few hundred of the ~7,000 steps)."""
+    import graphgen
+    import paper_1906_03113_amd as P
+    torch = _torch()
+    res = {}
+    for w in workloads:
+        g = graphgen.grid(1024, 0.9, 3) if w == "grid1024" else graphgen.workload(w)
+        G = P.Graph.from_graphgen(g)
+        s = int(graphgen.pick_sources(g, 1, 22)[0])
+        lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        pa = torch.empty_like(lv)
+        ws = P.Workspace(P.compare_workspace_size(G))
+        row = {"n": g.n, "nnz": g.nnz, "source": s}
+        for m in ("spmv", "spmspv", "spmmspv"):
+            if m == "spmspv" and w == "grid4096":
+                continue
+            box = {}
+
+            def run(m=m, box=box):
+                box["r"] = P.bfs_compare(G, s, m, level=lv, parent=pa, workspace=ws)
+            t = _timed(run)
+            _, _, ops, steps = box["r"]
+            row[m] = {"ms": t * 1e3, "ops": ops, "steps": steps}
+            log(f"[compare] {w} {m}: {t * 1e3:.2f} ms, ops {ops}, steps {steps}")
+        ws1 = P.Workspace(G.workspace_size(1))
+        deep = w.startswith("grid")
+        for v in ("push", "short_circuit"):
+            kw = dict(variant=v, loop="graph", levels_per_sync=64 if deep else 8)
+            t = _timed(lambda kw=kw: P.bfs(G, s, level=lv, parent=pa, workspace=ws1, **kw))
+            n_c = int((lv >= 0).sum().item())
+            row[v] = {"ms": t * 1e3, "ops": 2 * (n_c - 1)}
+            log(f"[compare] {w} method ({v}): {t * 1e3:.2f} ms, ops {2 * (n_c - 1)}")
+        res[w] = row
+        G.close()
+        del ws, ws1, lv, pa
+        torch.cuda.empty_cache()
+    return res
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="batching measurements (many sources, many graphs)")
-    ap.add_argument("--only", choices=["sources", "graphs"], default=None)
+    ap.add_argument("--only", choices=["sources", "graphs", "compare"], default=None)
     ap.add_argument("--tune-cache", default="", help="autotune cache for per-graph parameters")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -179,6 +228,8 @@ def main(argv=None):
         out["many_sources"] = many_sources(log=log)
     if a.only in (None, "graphs"):
         out["many_graphs"] = many_graphs(tune_cache=a.tune_cache, log=log)
+    if a.only in (None, "compare"):
+        out["compare"] = compare(log=log)
     txt = json.dumps(out)
     if a.out:
         with open(a.out, "w") as f:

@@ -96,3 +96,13 @@ def test_no_cpu_fallback_in_product_package():
             if f.endswith(".py"):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_compare_entry_points_reject_bad_arguments(L):
+    from paper_1906_03113_amd import _lib as B
+    assert L.bfs_compare_workspace_size(None) == 0
+    ops = ctypes.c_uint64(7)
+    steps = ctypes.c_uint32(7)
+    rc = L.bfs_run_compare(None, 0, 0, None, None, None, 0, ctypes.byref(ops), ctypes.byref(steps), None)
+    assert rc == B.BFS_EINVAL and L.bfs_last_error_detail()
+    assert ops.value == 7 and steps.value == 7          # outputs untouched on error

@@ -73,3 +73,24 @@ def test_rmat20_directed():
                    dict(variant="pull"), dict(variant="short_circuit")):
             say(f"[full] rmat20d s={s} {kw.get('variant')}")
             _check(g, s, run_gpu(P, G, s, **kw), f"rmat20d/{s}", cert=(i == 0))
+
+
+def test_compare_full_size():
+    """The comparison searches at full size: R-MAT s22 (SpMV-BFS, SpMmSpV-BFS)
+    and directed R-MAT s20 (all three); level / parent against the oracle, the
+    operation counts against the oracle's step-by-step counts."""
+    P = need_gpu()
+    import torch
+    from oracle import compare as C
+    for name, methods in (("rmat22", ("spmv", "spmmspv")), ("rmat20d", ("spmv", "spmspv", "spmmspv"))):
+        g = graphgen.workload(name)
+        G = P.Graph.from_graphgen(g)
+        s = int(graphgen.pick_sources(g, 1, 22)[0])
+        for m in methods:
+            say(f"[full] compare {name} s={s} {m}")
+            lv, pa, ops, steps = P.bfs_compare(G, s, m)
+            torch.cuda.synchronize()
+            _check(g, s, (lv.cpu().numpy(), pa.cpu().numpy()), f"{name}/compare/{m}")
+            _, _, wops, wsteps = C.run(g, s, m, ops_only=True)
+            assert (ops, steps) == (wops, wsteps), (name, m)
+        G.close()
