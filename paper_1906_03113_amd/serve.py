@@ -329,22 +329,39 @@ def resident_set(which: str = "small"):
 
 
 def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector):
-    """Per-graph launch parameters for the serving path, from one probe search
-    per graph: the autotuner's cached choice for the graph's shape if there is
-    one, else by diameter class - deep graphs read the frontier size back every
-    64 levels instead of every 4.  Also whether the graph is shallow (at most 64
-    levels), which lets its batches run as one multi-source search."""
+    """Per-graph launch parameters for the serving path, from probe searches on
+    each graph: the autotuner's cached choice for the graph's shape if there is
+    one, else by diameter class (deep graphs read the frontier size back every
+    64 levels instead of every 4); then the faster, on the probe source, of the
+    learned per-level form and plain push (on graphs thousands of levels deep
+    the per-level decision costs more than it saves).  Also whether the graph is
+    shallow (at most 64 levels), which lets its batches run as one
+    multi-source search."""
+    import torch
     import paper_1906_03113_amd as P
     from . import autotune as AT
     out, shallow = {}, {}
     for name, G in Gs.items():
+        s = int(srcs[name][0])
         info = {}
-        P.bfs(G, int(srcs[name][0]), variant="learned", selector=selector, info=info)
+        P.bfs(G, s, variant="learned", selector=selector, info=info)
         levels = int(info["levels"])
         kw = AT.lookup(G, levels)
         kw.pop("loop", None)                   # serving keeps the host loop (no per-query capture)
         if levels > 64:
             kw.setdefault("levels_per_sync", 64)
+        best, best_t = None, float("inf")
+        for form in (dict(variant="learned", selector=selector), dict(variant="push")):
+            run = dict(kw, **form)
+            P.bfs(G, s, **run)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.bfs(G, s, **run)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if t < best_t:
+                best, best_t = form, t
+        kw.update(best)
         out[name] = kw
         shallow[name] = levels <= 64
     return out, shallow
