@@ -16,6 +16,9 @@ Contents
   * ``brute``       (O-D, numpy): levels from Boolean matrix powers.
   * ``certify``     (I1-I4): a complete O(n + nnz) certificate for (level, parent).
   * ``mlp_ref``     float64 reference of the variant-selector network.
+  * ``spmspv``      one masked product y = A^T[R, C] x over the Boolean,
+                    arithmetic, min-plus or (min, select) semiring, by its
+                    definition.
   * ``compare``     the searches the Experiments section compares against
                     (SpMV-BFS, SpMSpV-BFS, SpMmSpV-BFS) and the method, step by
                     step, with their algebraic operation counts (Table 2).
