@@ -298,6 +298,58 @@ bfs_status bfs_run_compare(bfs_graph *g, int32_t source, uint32_t method, int32_
                            int32_t *parent, void *workspace, size_t ws_bytes, uint64_t *ops,
                            uint32_t *steps, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * One masked sparse-matrix x sparse-vector product over a semiring: the
+ * operation the method is made of (Definition 1: x_{k+1} = A^T[V_{k+1}, V_k]
+ * x_k is this product with the row mask = the unvisited rows), offered for
+ * use outside the search as masked-algebra libraries offer it.  Semirings
+ * (the Notation section's Boolean, arithmetic and tropical min-plus, and the
+ * (min, select) semiring that yields the smallest column); A is pattern-only
+ * (every stored entry is 1), values are unsigned 64-bit:
+ *   BFS_SEMIRING_BOOLEAN     y(i) = OR over products of (x(j) != 0)
+ *   BFS_SEMIRING_ARITHMETIC  y(i) = sum of x(j), modulo 2^64
+ *   BFS_SEMIRING_MIN_PLUS    y(i) = min of (x(j) + 1), saturating at 2^64 - 1
+ *   BFS_SEMIRING_MIN_SELECT  y(i) = min of x(j)
+ * ------------------------------------------------------------------------ */
+enum {
+    BFS_SEMIRING_BOOLEAN = 0,
+    BFS_SEMIRING_ARITHMETIC = 1,
+    BFS_SEMIRING_MIN_PLUS = 2,
+    BFS_SEMIRING_MIN_SELECT = 3
+};
+enum {
+    BFS_MASK_ROW_COMPLEMENT = 1u << 0,  /* the row mask names the rows to leave out */
+    BFS_MASK_COL_COMPLEMENT = 1u << 1   /* the column mask names the columns to leave out */
+};
+
+/* Workspace bytes for bfs_masked_spmspv with up to max_nx vector entries (0 on
+ * a bad argument); about 8 n + n / 8 + 24 max_nx bytes. */
+size_t bfs_spmspv_workspace_size(const bfs_graph *g, int32_t max_nx);
+
+/*
+ * y = A^T[R, C] x: for every vector entry (j, x(j)) whose column C allows and
+ * every entry i of A^T's column j (j's out-list) that R allows, y(i) (+)=
+ * 1 (x) x(j).  y's support is structural: every allowed row that receives a
+ * product.  Duplicate vector indices each contribute.
+ * x_idx, x_val: device, nx entries (int32 indices in [0, n), uint64 values);
+ * nx may be 0.  row_mask, col_mask: device bitmaps of ceil(n / 32) uint32
+ * words (bit i = word i / 32, bit i % 32), or NULL for no mask; mask_flags
+ * complements either.  y_idx, y_val: device, capacity n; receive the support
+ * in ascending order and its values.  ny: host, receives the support's size.
+ * workspace: device, bfs_spmspv_workspace_size(g, nx) bytes or more, 256-byte
+ * aligned, zero-filled before its first use; every call leaves it
+ * zero-filled, so one workspace serves any number of calls on one stream.
+ * The call waits for hip_stream.
+ * Errors: BFS_EINVAL (NULL argument, unknown semiring or mask flag, nx < 0,
+ * small or misaligned workspace), BFS_ERANGE (a vector index outside [0, n):
+ * nothing is written), BFS_EHIP.
+ */
+bfs_status bfs_masked_spmspv(bfs_graph *g, uint32_t semiring, const int32_t *x_idx,
+                             const uint64_t *x_val, int32_t nx, const uint32_t *row_mask,
+                             const uint32_t *col_mask, uint32_t mask_flags, int32_t *y_idx,
+                             uint64_t *y_val, int32_t *ny, void *workspace, size_t ws_bytes,
+                             void *hip_stream);
+
 /* Static text for a status code. */
 const char *bfs_status_string(bfs_status s);
 

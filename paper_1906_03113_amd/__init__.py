@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import BfsError, LOOPS, VARIANTS, VARIANT_NAMES, LevelRecord, RunOptions
 
-__all__ = ["Graph", "bfs", "bfs_batch", "bfs_roots", "bfs_compare", "compare_workspace_size", "BfsError", "VARIANTS", "LOOPS",
+__all__ = ["Graph", "bfs", "bfs_batch", "bfs_roots", "bfs_compare", "compare_workspace_size", "masked_spmspv",
+           "spmspv_workspace_size", "BfsError", "VARIANTS", "LOOPS",
            "Workspace", "make_options"]
 
 
@@ -260,3 +261,36 @@ def bfs_compare(g: Graph, source: int, method: str, level=None, parent=None,
                                           workspace.nbytes, ctypes.byref(ops), ctypes.byref(steps),
                                           _stream_handle(stream)))
     return level, parent, int(ops.value), int(steps.value)
+
+
+def spmspv_workspace_size(g: Graph, max_nx: int) -> int:
+    return int(_lib.lib().bfs_spmspv_workspace_size(g.handle, int(max_nx)))
+
+
+def masked_spmspv(g: Graph, semiring: str, x_idx, x_val, row_mask=None, col_mask=None,
+                  row_complement: bool = False, col_complement: bool = False,
+                  workspace: Optional[Workspace] = None, y_idx=None, y_val=None, stream=None):
+    """y = A^T[R, C] x over a semiring ("boolean", "arithmetic", "min_plus",
+    "min_select").  x_idx: int32 cuda tensor; x_val: int64 cuda tensor holding
+    the uint64 bit patterns; masks: int32 cuda tensors of ceil(n / 32) words or
+    None.  The workspace must start zero-filled (a new one is).  Returns
+    (y_idx, y_val) views of length ny (ascending indices; y_val as int64 bit
+    patterns); waits for the stream."""
+    t = _torch()
+    nx = int(x_idx.numel())
+    need = spmspv_workspace_size(g, nx)
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need)
+        workspace.buf.zero_()
+    if y_idx is None:
+        y_idx = t.empty(g.n, dtype=t.int32, device="cuda")
+    if y_val is None:
+        y_val = t.empty(g.n, dtype=t.int64, device="cuda")
+    flags = (1 if row_complement else 0) | (2 if col_complement else 0)
+    vp = lambda a: None if a is None else ctypes.c_void_p(a.data_ptr())
+    ny = ctypes.c_int32(0)
+    _lib.check(_lib.lib().bfs_masked_spmspv(g.handle, _lib.SEMIRINGS[semiring], vp(x_idx), vp(x_val), nx,
+                                            vp(row_mask), vp(col_mask), flags, vp(y_idx), vp(y_val),
+                                            ctypes.byref(ny), workspace.ptr, workspace.nbytes,
+                                            _stream_handle(stream)))
+    return y_idx[:ny.value], y_val[:ny.value]

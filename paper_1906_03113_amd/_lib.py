@@ -14,6 +14,7 @@ VARIANTS = {"push": 0, "pull": 1, "bitmap": 2, "learned": 3, "heuristic": 4, "sh
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 LOOPS = {"host": 0, "graph": 1, "persistent": 2}
 COMPARE = {"spmv": 0, "spmspv": 1, "spmmspv": 2}
+SEMIRINGS = {"boolean": 0, "arithmetic": 1, "min_plus": 2, "min_select": 3}
 
 
 class LevelRecord(ctypes.Structure):
@@ -98,6 +99,11 @@ def _optional(L):
     L.bfs_run_compare.argtypes = [vp, i32, u32, vp, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64),
                                   ctypes.POINTER(u32), vp]
     L.bfs_run_compare.restype = i32
+    L.bfs_spmspv_workspace_size.argtypes = [vp, i32]
+    L.bfs_spmspv_workspace_size.restype = sz
+    L.bfs_masked_spmspv.argtypes = [vp, u32, vp, vp, i32, vp, vp, u32, vp, vp,
+                                    ctypes.POINTER(i32), vp, sz, vp]
+    L.bfs_masked_spmspv.restype = i32
 
 
 def check(status: int) -> None:

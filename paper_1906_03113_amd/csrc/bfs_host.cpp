@@ -981,3 +981,61 @@ extern "C" bfs_status bfs_run_compare(bfs_graph *g, int32_t source, uint32_t met
     if (steps) *steps = hst.k;
     return BFS_OK;
 }
+
+// ---------------------------------------------------------------------------
+// One masked SpMSpV product over a semiring
+// ---------------------------------------------------------------------------
+
+extern "C" size_t bfs_spmspv_workspace_size(const bfs_graph *g, int32_t max_nx) {
+    if (!g || max_nx < 0) return 0;
+    return sp_layout(g->n, max_nx).total;
+}
+
+extern "C" bfs_status bfs_masked_spmspv(bfs_graph *g, uint32_t semiring, const int32_t *x_idx,
+                                        const uint64_t *x_val, int32_t nx, const uint32_t *row_mask,
+                                        const uint32_t *col_mask, uint32_t mask_flags, int32_t *y_idx,
+                                        uint64_t *y_val, int32_t *ny, void *workspace, size_t ws_bytes,
+                                        void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (semiring > kSrMinSelect) return fail(BFS_EINVAL, "unknown semiring %u", semiring);
+    if (nx < 0) return fail(BFS_EINVAL, "nx = %d", nx);
+    if (nx > 0 && (!x_idx || !x_val)) return fail(BFS_EINVAL, "x_idx / x_val is NULL");
+    if (!y_idx || !y_val || !ny || !workspace) return fail(BFS_EINVAL, "y_idx / y_val / ny / workspace is NULL");
+    if (mask_flags & ~3u) return fail(BFS_EINVAL, "unknown mask flags 0x%x", mask_flags);
+    if (((uintptr_t)workspace & 255) != 0) return fail(BFS_EINVAL, "workspace must be 256-byte aligned");
+    const SpLayout L = sp_layout(g->n, nx);
+    if (ws_bytes < L.total) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *b = (char *)workspace;
+    SpParams P{};
+    P.n = g->n;
+    P.words = (uint32_t)(((size_t)g->n + 31) / 32);
+    P.semiring = semiring;
+    P.out_ptr = g->out_ptr;
+    P.out_idx = g->out_idx;
+    P.x_idx = x_idx;
+    P.x_val = (const unsigned long long *)x_val;
+    P.nx = nx;
+    P.row_mask = row_mask;
+    P.col_mask = col_mask;
+    P.row_comp = (mask_flags & 1u) ? 1u : 0u;
+    P.col_comp = (mask_flags & 2u) ? 1u : 0u;
+    P.acc = (unsigned long long *)(b + L.acc);
+    P.touched = (uint32_t *)(b + L.touched);
+    P.items = (SpItem *)(b + L.items);
+    P.block_off = (uint32_t *)(b + L.block_off);
+    P.st = (SpState *)(b + L.state);
+    P.y_idx = y_idx;
+    P.y_val = (unsigned long long *)y_val;
+    P.ny = (int32_t *)(b + L.ny);
+    const uint32_t grid = (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
+    HIP_TRY(launch_spmspv(P, grid, s));
+    SpState hst;
+    int32_t hny = 0;
+    HIP_TRY(hipMemcpyAsync(&hst, P.st, sizeof hst, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hny, P.ny, sizeof hny, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hst.bad) return fail(BFS_ERANGE, "a vector index lies outside [0, %d)", g->n);
+    *ny = hny;
+    return BFS_OK;
+}

@@ -178,6 +178,52 @@ struct CmpLayout {
     size_t state, y, l0, l1, touched, x0, x1, total;
 };
 CmpLayout cmp_layout(int32_t n);
+
+// One masked sparse-matrix x sparse-vector product over a semiring
+// (bfs_spmspv.hip).
+enum Semiring : uint32_t { kSrBoolean = 0, kSrArithmetic = 1, kSrMinPlus = 2, kSrMinSelect = 3 };
+constexpr uint32_t kSpLong = 512;      // column length from which a vector entry's column is split
+constexpr uint32_t kSpChunk = 1024;    // entries per chunk of a split column
+constexpr uint32_t kSpOutWords = 256;  // bitmap words per workgroup of the output passes
+
+struct alignas(256) SpState {
+    uint32_t nitems;               // split columns listed by the product pass
+    uint32_t bad;                  // a vector index outside [0, n)
+    unsigned long long nchunks;    // chunks over all split columns
+};
+
+struct SpItem {                    // a vector entry whose column is split
+    int32_t j;
+    uint32_t nch;                  // its chunks
+    unsigned long long v;          // its value
+    unsigned long long base;       // its first chunk (exclusive prefix of nch)
+};
+
+struct SpParams {
+    int32_t n;
+    uint32_t words;
+    uint32_t semiring;
+    const int32_t *out_ptr, *out_idx;
+    const int32_t *x_idx;
+    const unsigned long long *x_val;
+    int32_t nx;
+    const uint32_t *row_mask, *col_mask;   // nullptr: no mask
+    uint32_t row_comp, col_comp;
+    unsigned long long *acc;               // [n] the product, zero between calls (min semirings store ~value)
+    uint32_t *touched;                     // [words] the product's support, zero between calls
+    SpItem *items;                         // [nx]
+    uint32_t *block_off;                   // [ceil(words / kSpOutWords)]
+    SpState *st;
+    int32_t *y_idx;
+    unsigned long long *y_val;
+    int32_t *ny;                           // device: the output's length
+};
+
+struct SpLayout {
+    size_t state, acc, touched, items, block_off, ny, total;
+};
+SpLayout sp_layout(int32_t n, int32_t max_nx);
+hipError_t launch_spmspv(const SpParams &p, uint32_t grid, hipStream_t s);
 hipError_t launch_cmp_init(const CmpParams &p, int32_t source, hipStream_t s);
 hipError_t launch_cmp_step(const CmpParams &p, uint32_t grid, hipStream_t s);
 
