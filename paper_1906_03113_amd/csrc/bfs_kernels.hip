@@ -220,6 +220,7 @@ struct OutLds {
 struct LevelPtrs {
     uint32_t k, cs, ns;
     bool sc;                  // this level claims rows short-circuit (parents set afterwards)
+    bool pre;                 // pre-read the parent before its atomicMin
     const uint32_t *vb_cur;
     uint32_t *vb_nxt;
     const uint32_t *fb_cur;
@@ -255,6 +256,7 @@ __device__ __forceinline__ LevelPtrs level_ptrs(const LevelParams &P, uint32_t k
     L.c_nxt = odd ? P.cmap[0] : P.cmap[1];
     L.u_nxt = nullptr;
     L.sc = false;
+    L.pre = true;
     return L;
 }
 
@@ -331,8 +333,8 @@ __device__ __forceinline__ void out_flush(const LevelParams &P, const LevelPtrs 
 // the per-entry step: test the row mask, min-select the parent, claim
 // ---------------------------------------------------------------------------
 
-// For an unmasked pair (j, i) (row i not visited through level k): returns
-// true for exactly one such pair per newly reached i, the one whose atomicMin
+// The claim of an unmasked pair (j, i) (row i not visited through level k):
+// exactly one such pair per newly reached i wins, the one whose atomicMin
 // found the parent slot still empty.  Every unmasked pair reaches the
 // atomicMin unless the slot already holds a smaller or equal vertex, so the
 // final parent is the minimum over the level's frontier in-neighbours.  The
@@ -343,21 +345,7 @@ __device__ __forceinline__ void out_flush(const LevelParams &P, const LevelPtrs 
 // i claims it by turning level[i] from -1 to k + 1, so each reached vertex
 // takes exactly one claim and no parent atomic; k_parents sets those parents
 // after the search.  The coherent pre-read of level[i] sees other XCDs'
-// claims, so most losing pairs skip the atomic.
-__device__ __forceinline__ bool claim(const LevelParams &P, const LevelPtrs &L, int32_t i, int32_t j,
-                                      uint32_t k) {
-    if (L.sc) {
-        if (__hip_atomic_load(&P.level[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1) return false;
-        return atomicCAS(&P.level[i], -1, (int32_t)(k + 1)) == -1;
-    }
-    const uint32_t p = ld_agent(&P.parent[i]);
-    if (p <= (uint32_t)j) return false;
-    const uint32_t old = atomicMin(&P.parent[i], (uint32_t)j);
-    if (old != 0xFFFFFFFFu) return false;
-    P.level[i] = (int32_t)(k + 1);
-    return true;
-}
-
+// claims, so most losing pairs skip the atomic.  (settle4 below.)
 // Set one bit per active lane in a bitmap.  Lanes holding vertices of the
 // same 32-bit word are combined into one atomicOr (wave-contiguous atomics are
 // an order of magnitude cheaper than ones that collide on a word); after a few
@@ -470,11 +458,75 @@ __device__ __forceinline__ uint32_t mask_word(const LevelPtrs &L, int32_t i) {
 
 // Mask test, parent min-select and claim for one pair (j, i), then the
 // block-wide append of the vertices claimed.  Called by every thread.
-__device__ __forceinline__ void settle(const LevelParams &P, const LevelPtrs &L, OutLds &O,
-                                       int32_t i, int32_t j, uint32_t mw) {
-    const bool unmasked = (i >= 0) && !((mw >> (i & 31)) & 1u);
-    const bool owner = unmasked && claim(P, L, i, j, L.k);
-    append_next(P, L, O, owner, i);
+// The claims of a lane's four entries of one round, with the memory
+// operations of the four in flight together: the coherent pre-reads, then the
+// atomics, then the column bounds of the rows it won (a row reached through
+// two of the four entries is won by the atomic performed first).  Then each
+// winner joins F_{k+1} (LDS staging, with a flush check after each of the
+// four appends so the staging buffers never overflow).
+__device__ __forceinline__ bool unmasked(int32_t i, uint32_t mw) {
+    return (i >= 0) && !((mw >> (i & 31)) & 1u);
+}
+
+__device__ __forceinline__ void settle4(const LevelParams &P, const LevelPtrs &L, OutLds &O,
+                                        int32_t i0, int32_t j0, uint32_t m0, int32_t i1, int32_t j1,
+                                        uint32_t m1, int32_t i2, int32_t j2, uint32_t m2, int32_t i3,
+                                        int32_t j3, uint32_t m3) {
+    const bool u0 = unmasked(i0, m0), u1 = unmasked(i1, m1);
+    const bool u2 = unmasked(i2, m2), u3 = unmasked(i3, m3);
+    bool o0, o1, o2, o3;
+    const int32_t nk = (int32_t)(L.k + 1);
+    if (L.sc) {
+        // short circuit: the first column to turn level[i] from -1 claims i
+        const int32_t v0 = u0 ? __hip_atomic_load(&P.level[i0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        const int32_t v1 = u1 ? __hip_atomic_load(&P.level[i1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        const int32_t v2 = u2 ? __hip_atomic_load(&P.level[i2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        const int32_t v3 = u3 ? __hip_atomic_load(&P.level[i3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        const bool t0 = u0 && v0 == -1, t1 = u1 && v1 == -1, t2 = u2 && v2 == -1, t3 = u3 && v3 == -1;
+        const int32_t c0 = t0 ? atomicCAS(&P.level[i0], -1, nk) : 0;
+        const int32_t c1 = t1 ? atomicCAS(&P.level[i1], -1, nk) : 0;
+        const int32_t c2 = t2 ? atomicCAS(&P.level[i2], -1, nk) : 0;
+        const int32_t c3 = t3 ? atomicCAS(&P.level[i3], -1, nk) : 0;
+        o0 = t0 && c0 == -1;
+        o1 = t1 && c1 == -1;
+        o2 = t2 && c2 == -1;
+        o3 = t3 && c3 == -1;
+    } else {
+        // min-select: pairs that cannot lower the parent skip the atomic (on a
+        // small level the pre-read is skipped: its latency costs more than
+        // the few atomics it would save); the atomic that found the slot
+        // empty claims the row
+        const bool pre = L.pre;
+        const uint32_t p0 = (u0 && pre) ? ld_agent(&P.parent[i0]) : 0xFFFFFFFFu;
+        const uint32_t p1 = (u1 && pre) ? ld_agent(&P.parent[i1]) : 0xFFFFFFFFu;
+        const uint32_t p2 = (u2 && pre) ? ld_agent(&P.parent[i2]) : 0xFFFFFFFFu;
+        const uint32_t p3 = (u3 && pre) ? ld_agent(&P.parent[i3]) : 0xFFFFFFFFu;
+        const bool t0 = u0 && p0 > (uint32_t)j0, t1 = u1 && p1 > (uint32_t)j1;
+        const bool t2 = u2 && p2 > (uint32_t)j2, t3 = u3 && p3 > (uint32_t)j3;
+        const uint32_t a0 = t0 ? atomicMin(&P.parent[i0], (uint32_t)j0) : 0u;
+        const uint32_t a1 = t1 ? atomicMin(&P.parent[i1], (uint32_t)j1) : 0u;
+        const uint32_t a2 = t2 ? atomicMin(&P.parent[i2], (uint32_t)j2) : 0u;
+        const uint32_t a3 = t3 ? atomicMin(&P.parent[i3], (uint32_t)j3) : 0u;
+        o0 = t0 && a0 == 0xFFFFFFFFu;
+        o1 = t1 && a1 == 0xFFFFFFFFu;
+        o2 = t2 && a2 == 0xFFFFFFFFu;
+        o3 = t3 && a3 == 0xFFFFFFFFu;
+        if (o0) P.level[i0] = nk;
+        if (o1) P.level[i1] = nk;
+        if (o2) P.level[i2] = nk;
+        if (o3) P.level[i3] = nk;
+    }
+    const int32_t a00 = o0 ? P.out_ptr[i0] : 0, a01 = o0 ? P.out_ptr[i0 + 1] : 0;
+    const int32_t a10 = o1 ? P.out_ptr[i1] : 0, a11 = o1 ? P.out_ptr[i1 + 1] : 0;
+    const int32_t a20 = o2 ? P.out_ptr[i2] : 0, a21 = o2 ? P.out_ptr[i2 + 1] : 0;
+    const int32_t a30 = o3 ? P.out_ptr[i3] : 0, a31 = o3 ? P.out_ptr[i3 + 1] : 0;
+    append_next(P, L, O, o0, i0, false, a00, a01);
+    out_flush(P, L, O, false);
+    append_next(P, L, O, o1, i1, false, a10, a11);
+    out_flush(P, L, O, false);
+    append_next(P, L, O, o2, i2, false, a20, a21);
+    out_flush(P, L, O, false);
+    append_next(P, L, O, o3, i3, false, a30, a31);
     out_flush(P, L, O, false);
 }
 
@@ -511,10 +563,7 @@ __device__ __forceinline__ void expand_tile(const LevelParams &P, const LevelPtr
         tile_entry(P, T, total, base + 3 * kBlock + tid, lo, i3, j3);
         const uint32_t m0 = mask_word(L, i0), m1 = mask_word(L, i1);
         const uint32_t m2 = mask_word(L, i2), m3 = mask_word(L, i3);
-        settle(P, L, O, i0, j0, m0);
-        settle(P, L, O, i1, j1, m1);
-        settle(P, L, O, i2, j2, m2);
-        settle(P, L, O, i3, j3, m3);
+        settle4(P, L, O, i0, j0, m0, i1, j1, m1, i2, j2, m2, i3, j3, m3);
     }
     __syncthreads();   // T is reused by the next tile
 }
@@ -546,10 +595,7 @@ __device__ __forceinline__ void expand_chunk(const LevelParams &P, const LevelPt
         const int32_t i3 = (e + 3 * kBlock < e1) ? P.out_idx[e + 3 * kBlock] : -1;
         const uint32_t m0 = mask_word(L, i0), m1 = mask_word(L, i1);
         const uint32_t m2 = mask_word(L, i2), m3 = mask_word(L, i3);
-        settle(P, L, O, i0, j, m0);
-        settle(P, L, O, i1, j, m1);
-        settle(P, L, O, i2, j, m2);
-        settle(P, L, O, i3, j, m3);
+        settle4(P, L, O, i0, j, m0, i1, j, m1, i2, j, m2, i3, j, m3);
     }
 }
 
@@ -914,6 +960,8 @@ __device__ __forceinline__ void level_body(const LevelParams &P, uint32_t k, uin
     const uint32_t nreg = st->nf[L.cs];
     const unsigned long long hp = st->heavy[L.cs];
     const uint32_t nlong = (uint32_t)hp, nchunks = (uint32_t)(hp >> 32);
+    // small level: fewer than 8192 short columns and under 2^20 entries in long ones
+    L.pre = !(nreg < 8192u && (unsigned long long)nchunks * P.chunk < (1ull << 20));
     const uint32_t v = level_form(P, st->variant);     // decided before the launch
     if (bid == 0 && threadIdx.x == 0) {
         BfsState *w = P.st;
