@@ -1181,7 +1181,9 @@ __global__ void k_decide(LevelParams P) {
 // group by bumping the group's own generation, which the rest of the group
 // watches.  Arrivals serialise on kBarGroups + nblocks / kBarGroups atomics
 // instead of nblocks, and at most nblocks / kBarGroups blocks poll any one
-// line.  Returns false only if a spin limit runs out, which cannot happen when
+// line.  Arrivals and releases are release fences (L2 write-back only) and the
+// way out is an acquire fence (invalidate only): a full fence at arrival would
+// also invalidate the L2 under the blocks still working on the level.  Returns false only if a spin limit runs out, which cannot happen when
 // every block is resident.
 __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, uint32_t nf, uint32_t nblocks,
                               uint32_t *s_role, float *s_w) {
@@ -1195,11 +1197,11 @@ __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, 
     if (threadIdx.x == 0) {
         uint32_t role = 0;                                   // 0 member, 1 group's last, 2 very last
         gen = ld_agent(ggen);
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this block's part of level k
         if (atomicAdd(&st->bar_group[g * 16], 1u) == in_group - 1) {
             __hip_atomic_store(&st->bar_group[g * 16], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tgen = ld_agent(&st->barrier_gen);
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             role = 1;
             if (atomicAdd(&st->bar_top, 1u) == groups - 1) {
                 __hip_atomic_store(&st->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1215,7 +1217,7 @@ __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, 
     uint32_t ok = 1;
     if (threadIdx.x == 0) {
         if (role == 2) {
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the level's close
             atomicAdd(&st->barrier_gen, 1u);
         } else if (role == 1) {
             uint32_t spins = 0;
@@ -1225,7 +1227,7 @@ __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, 
             }
         }
         if (role != 0) {
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             atomicAdd(ggen, 1u);                             // release this group
         } else {
             uint32_t spins = 0;
@@ -1234,7 +1236,7 @@ __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, 
                 if (++spins > (1u << 26)) { ok = 0; break; }
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see every block's level k
         *s_role = ok;
     }
     __syncthreads();
