@@ -923,8 +923,7 @@ __device__ __forceinline__ Closed finish_level(const LevelParams &P, uint32_t k,
         st->u_len = ld_agent(&st->u_wr);
     }
     st->u_wr = 0;
-    __threadfence();
-    st->level = k + 1;
+    st->level = k + 1;        // published by the launch's end, or the barrier's release
     Closed c;
     c.nf = nf_next;
     c.s.nf = (float)nf_next;
@@ -1136,11 +1135,15 @@ __device__ __forceinline__ void report_status(const LevelParams &P, uint32_t lev
 
 // Close level k (every block of the level is done): fold the counters, decide
 // the next level's form, report.  Called by every thread of one block; s_w is
-// that block's LDS (kMlpTotal floats), free by now.
-__device__ __forceinline__ void close_level(const LevelParams &P, uint32_t k, uint32_t nf, float *s_w) {
+// that block's LDS (kMlpTotal floats), free by now.  Everything it reads that
+// other blocks changed during the level it reads with coherent loads; the
+// persistent kernel also acquires (`acquire`) the state that an earlier
+// level's close wrote in the same launch.
+__device__ __forceinline__ void close_level(const LevelParams &P, uint32_t k, uint32_t nf, float *s_w,
+                                            bool acquire) {
     __shared__ Closed s_c;
     if (threadIdx.x == 0) {
-        __threadfence();                                     // see every block's part
+        if (acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_c = finish_level(P, k, nf);
     }
     __syncthreads();
@@ -1159,7 +1162,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_level(LevelParams P) {
     const uint32_t nf = frontier_size(st, k & 3);
     if (nf == 0) return;
     level_body(P, k, blockIdx.x, gridDim.x, lds);
-    if (last_to_arrive(st, gridDim.x)) close_level(P, k, nf, lds.w);
+    if (last_to_arrive(st, gridDim.x)) close_level(P, k, nf, lds.w, false);
 }
 
 // The form of level 0 (after the init kernels).
@@ -1212,7 +1215,7 @@ __device__ __forceinline__ bool level_barrier(const LevelParams &P, uint32_t k, 
     }
     __syncthreads();
     const uint32_t role = *s_role;
-    if (role == 2) close_level(P, k, nf, s_w);               // every block is done with level k
+    if (role == 2) close_level(P, k, nf, s_w, true);               // every block is done with level k
     __syncthreads();
     uint32_t ok = 1;
     if (threadIdx.x == 0) {
