@@ -94,3 +94,33 @@ def test_compare_full_size():
             _, _, wops, wsteps = C.run(g, s, m, ops_only=True)
             assert (ops, steps) == (wops, wsteps), (name, m)
         G.close()
+
+
+def test_masked_spmspv_full_size():
+    """Theorem 1 at full size through the masked SpMSpV primitive: on R-MAT
+    s22, for every level k of the oracle's search, the (min, select) product of
+    x = F_k (x(j) = j) under the complemented mask of the rows visited through
+    level k has the support {v : level[v] = k + 1} and the values parent[v]."""
+    P = need_gpu()
+    import torch
+    g = graphgen.workload("rmat22")
+    G = P.Graph.from_graphgen(g)
+    s = int(graphgen.pick_sources(g, 64, 22)[0])
+    wl, wp = oracle.bfs_graph(g, s)
+    ws = P.Workspace(P.spmspv_workspace_size(G, int((wl >= 0).sum())))
+    ws.buf.zero_()
+    for k in range(int(wl.max()) + 1):
+        front = np.nonzero(wl == k)[0].astype(np.int32)
+        seen = (wl >= 0) & (wl <= k)
+        words = np.zeros((g.n + 31) // 32, np.uint32)
+        idx = np.nonzero(seen)[0]
+        np.bitwise_or.at(words, idx >> 5, (np.uint32(1) << (idx & 31).astype(np.uint32)))
+        say(f"[full] spmspv rmat22 level {k} |x|={len(front)}")
+        yi, yv = P.masked_spmspv(G, "min_select", torch.from_numpy(front).cuda(),
+                                 torch.from_numpy(front.astype(np.int64)).cuda(),
+                                 torch.from_numpy(words.view(np.int32)).cuda(), None, True, workspace=ws)
+        torch.cuda.synchronize()
+        want = np.nonzero(wl == k + 1)[0]
+        assert np.array_equal(yi.cpu().numpy(), want), k
+        assert np.array_equal(yv.cpu().numpy(), wp[want].astype(np.int64)), k
+    G.close()
