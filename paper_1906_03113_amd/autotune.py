@@ -12,7 +12,8 @@ the graph itself (a few searches per candidate) and cached under a shape key:
      class from one probe search: levels <= 64 "low", <= 1024 "mid", else "high")
 
 The cache is a JSON file; `lookup` returns the cached parameters (or the
-defaults) for any graph of the same shape.
+defaults) for any graph of the same shape.  `tune_batch_width` does the same
+for the number of sources per multi-source call (`lookup_batch_width`).
 """
 from __future__ import annotations
 
@@ -131,6 +132,71 @@ def store(cache: str, key: str, entry: Dict) -> None:
     os.replace(tmp, cache)
 
 
+BATCH_WIDTHS = (64, 128, 256)
+
+
+def time_batches(G, sources: Sequence[int], width: int, reps: int = 2) -> float:
+    """Best-of-reps wall time (s) for searching from every source with
+    bfs_run_batch calls of `width` sources each (outputs and one workspace
+    allocated first; the last call takes the remainder)."""
+    torch = _torch()
+    import paper_1906_03113_amd as P
+    src = [int(s) for s in sources]
+    lv = [torch.empty(G.n, dtype=torch.int32, device="cuda") for _ in src]
+    pa = [torch.empty(G.n, dtype=torch.int32, device="cuda") for _ in src]
+    ws = P.Workspace(G.workspace_size(min(width, len(src))))
+    best = math.inf
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(0, len(src), width):
+            P.bfs_batch(G, src[b:b + width], levels=lv[b:b + width], parents=pa[b:b + width],
+                        workspace=ws, variant="heuristic")
+        torch.cuda.synchronize()
+        if r:
+            best = min(best, time.perf_counter() - t0)
+    del lv, pa, ws
+    torch.cuda.empty_cache()
+    return best
+
+
+def tune_batch_width(G, sources: Sequence[int], widths: Sequence[int] = BATCH_WIDTHS,
+                     cache: str = DEFAULT_CACHE, log=None, timer=None) -> Dict:
+    """Sources per multi-source call (64 per mask word, so multiples of 64):
+    time the same set of sources in calls of each width, cache the fastest
+    under the graph's shape key."""
+    import paper_1906_03113_amd as P
+    info = {}
+    P.bfs(G, int(sources[0]), info=info, variant="heuristic")
+    key = shape_key(G, int(info["levels"])) + "|batch"
+    timer = timer or time_batches
+    times = {}
+    for w in widths:
+        if w > len(sources) or w % 64:
+            continue
+        times[w] = timer(G, sources, w)
+        if log:
+            log(f"[autotune] {key} width {w} -> {times[w] * 1e3:.2f} ms for {len(sources)} sources")
+    best = min(times, key=times.get)
+    entry = {"width": best, "time_s": times[best], "times_s": {str(w): t for w, t in times.items()},
+             "sources": len(sources)}
+    store(cache, key, entry)
+    return dict(key=key, **entry)
+
+
+def lookup_batch_width(G, levels: int, cache: str = DEFAULT_CACHE, default: int = 64) -> int:
+    """Cached sources per multi-source call for G's shape, else `default`."""
+    if not os.path.exists(cache):
+        return default
+    try:
+        with open(cache) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return default
+    e = d.get(shape_key(G, levels) + "|batch")
+    return int(e["width"]) if e else default
+
+
 def lookup(G, levels: int, cache: str = DEFAULT_CACHE) -> Dict:
     """Cached parameters for G's shape, or {} (the library's defaults)."""
     if not os.path.exists(cache):
@@ -153,6 +219,8 @@ def main(argv=None):
     ap.add_argument("--budget", type=int, default=16)
     ap.add_argument("--sources", type=int, default=2)
     ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--batch", action="store_true",
+                    help="tune the sources per multi-source call instead (256 sources per workload)")
     a = ap.parse_args(argv)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
     torch = _torch()
@@ -165,6 +233,14 @@ def main(argv=None):
     for w in a.workloads.split(","):
         g = graphgen.workload(w)
         G = P.Graph.from_graphgen(g)
+        if a.batch:
+            src = graphgen.pick_sources(g, 256, 123)
+            r = tune_batch_width(G, src, cache=a.cache, log=log)
+            log(f"[autotune] {w}: best width {r['width']} "
+                f"({', '.join(f'{k}: {v * 1e3:.2f} ms' for k, v in r['times_s'].items())})")
+            out[w] = r
+            G.close()
+            continue
         src = graphgen.pick_sources(g, a.sources, 123)
         r = tune(G, src, a.budget, a.cache, vkw, log)
         log(f"[autotune] {w}: best {r['params']} {r['time_s'] * 1e3:.2f} ms "

@@ -60,3 +60,27 @@ def test_selector_level_weights_and_spread():
     assert len(kept) == 300 and kept[0]["level"] == 0 and kept[-1]["level"] == 999
     assert all(a["level"] < b["level"] for a, b in zip(kept, kept[1:]))
     assert S._spread(lv[:10], 300) == lv[:10]
+
+
+def test_batch_width_choice_and_cache(tmp_path, monkeypatch):
+    """The width with the smallest measured time is cached under the shape key
+    and returned by lookup_batch_width; widths above the source count or not
+    a multiple of 64 are not tried."""
+    import paper_1906_03113_amd as P
+
+    class FakeGraph:
+        n, nnz, directed = 1 << 20, 16 << 20, False
+
+    monkeypatch.setattr(P, "bfs", lambda G, s, info=None, **kw: info.update(levels=7))
+    tried = []
+
+    def timer(G, sources, w):
+        tried.append(w)
+        return {64: 3.0, 128: 2.0, 256: 2.5}[w]
+
+    cache = str(tmp_path / "t.json")
+    r = A.tune_batch_width(FakeGraph(), list(range(200)), widths=(64, 100, 128, 256), cache=cache,
+                           timer=timer)
+    assert tried == [64, 128] and r["width"] == 128
+    assert A.lookup_batch_width(FakeGraph(), 7, cache) == 128
+    assert A.lookup_batch_width(FakeGraph(), 7, str(tmp_path / "none.json")) == 64
