@@ -1,0 +1,23 @@
+"""CPU checks of bench.py's contract: one GPU only, and the committed HBM
+traffic summary belongs to the current level-kernel source."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU only" in r.stderr
+    assert r.stdout.strip() == ""                    # no JSON line
+
+
+def test_traffic_summary_matches_kernel_source():
+    sys.path.insert(0, ROOT)
+    import bench
+    t = bench.measured_traffic()
+    assert t is not None, "profiles/k_level_rmat22_push_traffic.md was taken on another kernel source"
+    assert t > 71_337_629                             # at least the algorithmic bytes per launch
