@@ -298,11 +298,23 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--small", action="store_true", help="skip the large training graphs")
     ap.add_argument("--cap", type=int, default=300, help="levels kept per training search")
+    ap.add_argument("--eval", action="store_true",
+                    help="only measure the held-out regret of the weights in --out (no training)")
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch = _torch()
     torch.cuda.init()                 # the device context first, before any CPU-heavy setup
     train_g, held_g = training_graphs(include_large=not args.small)
+    if args.eval:
+        with open(args.out) as f:
+            w = np.asarray(json.load(f)["weights"], np.float32)
+        res = {}
+        for k, v in held_g.items():
+            Xh, Th, Mh = collect(v, per_graph=2, log=log)
+            res[k] = regret(choose(w, Xh), Th, Mh)
+            log(f"[selector] held-out {k}: {res[k]}")
+        print(json.dumps({"held_out": res}))
+        return
     X, T, M = collect(train_g, log=log, cap=args.cap)
     held = {k: collect(v, per_graph=2, log=log) for k, v in held_g.items()}
     log(f"[selector] training rows {len(X)}, held-out rows "
