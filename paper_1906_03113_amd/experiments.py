@@ -1,7 +1,7 @@
 """The batching measurements: many sources on one graph in one call, and many
 uneven graphs in one launch.
 
-    python -m paper_1906_03113_amd.experiments [--only sources|graphs|compare] [--out FILE]
+    python -m paper_1906_03113_amd.experiments [--only sources|graphs|compare|spmspv] [--out FILE]
 
 * sources: directed R-MAT scale 20 (edgefactor 16, out-edges), 256 sources of
   nonzero out-degree (seed 41) in one bfs_run_batch call (4 mask words per
@@ -17,6 +17,7 @@ uneven graphs in one launch.
 * compare: the Experiments section's comparison searches (SpMV-BFS, SpMSpV-BFS,
   SpMmSpV-BFS) against the method on ER n=16,384, directed R-MAT s20, R-MAT
   s22 and 1024^2 / 4096^2 grids: operation counts and time per search.
+* spmspv: the masked SpMSpV primitive on every level of an R-MAT s22 search.
 
 Throughput is GTEPS = sum over the searches of m_c (edges of the reached
 component; each undirected edge once, each directed edge once) / wall time,
@@ -213,10 +214,54 @@ def compare(workloads=("er16k", "rmat20d", "rmat22", "grid1024", "grid4096"), lo
     return res
 
 
+def spmspv_levels(log=print) -> Dict:
+    """The masked SpMSpV primitive on the levels of an R-MAT s22 search: for
+    each level k of the oracle's search from the first of the 64 bench sources
+    (pick_sources(g, 64, 22)[0]), x = F_k with x(j) = j and the row mask = the
+    rows visited through level k, complemented; (min, select) and Boolean
+    products, wall time of one call (which waits for the stream) after one
+    warm-up call."""
+    import graphgen
+    import oracle
+    import paper_1906_03113_amd as P
+    torch = _torch()
+    g = graphgen.workload("rmat22")
+    G = P.Graph.from_graphgen(g)
+    s = int(graphgen.pick_sources(g, 64, 22)[0])
+    wl, _ = oracle.bfs_graph(g, s)
+    deg = np.diff(g.ptr.astype(np.int64))
+    yi = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    yv = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    ws = P.Workspace(P.spmspv_workspace_size(G, int((wl >= 0).sum())))
+    ws.buf.zero_()
+    out = []
+    for k in range(int(wl.max()) + 1):
+        front = np.nonzero(wl == k)[0].astype(np.int32)
+        seen = np.nonzero((wl >= 0) & (wl <= k))[0]
+        words = np.zeros((g.n + 31) // 32, np.uint32)
+        np.bitwise_or.at(words, seen >> 5, (np.uint32(1) << (seen & 31).astype(np.uint32)))
+        xi = torch.from_numpy(front).cuda()
+        xv = torch.from_numpy(front.astype(np.int64)).cuda()
+        mask = torch.from_numpy(words.view(np.int32)).cuda()
+        row = {"level": k, "vector": len(front), "entries": int(deg[front].sum())}
+        for sr in ("min_select", "boolean"):
+            P.masked_spmspv(G, sr, xi, xv, mask, None, True, workspace=ws, y_idx=yi, y_val=yv)
+            t0 = time.perf_counter()
+            a, _ = P.masked_spmspv(G, sr, xi, xv, mask, None, True, workspace=ws, y_idx=yi, y_val=yv)
+            t = time.perf_counter() - t0
+            row[sr] = {"ms": t * 1e3}
+            row["support"] = int(a.numel())
+            log(f"[spmspv] level {k} |x|={len(front)} entries {row['entries']} {sr}: {t * 1e3:.3f} ms, "
+                f"support {a.numel()}")
+        out.append(row)
+    G.close()
+    return {"levels": out}
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="batching measurements (many sources, many graphs)")
-    ap.add_argument("--only", choices=["sources", "graphs", "compare"], default=None)
+    ap.add_argument("--only", choices=["sources", "graphs", "compare", "spmspv"], default=None)
     ap.add_argument("--tune-cache", default="", help="autotune cache for per-graph parameters")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -230,6 +275,8 @@ def main(argv=None):
         out["many_graphs"] = many_graphs(tune_cache=a.tune_cache, log=log)
     if a.only in (None, "compare"):
         out["compare"] = compare(log=log)
+    if a.only in (None, "spmspv"):
+        out["spmspv"] = spmspv_levels(log=log)
     txt = json.dumps(out)
     if a.out:
         with open(a.out, "w") as f:
