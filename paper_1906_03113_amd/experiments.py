@@ -216,19 +216,19 @@ def compare(workloads=("er16k", "rmat20d", "rmat22", "grid1024", "grid4096"), lo
 
 def spmspv_levels(log=print) -> Dict:
     """The masked SpMSpV primitive on the levels of an R-MAT s22 search: for
-    each level k of the oracle's search from the first of the 64 bench sources
+    each level k of the search from the first of the 64 bench sources
     (pick_sources(g, 64, 22)[0]), x = F_k with x(j) = j and the row mask = the
     rows visited through level k, complemented; (min, select) and Boolean
     products, wall time of one call (which waits for the stream) after one
-    warm-up call."""
+    warm-up call.  The levels come from the library's own search."""
     import graphgen
-    import oracle
     import paper_1906_03113_amd as P
     torch = _torch()
     g = graphgen.workload("rmat22")
     G = P.Graph.from_graphgen(g)
     s = int(graphgen.pick_sources(g, 64, 22)[0])
-    wl, _ = oracle.bfs_graph(g, s)
+    lv, _ = P.bfs(G, s)
+    wl = lv.cpu().numpy()
     deg = np.diff(g.ptr.astype(np.int64))
     yi = torch.empty(g.n, dtype=torch.int32, device="cuda")
     yv = torch.empty(g.n, dtype=torch.int64, device="cuda")
