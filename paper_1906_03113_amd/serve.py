@@ -268,9 +268,10 @@ class Server:
 
 def run_load(executor: GpuExecutor, graph_names: Sequence[str], sources: Dict[str, np.ndarray],
              rate_qps: float, count: int, seed: int, budget_bytes: int, workers: int,
-             max_batch: int = 64) -> Dict[str, float]:
+             max_batch: int = 64, progress=None) -> Dict[str, float]:
     """Poisson arrivals at rate_qps, graph uniform, source uniform among the graph's
-    candidate sources; returns latency percentiles and throughput."""
+    candidate sources; returns latency percentiles and throughput.  `progress`
+    (optional) is called with a line every 500 submitted queries."""
     rng = np.random.default_rng(seed)
     arr = poisson_arrivals(rate_qps, count, seed)
     qs = []
@@ -287,6 +288,8 @@ def run_load(executor: GpuExecutor, graph_names: Sequence[str], sources: Dict[st
                 time.sleep(delay)
             q.arrival = srv.now()
             srv.submit(q)
+            if progress and (q.qid + 1) % 500 == 0:
+                progress(f"[serve]   {q.qid + 1}/{count} queries submitted at {rate_qps:.1f} q/s")
         srv.drain(qs)
         wall = srv.now() - t_start
     finally:
@@ -408,8 +411,10 @@ def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers
     res = {"saturation_qps_plain": sat_qps, "graphs": names, "rates": {}}
     for frac in rates:
         rate = frac * sat_qps
-        r_plain = run_load(plain, names, srcs, rate, queries, seed, budget_bytes, workers=1, max_batch=1)
-        r_fast = run_load(fast, names, srcs, rate, queries, seed, budget_bytes, workers=workers)
+        r_plain = run_load(plain, names, srcs, rate, queries, seed, budget_bytes, workers=1, max_batch=1,
+                           progress=log)
+        r_fast = run_load(fast, names, srcs, rate, queries, seed, budget_bytes, workers=workers,
+                          progress=log)
         res["rates"][str(frac)] = {"plain": r_plain, "batched_learned": r_fast}
         if log:
             log(f"[serve] {frac:.2f} x sat ({rate:.1f} q/s): plain p50 {r_plain['p50_ms']:.2f} ms "
