@@ -177,7 +177,11 @@ def main():
                     "kernel": "k_level", "launches_per_search": round(launches / (len(sources) * args.steps), 2),
                     "mean_launch_us": round(avg_us, 3),
                     "algorithmic_bytes_per_launch": round(avg_bytes),
-                    "kernel_us_per_search": round(kern_us / (len(sources) * args.steps), 2)}
+                    "kernel_us_per_search": round(kern_us / (len(sources) * args.steps), 2),
+                    "median_kernel_us_per_search": round(float(np.median([i["kernel_us"] for i in infos])), 2),
+                    # the same bytes over the whole timed step (init, host round trips included)
+                    "end_to_end_GBps": round(bytes_total / (dt * args.steps) / 1e9, 1),
+                    "end_to_end_frac": round(bytes_total / (dt * args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"[bench] k_level: {launches} launches, mean {avg_us:.2f} us, {ach:.1f} GB/s algorithmic "
             f"({ach / HBM_PEAK_GBS * 100:.1f}% of 8 TB/s)")
 
