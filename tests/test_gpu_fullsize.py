@@ -1,7 +1,9 @@
 """Parity at the full workload sizes: R-MAT scale 22 (undirected), the 4096^2
 percolated grid (thousands of levels) and R-MAT scale 20 (directed), each in
-the launch configurations bench.py times.  Whole arrays are compared with the
-oracle (it finishes in about a second per search at these sizes)."""
+the launch configurations bench.py times; the batching workloads (256
+sources in one call, the 64-graph ER pack); the comparison searches and the
+masked SpMSpV primitive.  Whole arrays are compared with the oracle (it
+finishes in about a second per search at these sizes)."""
 import numpy as np
 import pytest
 
@@ -124,3 +126,44 @@ def test_masked_spmspv_full_size():
         assert np.array_equal(yi.cpu().numpy(), want), k
         assert np.array_equal(yv.cpu().numpy(), wp[want].astype(np.int64)), k
     G.close()
+
+
+def test_rmat20d_batch_of_256():
+    """256 sources in one call on directed R-MAT s20 (4 mask words per vertex),
+    the launch the batching measurement times; sampled queries, whole arrays."""
+    P = need_gpu()
+    import torch
+    g = graphgen.workload("rmat20d")
+    G = P.Graph.from_graphgen(g)
+    src = [int(s) for s in graphgen.pick_sources(g, 256, 41)]
+    say("[full] rmat20d multi-source x256")
+    lv, pa = P.bfs_batch(G, src, variant="heuristic")
+    torch.cuda.synchronize()
+    for q in (0, 63, 64, 130, 255):
+        _check(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"rmat20d batch q{q}")
+
+
+def test_er_pack_of_64_graphs():
+    """The 64 uneven ER graphs packed block-diagonally, one root per block, as
+    one persistent launch and as the graph loop: every block against the
+    oracle's search of its own graph."""
+    P = need_gpu()
+    import torch
+    gs = graphgen.er_family(count=64, lo=10, hi=18, dmin=4, dmax=32)
+    packed, offs = graphgen.block_diagonal(gs)
+    G = P.Graph.from_graphgen(packed)
+    roots = []
+    for b, g in enumerate(gs):
+        nz = np.nonzero(g.out_degree() > 0)[0]
+        roots.append(int(offs[b] + (nz[0] if len(nz) else 0)))
+    want = [oracle.bfs_graph(g, roots[b] - int(offs[b])) for b, g in enumerate(gs)]
+    for loop in ("persistent", "graph"):
+        say(f"[full] ER pack x64 loop={loop}")
+        lv, pa = P.bfs_roots(G, roots, loop=loop)
+        torch.cuda.synchronize()
+        lv, pa = lv.cpu().numpy(), pa.cpu().numpy()
+        for b in range(len(gs)):
+            o0, o1 = int(offs[b]), int(offs[b + 1])
+            wl, wp = want[b]
+            assert np.array_equal(lv[o0:o1], wl), (loop, b)
+            assert np.array_equal(pa[o0:o1], np.where(wp >= 0, wp + o0, -1)), (loop, b)
