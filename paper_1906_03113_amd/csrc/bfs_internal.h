@@ -21,21 +21,20 @@ enum Variant : uint32_t { kPush = 0, kPull = 1, kBitmap = 2, kLearned = 3, kHeur
 // Device-resident search state (first bytes of every workspace).
 struct alignas(256) BfsState {
     uint32_t level;          // current level k
-    uint32_t done;           // blocks of the level kernel that have finished
     uint32_t variant;        // variant run at level k
     uint32_t u_buf;          // which unvisited-list buffer is current
     uint32_t u_len;          // its length; kAllVertices = the implicit list 0..n-1
     uint32_t u_wr;           // appends into the other buffer during a pull level
     uint32_t visited_cnt;    // |B_k|
-    uint32_t barrier;        // grid barrier counter (persistent mode)
     unsigned long long visited_deg;   // sum of out-degrees over B_k
     uint32_t nf[kRing];                  // |F| (short columns, in the list) per ring slot
     unsigned long long heavy[kRing];     // long columns: (#columns) | (#chunks << 32)
     unsigned long long sdf[kRing];       // sum of out-degrees over F per ring slot
     uint32_t barrier_gen;
     uint32_t pad[7];
-    // two-level grid barrier (persistent mode): one arrival counter per group
-    // of blocks, each on its own 64-byte line, then one for the groups
+    // arrivals at the end of a level (every level launch, and the persistent
+    // kernel's grid barrier): one counter per group of blocks, each on its own
+    // 64-byte line, then one for the groups
     uint32_t bar_group[kBarGroups * 16];
     uint32_t bar_top;
     uint32_t pad2[15];

@@ -1009,12 +1009,10 @@ __global__ __launch_bounds__(kBlock) void k_init(LevelParams P, int32_t single_r
     if (gid == 0) {
         BfsState *st = P.st;
         st->level = 0;
-        st->done = 0;
         st->variant = 0;
         st->u_buf = 0;
         st->u_len = kAllVertices;
         st->u_wr = 0;
-        st->barrier = 0;
         st->barrier_gen = 0;
         for (int g = 0; g < kBarGroups; ++g) st->bar_group[g * 16] = 0;
         st->bar_top = 0;
