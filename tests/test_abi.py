@@ -106,3 +106,32 @@ def test_compare_entry_points_reject_bad_arguments(L):
     rc = L.bfs_run_compare(None, 0, 0, None, None, None, 0, ctypes.byref(ops), ctypes.byref(steps), None)
     assert rc == B.BFS_EINVAL and L.bfs_last_error_detail()
     assert ops.value == 7 and steps.value == 7          # outputs untouched on error
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/bfs.h is a C99 header (no C++ in the signatures), and a C
+    program links the library and gets its validation errors without a GPU."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include <stdio.h>\n#include "bfs.h"\n'
+        "int main(void) {\n"
+        "    bfs_graph *g = NULL;\n"
+        "    int32_t ptr[3] = {0, 1, 2}, idx[2] = {1, 0};\n"
+        "    bfs_status s = bfs_graph_create(0, ptr, idx, NULL, NULL, 0, NULL, &g);\n"
+        "    if (s != BFS_EINVAL || g != NULL) return 1;\n"
+        "    if (bfs_workspace_size(NULL, 1, 0) != 0) return 2;\n"
+        '    printf("%s|%s\\n", bfs_status_string(s), bfs_last_error_detail());\n'
+        "    return 0;\n}\n")
+    exe = tmp_path / "abi"
+    lib_dir = os.path.join(ROOT, "paper_1906_03113_amd")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                    os.path.join(ROOT, "include"), str(src), "-L", lib_dir, "-lbfs",
+                    "-Wl,-rpath," + lib_dir, "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    assert "|" in r.stdout and r.stdout.split("|")[1].strip()
