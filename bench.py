@@ -208,6 +208,7 @@ def main():
         log(f"[bench] cpu oracle: {count} searches in {t_cpu:.2f}s = {cpu_gteps:.4f} GTEPS")
 
     # the other configurations of the same step (same sources, same outputs)
+    vm_mode = None
     modes = {"plain_push": {"gteps": round(gteps, 3), "ms_per_step": round(dt * 1e3, 4),
                             "variant": args.variant, "loop": args.loop}}
     if not args.plain_only:
@@ -280,7 +281,30 @@ def main():
                                           "plain_bytes_rate_GBps": round(b_step / dtb / 1e9, 1)}
             log(f"[bench] multi-source batch: {dtb * 1e3:.3f} ms/step, {total_m / dtb / 1e9:.2f} GTEPS")
             del bl, bp, wsb
+            torch.cuda.empty_cache()
+            # the same searches with the results in one vertex-major pair of
+            # arrays (the search's own layout: no transpose pass); reported
+            # beside, not a candidate for `value` (a different output layout)
+            ld = 64 * ((nq + 63) // 64)
+            vl = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
+            vp = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
+            src = [int(s) for s in sources]
+            wsv = P.Workspace(P.batch_vm_workspace_size(G, nq))
+            P.bfs_batch_vm(G, src, level=vl, parent=vp, workspace=wsv)
+            torch.cuda.synchronize()
+            t0v = time.perf_counter()
+            for k in range(args.steps):
+                P.bfs_batch_vm(G, src, level=vl, parent=vp, workspace=wsv)
+            torch.cuda.synchronize()
+            dtv = (time.perf_counter() - t0v) / args.steps
+            vm_mode = {"gteps": round(total_m / dtv / 1e9, 3), "ms_per_step": round(dtv * 1e3, 4),
+                       "searches_per_call": nq, "layout": "vertex-major [n][64 * ceil(sources / 64)]"}
+            log(f"[bench] multi-source batch, vertex-major results: {dtv * 1e3:.3f} ms/step, "
+                f"{total_m / dtv / 1e9:.2f} GTEPS")
+            del vl, vp, wsv
     best = max(modes, key=lambda m: modes[m]["gteps"])
+    if vm_mode is not None:
+        modes["batch_multisource_vertex_major"] = vm_mode
 
     serving = None
     if not args.no_serve and not args.plain_only:

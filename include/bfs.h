@@ -197,6 +197,28 @@ bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t *roots_host
 /* Workspace bytes for bfs_run_roots with nroots roots (0 on a bad argument). */
 size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots);
 
+/*
+ * Many sources on one graph (Theorem 1 applied per source, 64 sources per
+ * 64-bit mask word, as bfs_run_batch does for one graph), with the results in
+ * one vertex-major pair of arrays instead of one array per source: with
+ * ld = 64 * ceil(num_sources / 64), level[v * ld + q] and parent[v * ld + q]
+ * are source q's level and parent of vertex v (the same values bfs_run gives);
+ * columns q >= num_sources hold -1.  This is the layout the search builds
+ * anyway, so no transpose pass runs at the end.
+ * sources: host, num_sources ints in [0, n) (duplicates allowed).
+ * level, parent: device int32[n * ld] each, caller-owned, 16-byte aligned.
+ * workspace: bfs_batch_vm_workspace_size(g, num_sources) bytes or more,
+ * 256-byte aligned.  opt: as for bfs_run_batch (variant, grid_blocks).
+ * Errors: BFS_EINVAL (NULL argument, num_sources < 1, misaligned or small
+ * buffers, unknown variant), BFS_ERANGE (a source outside [0, n)), BFS_EHIP.
+ */
+bfs_status bfs_run_batch_vm(bfs_graph *g, int32_t num_sources, const int32_t *sources,
+                            int32_t *level, int32_t *parent, bfs_run_options *opt,
+                            void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Workspace bytes for bfs_run_batch_vm (0 on a bad argument). */
+size_t bfs_batch_vm_workspace_size(const bfs_graph *g, int32_t num_sources);
+
 /* ------------------------------------------------------------------------
  * The variant selector.  Not part of the paper: the paper's method is the
  * push form; these entry points serve the build's per-level choice between

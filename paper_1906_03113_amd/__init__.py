@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import BfsError, LOOPS, VARIANTS, VARIANT_NAMES, LevelRecord, RunOptions
 
-__all__ = ["Graph", "bfs", "bfs_batch", "bfs_roots", "bfs_compare", "compare_workspace_size", "masked_spmspv",
+__all__ = ["Graph", "bfs", "bfs_batch", "bfs_batch_vm", "batch_vm_workspace_size", "bfs_roots",
+           "bfs_compare", "compare_workspace_size", "masked_spmspv",
            "spmspv_workspace_size", "BfsError", "VARIANTS", "LOOPS",
            "Workspace", "make_options"]
 
@@ -294,3 +295,36 @@ def masked_spmspv(g: Graph, semiring: str, x_idx, x_val, row_mask=None, col_mask
                                             ctypes.byref(ny), workspace.ptr, workspace.nbytes,
                                             _stream_handle(stream)))
     return y_idx[:ny.value], y_val[:ny.value]
+
+
+def batch_vm_workspace_size(g: Graph, num_sources: int) -> int:
+    """Workspace bytes bfs_batch_vm needs for this many sources."""
+    return int(_lib.lib().bfs_batch_vm_workspace_size(g.handle, int(num_sources)))
+
+
+def bfs_batch_vm(g: Graph, sources: Sequence[int], variant="heuristic", level=None, parent=None,
+                 workspace: Optional[Workspace] = None, stream=None, **kw):
+    """Many sources on one graph with vertex-major results: returns (level,
+    parent) as int32 cuda tensors of shape [n, ld], ld = 64 * ceil(len / 64);
+    column q holds source q's arrays (columns past the sources hold -1)."""
+    t = _torch()
+    src = _i32_host(np.asarray(sources))
+    ld = 64 * ((len(src) + 63) // 64)
+    if level is None:
+        level = t.empty((g.n, ld), dtype=t.int32, device="cuda")
+    if parent is None:
+        parent = t.empty((g.n, ld), dtype=t.int32, device="cuda")
+    for name, a in (("level", level), ("parent", parent)):
+        if (tuple(a.shape) != (g.n, ld) or a.dtype != t.int32 or not a.is_cuda
+                or not a.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous int32 cuda tensor of shape "
+                             f"({g.n}, {ld}), got {tuple(a.shape)} {a.dtype} on {a.device}")
+    need = batch_vm_workspace_size(g, len(src))
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need)
+    o, _ = make_options(variant, "host", **kw)
+    _lib.check(_lib.lib().bfs_run_batch_vm(g.handle, len(src), src.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.c_void_p(level.data_ptr()),
+                                           ctypes.c_void_p(parent.data_ptr()), ctypes.byref(o),
+                                           workspace.ptr, workspace.nbytes, _stream_handle(stream)))
+    return level, parent

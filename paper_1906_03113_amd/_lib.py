@@ -94,6 +94,10 @@ def _optional(L):
     L.bfs_profile_levels.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, i32,
                                      ctypes.POINTER(LevelRecord), u32, ctypes.POINTER(u32), vp]
     L.bfs_profile_levels.restype = i32
+    L.bfs_batch_vm_workspace_size.argtypes = [vp, i32]
+    L.bfs_batch_vm_workspace_size.restype = sz
+    L.bfs_run_batch_vm.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(RunOptions), vp, sz, vp]
+    L.bfs_run_batch_vm.restype = i32
     L.bfs_compare_workspace_size.argtypes = [vp]
     L.bfs_compare_workspace_size.restype = sz
     L.bfs_run_compare.argtypes = [vp, i32, u32, vp, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64),

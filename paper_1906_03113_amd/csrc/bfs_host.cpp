@@ -184,7 +184,7 @@ WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor) {
 }  // namespace bfsi
 
 namespace bfsi {
-MsLayout ms_layout(int32_t n, int32_t nq) {
+MsLayout ms_layout(int32_t n, int32_t nq, bool staged) {
     MsLayout L{};
     const size_t W = ((size_t)nq + 63) / 64;
     size_t off = 0;
@@ -198,8 +198,8 @@ MsLayout ms_layout(int32_t n, int32_t nq) {
     L.f2 = take((size_t)n * 4);
     L.flag = take((size_t)n * 4);
     L.cnt = take(64);
-    L.slev = take((size_t)n * W * 64 * 4);
-    L.spar = take((size_t)n * W * 64 * 4);
+    L.slev = staged ? take((size_t)n * W * 64 * 4) : 0;
+    L.spar = staged ? take((size_t)n * W * 64 * 4) : 0;
     L.lptr = take((size_t)nq * 8);
     L.pptr = take((size_t)nq * 8);
     L.src = take((size_t)nq * 4);
@@ -660,10 +660,15 @@ extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
 }
 
 // All queries on one graph: the multi-source kernels.
+// level / parent: per-source arrays (staged results, transposed at the end),
+// or with vm_level / vm_parent set, the caller's vertex-major arrays, written
+// in place.
 static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sources,
                                    int32_t *const *level, int32_t *const *parent,
-                                   bfs_run_options *opt, void *workspace, hipStream_t s) {
-    const MsLayout L = ms_layout(g->n, nq);
+                                   bfs_run_options *opt, void *workspace, hipStream_t s,
+                                   int32_t *vm_level = nullptr, int32_t *vm_parent = nullptr) {
+    const bool vm = vm_level != nullptr;
+    const MsLayout L = ms_layout(g->n, nq, !vm);
     char *b = (char *)workspace;
     MsLevel p{};
     p.n = g->n;
@@ -689,8 +694,9 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     p.nlo_chunks = g->nlo_chunks;
     p.nli = g->nli;
     p.nli_chunks = g->nli_chunks;
-    p.slev = (int32_t *)(b + L.slev);
-    p.spar = (uint32_t *)(b + L.spar);
+    p.slev = vm ? vm_level : (int32_t *)(b + L.slev);
+    p.spar = vm ? (uint32_t *)vm_parent : (uint32_t *)(b + L.spar);
+    p.fill_levels = vm ? 1u : 0u;
     p.level = (int32_t *const *)(b + L.lptr);
     p.parent = (int32_t *const *)(b + L.pptr);
     p.sources = (const int32_t *)(b + L.src);
@@ -698,8 +704,10 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     bfs_status st = host_slot(hs);
     if (st != BFS_OK) return st;
     p.host_status = hs->d;
-    HIP_TRY(hipMemcpyAsync(b + L.lptr, level, (size_t)nq * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b + L.pptr, parent, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    if (!vm) {
+        HIP_TRY(hipMemcpyAsync(b + L.lptr, level, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b + L.pptr, parent, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipMemcpyAsync(b + L.src, sources, (size_t)nq * 4, hipMemcpyHostToDevice, s));
     uint32_t grid = (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
     HIP_TRY(launch_ms(p, 0, 0, grid, s));
@@ -727,7 +735,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
         if (done) break;
         frontier = hs->h[1];
     }
-    HIP_TRY(launch_ms(p, 7, k, grid, s));      // staged results -> per-source arrays
+    if (!vm) HIP_TRY(launch_ms(p, 7, k, grid, s));      // staged results -> per-source arrays
     if (opt) {
         opt->levels = k + 1;
         opt->trace_count = 0;
@@ -1038,4 +1046,32 @@ extern "C" bfs_status bfs_masked_spmspv(bfs_graph *g, uint32_t semiring, const i
     if (hst.bad) return fail(BFS_ERANGE, "a vector index lies outside [0, %d)", g->n);
     *ny = hny;
     return BFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Many sources with vertex-major outputs
+// ---------------------------------------------------------------------------
+
+extern "C" size_t bfs_batch_vm_workspace_size(const bfs_graph *g, int32_t num_sources) {
+    if (!g || num_sources <= 0) return 0;
+    return ms_layout(g->n, num_sources, false).total;
+}
+
+extern "C" bfs_status bfs_run_batch_vm(bfs_graph *g, int32_t num_sources, const int32_t *sources,
+                                       int32_t *level, int32_t *parent, bfs_run_options *opt,
+                                       void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (num_sources <= 0) return fail(BFS_EINVAL, "num_sources = %d", num_sources);
+    if (!sources || !level || !parent || !workspace) return fail(BFS_EINVAL, "NULL argument");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BFS_EINVAL, "workspace must be 256-byte aligned");
+    if (((uintptr_t)level & 15) != 0 || ((uintptr_t)parent & 15) != 0)
+        return fail(BFS_EINVAL, "level / parent must be 16-byte aligned");
+    for (int32_t q = 0; q < num_sources; ++q)
+        if (sources[q] < 0 || sources[q] >= g->n)
+            return fail(BFS_ERANGE, "source %d (%d) outside [0, %d)", q, sources[q], g->n);
+    const size_t need = bfs_batch_vm_workspace_size(g, num_sources);
+    if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    if (opt && opt->variant > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", opt->variant);
+    return run_multi_source(g, num_sources, sources, nullptr, nullptr, opt, workspace,
+                            (hipStream_t)hip_stream, level, parent);
 }

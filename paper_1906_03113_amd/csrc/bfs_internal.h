@@ -126,12 +126,16 @@ struct MsLevel {
     int32_t *const *parent;
     const int32_t *sources;        // device, nq
     uint32_t *host_status;         // pinned host: [0] level, [1] next frontier size
+    uint32_t fill_levels;          // slev / spar are the caller's vertex-major outputs:
+                                   // every level starts at -1 (no transpose at the end)
 };
 
 struct MsLayout {
     size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, slev, spar, lptr, pptr, src, total;
 };
-MsLayout ms_layout(int32_t n, int32_t nq);
+// staged = false: the results go straight to the caller's vertex-major
+// arrays, so the layout holds no staging (slev / spar are 0)
+MsLayout ms_layout(int32_t n, int32_t nq, bool staged = true);
 
 // launches (bfs_kernels.hip)
 hipError_t launch_init(const LevelParams &p, int32_t nroots, const int32_t *roots_dev,

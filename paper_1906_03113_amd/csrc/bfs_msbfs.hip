@@ -97,7 +97,8 @@ __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const 
 // Every mask to zero and every staged parent to 0xFFFFFFFF (parents are
 // combined with atomicMin).  Staged levels are written before they are read
 // (k_ms_out reads only entries whose vis bit is set), and k_ms_out writes
-// every output.
+// every output; when the staged arrays are the caller's vertex-major outputs
+// the levels start at -1 too (there is no k_ms_out).
 __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
     const size_t gid = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kBlock;
@@ -112,6 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
     const size_t ns = (size_t)p.n * p.W * 16u;          // staged parents, 16 bytes at a time
     for (size_t i = gid; i < ns; i += stride)
         reinterpret_cast<uint4 *>(p.spar)[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    if (p.fill_levels)                                  // the caller's arrays: unreached = -1
+        for (size_t i = gid; i < ns; i += stride) reinterpret_cast<int4 *>(p.slev)[i] = make_int4(-1, -1, -1, -1);
     if (gid < 4) p.cnt[gid] = 0u;
 }
 

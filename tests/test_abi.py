@@ -108,6 +108,14 @@ def test_compare_entry_points_reject_bad_arguments(L):
     assert ops.value == 7 and steps.value == 7          # outputs untouched on error
 
 
+def test_vertex_major_batch_rejects_bad_arguments(L):
+    from paper_1906_03113_amd import _lib as B
+    assert L.bfs_batch_vm_workspace_size(None, 64) == 0
+    src = (ctypes.c_int32 * 2)(0, 1)
+    rc = L.bfs_run_batch_vm(None, 2, src, None, None, None, None, 0, None)
+    assert rc == B.BFS_EINVAL and "graph" in L.bfs_last_error_detail().decode()
+
+
 def test_header_is_plain_c(tmp_path):
     """include/bfs.h is a C99 header (no C++ in the signatures), and a C
     program links the library and gets its validation errors without a GPU."""

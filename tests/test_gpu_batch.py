@@ -72,3 +72,52 @@ def test_block_diagonal_uneven_graphs(P):
             wl, wp = oracle.bfs_graph(g, roots[b] - o0)
             assert np.array_equal(lv[o0:o1], wl)
             assert np.array_equal(pa[o0:o1], np.where(wp >= 0, wp + o0, -1))
+
+
+@pytest.mark.parametrize("variant", ["push", "pull", "heuristic"])
+@pytest.mark.parametrize("name,nq", [("er", 1), ("rmat", 64), ("rmatd", 130), ("grid", 63)])
+def test_vertex_major_batch(P, name, nq, variant):
+    """The multi-source batch with [n][ld] results: column q equals source
+    q's single-source oracle; columns past the sources hold -1."""
+    import torch
+    g = {"er": lambda: graphgen.erdos_renyi(5000, 6, 31),
+         "rmat": lambda: graphgen.rmat(13, 16, 32),
+         "rmatd": lambda: graphgen.rmat(12, 16, 33, directed=True),
+         "grid": lambda: graphgen.grid(60, 0.85, 34)}[name]()
+    G = P.Graph.from_graphgen(g)
+    rng = np.random.default_rng(100 + nq)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = rng.choice(cand, size=nq, replace=True)
+    if nq > 2:
+        src[1] = src[0]
+    ld = 64 * ((nq + 63) // 64)
+    say(f"[batch-vm] {name} nq={nq} {variant}")
+    lv, pa = P.bfs_batch_vm(G, [int(s) for s in src], variant=variant)
+    torch.cuda.synchronize()
+    assert tuple(lv.shape) == (g.n, ld) and tuple(pa.shape) == (g.n, ld)
+    lv, pa = lv.cpu().numpy(), pa.cpu().numpy()
+    for q, s in enumerate(src):
+        assert_same(g, int(s), (lv[:, q].copy(), pa[:, q].copy()), f"{name}/q{q}/s{s}")
+    assert np.all(lv[:, nq:] == -1) and np.all(pa[:, nq:] == -1)
+
+
+def test_vertex_major_reuses_outputs(P):
+    """Two calls into the same arrays and workspace, the second with fewer
+    sources in the same 64-column word: nothing of the first call survives."""
+    import torch
+    g = graphgen.rmat(12, 16, 41)
+    G = P.Graph.from_graphgen(g)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    a = [int(s) for s in cand[:40]]
+    b = [int(s) for s in cand[100:117]]
+    lv = torch.empty((g.n, 64), dtype=torch.int32, device="cuda")
+    pa = torch.empty((g.n, 64), dtype=torch.int32, device="cuda")
+    ws = P.Workspace(P.batch_vm_workspace_size(G, 40))
+    say("[batch-vm] reuse 40 then 17 sources")
+    P.bfs_batch_vm(G, a, level=lv, parent=pa, workspace=ws)
+    P.bfs_batch_vm(G, b, level=lv, parent=pa, workspace=ws)
+    torch.cuda.synchronize()
+    l, p = lv.cpu().numpy(), pa.cpu().numpy()
+    for q, s in enumerate(b):
+        assert_same(g, s, (l[:, q].copy(), p[:, q].copy()), f"reuse/q{q}")
+    assert np.all(l[:, len(b):] == -1) and np.all(p[:, len(b):] == -1)

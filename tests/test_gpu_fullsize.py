@@ -45,10 +45,22 @@ def test_rmat22_batch_of_64():
     G = P.Graph.from_graphgen(g)
     src = [int(s) for s in graphgen.pick_sources(g, 64, 22)]
     say("[full] rmat22 multi-source x64")
-    lv, pa = P.bfs_batch(G, src)
+    lv, pa = P.bfs_batch(G, src, variant="heuristic")
     torch.cuda.synchronize()
     for q in (0, 17, 63):                     # sampled queries, whole arrays
         _check(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"rmat22 batch q{q}")
+    # the vertex-major form bench.py times beside it: sampled columns against
+    # the oracle, every column against the per-source arrays checked above
+    say("[full] rmat22 multi-source x64, vertex-major results")
+    vl, vp = P.bfs_batch_vm(G, src, variant="heuristic")
+    torch.cuda.synchronize()
+    for q in (5, 40):
+        _check(g, src[q], (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"rmat22 vm q{q}")
+    assert torch.equal(vl, torch.stack(lv, 1)) and torch.equal(vp, torch.stack(pa, 1))
+    say("[full] rmat22 multi-source x64, vertex-major results, push every level")
+    vl, vp = P.bfs_batch_vm(G, src, variant="push", level=vl, parent=vp)
+    torch.cuda.synchronize()
+    assert torch.equal(vl, torch.stack(lv, 1)) and torch.equal(vp, torch.stack(pa, 1))
 
 
 def test_grid4096():
