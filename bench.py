@@ -11,8 +11,8 @@ component, each undirected edge once) / wall time of the step.
 roofline = the level kernel (k_level): algorithmic bytes per launch / mean
 launch duration, the durations from HIP events around every launch in the
 timed region.
-cpu_baseline = the CPU oracle (queue BFS + min-parent pass, one thread) timed
-on a bounded sample of the same searches.
+cpu_baseline = the CPU oracle (queue BFS + min-parent pass, one thread pinned
+to one core) timed on a bounded sample of the same searches.
 """
 from __future__ import annotations
 
@@ -58,6 +58,17 @@ WORKLOADS = {
     "grid4096": ("grid4096", 16, 31, "4096x4096 grid, edges kept with p=0.9, undirected"),
     "rmatd20": ("rmat20d", 16, 32, "R-MAT scale 20, edgefactor 16, directed (out-edges)"),
 }
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -197,13 +208,22 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         ip, ii = g.csc()
-        t_first = oracle.time_queue_bfs(g.n, g.ptr, g.idx, sources[:1], ip, ii)
-        count = max(1, min(len(sources), int(args.cpu_seconds / max(t_first, 1e-6))))
-        t_cpu = oracle.time_queue_bfs(g.n, g.ptr, g.idx, sources[:count], ip, ii) if count > 1 else t_first
+        # single thread, pinned to one core of those this process may use
+        allowed = sorted(os.sched_getaffinity(0))
+        core = allowed[-1]
+        os.sched_setaffinity(0, {core})
+        try:
+            t_first = oracle.time_queue_bfs(g.n, g.ptr, g.idx, sources[:1], ip, ii)
+            count = max(1, min(len(sources), int(args.cpu_seconds / max(t_first, 1e-6))))
+            t_cpu = (oracle.time_queue_bfs(g.n, g.ptr, g.idx, sources[:count], ip, ii)
+                     if count > 1 else t_first)
+        finally:
+            os.sched_setaffinity(0, allowed)
         cpu_gteps = float(sum(m_c[:count])) / t_cpu / 1e9
         cpu = {"value": round(cpu_gteps, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"first {count} of the {len(sources)} sources of the step "
                          f"({t_cpu:.2f} s, single thread, queue BFS + min-parent pass)",
+               "pinned_core": core, "host_cpus": len(allowed), "host_cpu_model": _cpu_model(),
                "gpu_over_cpu": round(gteps / cpu_gteps, 1)}
         log(f"[bench] cpu oracle: {count} searches in {t_cpu:.2f}s = {cpu_gteps:.4f} GTEPS")
 
