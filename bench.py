@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--ms-pull-shift", type=int, default=-1,
+                    help="multi-source pull threshold n >> shift (-1 = measure 5, 7, ..., 13 first, 0 = n/32)")
     ap.add_argument("--serve-queries", type=int, default=300)
     ap.add_argument("--selector", default=None,
                     help="selector weights (JSON); default: the trained weights in the package")
@@ -277,16 +279,34 @@ def main():
         # all sources in one multi-source call (64 per mask word)
         nq = len(sources)
         if nq > 1:
+            src = [int(s) for s in sources]
+            ld = 64 * ((nq + 63) // 64)
+            vl = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
+            vp = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
+            wsv = P.Workspace(P.batch_vm_workspace_size(G, nq))
+            # the multi-source direction threshold (pull once the union
+            # frontier holds more than n >> shift vertices): the autotuner's
+            # measured search over these sources, before the timed region
+            shift, tuning = args.ms_pull_shift, None
+            if shift < 0:
+                from paper_1906_03113_amd import autotune as AT
+                tr = AT.tune_pull_shift(
+                    G, src, cache=None,
+                    timer=lambda G_, s_, sh: AT.time_pull_shift(G_, s_, sh, reps=2, out=(vl, vp, wsv)))
+                shift = tr["shift"]
+                tuning = {k: round(v * 1e3, 3) for k, v in tr["times_s"].items()}
+                log(f"[bench] multi-source pull shift {shift} "
+                    f"(ms per call: {', '.join(f'{k}: {v}' for k, v in tuning.items())})")
             bl = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(nq)]
             bp = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(nq)]
             wsb = P.Workspace(G.workspace_size(nq))
-            P.bfs_batch(G, [int(s) for s in sources], levels=bl, parents=bp, workspace=wsb,
-                        variant="heuristic")
+            P.bfs_batch(G, src, levels=bl, parents=bp, workspace=wsb, variant="heuristic",
+                        ms_pull_shift=shift)
             torch.cuda.synchronize()
             t0b = time.perf_counter()
             for k in range(args.steps):
-                P.bfs_batch(G, [int(s) for s in sources], levels=bl, parents=bp, workspace=wsb,
-                            variant="heuristic")
+                P.bfs_batch(G, src, levels=bl, parents=bp, workspace=wsb, variant="heuristic",
+                            ms_pull_shift=shift)
             torch.cuda.synchronize()
             dtb = (time.perf_counter() - t0b) / args.steps
             # the per-search algorithmic bytes of the plain form, summed over the
@@ -297,6 +317,8 @@ def main():
             modes["batch_multisource"] = {"gteps": round(total_m / dtb / 1e9, 3),
                                           "ms_per_step": round(dtb * 1e3, 4),
                                           "searches_per_call": nq,
+                                          "ms_pull_shift": shift or 5,
+                                          "pull_shift_tuning_ms_per_call": tuning,
                                           "plain_bytes_per_step": round(b_step),
                                           "plain_bytes_rate_GBps": round(b_step / dtb / 1e9, 1)}
             log(f"[bench] multi-source batch: {dtb * 1e3:.3f} ms/step, {total_m / dtb / 1e9:.2f} GTEPS")
@@ -305,20 +327,16 @@ def main():
             # the same searches with the results in one vertex-major pair of
             # arrays (the search's own layout: no transpose pass); reported
             # beside, not a candidate for `value` (a different output layout)
-            ld = 64 * ((nq + 63) // 64)
-            vl = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
-            vp = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
-            src = [int(s) for s in sources]
-            wsv = P.Workspace(P.batch_vm_workspace_size(G, nq))
-            P.bfs_batch_vm(G, src, level=vl, parent=vp, workspace=wsv)
+            P.bfs_batch_vm(G, src, level=vl, parent=vp, workspace=wsv, ms_pull_shift=shift)
             torch.cuda.synchronize()
             t0v = time.perf_counter()
             for k in range(args.steps):
-                P.bfs_batch_vm(G, src, level=vl, parent=vp, workspace=wsv)
+                P.bfs_batch_vm(G, src, level=vl, parent=vp, workspace=wsv, ms_pull_shift=shift)
             torch.cuda.synchronize()
             dtv = (time.perf_counter() - t0v) / args.steps
             vm_mode = {"gteps": round(total_m / dtv / 1e9, 3), "ms_per_step": round(dtv * 1e3, 4),
-                       "searches_per_call": nq, "layout": "vertex-major [n][64 * ceil(sources / 64)]"}
+                       "searches_per_call": nq, "ms_pull_shift": shift or 5,
+                       "layout": "vertex-major [n][64 * ceil(sources / 64)]"}
             log(f"[bench] multi-source batch, vertex-major results: {dtv * 1e3:.3f} ms/step, "
                 f"{total_m / dtv / 1e9:.2f} GTEPS")
             del vl, vp, wsv

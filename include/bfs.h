@@ -97,6 +97,11 @@ typedef struct bfs_run_options {
     uint32_t grid_blocks;      /* workgroups per level launch (0 = 8 per compute unit)          */
     uint32_t heavy_degree;     /* out-degree from which a column is split into chunks (0 = 512) */
     uint32_t chunk_edges;      /* entries per chunk of a split column (0 = 1024)                */
+    uint32_t ms_pull_shift;    /* multi-source searches (bfs_run_batch on one graph,
+                                  bfs_run_batch_vm) under BFS_VARIANT_HEURISTIC / LEARNED: a
+                                  level runs in the pull form when the union frontier holds
+                                  more than n >> ms_pull_shift vertices (0 = 5, i.e. n / 32;
+                                  at most 31, else BFS_EINVAL).  Never changes a result.       */
     const float *selector;     /* device: selector weights for BFS_VARIANT_LEARNED (NULL =
                                   push on every level)                                          */
     bfs_level_record *trace;   /* host: per-level records, or NULL                              */

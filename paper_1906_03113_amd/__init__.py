@@ -134,7 +134,7 @@ class Workspace:
 
 def make_options(variant="push", loop="host", levels_per_sync=0, grid_blocks=0,
                  heavy_degree=0, chunk_edges=0, selector=None, trace_capacity=0,
-                 time_kernels=False) -> Tuple[RunOptions, Optional[ctypes.Array]]:
+                 time_kernels=False, ms_pull_shift=0) -> Tuple[RunOptions, Optional[ctypes.Array]]:
     o = RunOptions()
     o.time_kernels = 1 if time_kernels else 0
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
@@ -143,6 +143,7 @@ def make_options(variant="push", loop="host", levels_per_sync=0, grid_blocks=0,
     o.grid_blocks = int(grid_blocks)
     o.heavy_degree = int(heavy_degree)
     o.chunk_edges = int(chunk_edges)
+    o.ms_pull_shift = int(ms_pull_shift)
     o.selector = ctypes.c_void_p(int(selector.data_ptr())) if selector is not None else None
     recs = None
     if trace_capacity:

@@ -28,7 +28,7 @@ class RunOptions(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_uint32), ("loop_mode", ctypes.c_uint32),
                 ("levels_per_sync", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
                 ("heavy_degree", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
-                ("selector", ctypes.c_void_p),
+                ("ms_pull_shift", ctypes.c_uint32), ("selector", ctypes.c_void_p),
                 ("trace", ctypes.POINTER(LevelRecord)), ("trace_capacity", ctypes.c_uint32),
                 ("time_kernels", ctypes.c_uint32), ("trace_count", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32), ("launches", ctypes.c_uint32),

@@ -13,7 +13,9 @@ the graph itself (a few searches per candidate) and cached under a shape key:
 
 The cache is a JSON file; `lookup` returns the cached parameters (or the
 defaults) for any graph of the same shape.  `tune_batch_width` does the same
-for the number of sources per multi-source call (`lookup_batch_width`).
+for the number of sources per multi-source call (`lookup_batch_width`), and
+`tune_pull_shift` for the frontier size from which a multi-source level runs
+in the pull form (`lookup_pull_shift`).
 """
 from __future__ import annotations
 
@@ -197,6 +199,73 @@ def lookup_batch_width(G, levels: int, cache: str = DEFAULT_CACHE, default: int 
     return int(e["width"]) if e else default
 
 
+PULL_SHIFTS = (5, 7, 9, 11, 13)
+
+
+def time_pull_shift(G, sources: Sequence[int], shift: int, reps: int = 2, out=None) -> float:
+    """Best-of-reps wall time (s) of one multi-source call over `sources`
+    (heuristic direction, the pull threshold n >> shift); `out` = (level,
+    parent, workspace) to reuse, else allocated here."""
+    torch = _torch()
+    import paper_1906_03113_amd as P
+    src = [int(s) for s in sources]
+    if out is None:
+        ld = 64 * ((len(src) + 63) // 64)
+        out = (torch.empty((G.n, ld), dtype=torch.int32, device="cuda"),
+               torch.empty((G.n, ld), dtype=torch.int32, device="cuda"),
+               P.Workspace(P.batch_vm_workspace_size(G, len(src))))
+    lv, pa, ws = out
+    best = math.inf
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.bfs_batch_vm(G, src, level=lv, parent=pa, workspace=ws, ms_pull_shift=shift)
+        torch.cuda.synchronize()
+        if r:
+            best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune_pull_shift(G, sources: Sequence[int], shifts: Sequence[int] = PULL_SHIFTS,
+                    cache: Optional[str] = DEFAULT_CACHE, log=None, timer=None) -> Dict:
+    """The multi-source direction threshold (pull once the union frontier
+    holds more than n >> shift vertices): time one call over the same sources
+    at each shift, cache the fastest under the graph's shape key (cache=None:
+    measure only)."""
+    import paper_1906_03113_amd as P
+    info = {}
+    P.bfs(G, int(sources[0]), info=info, variant="heuristic")
+    key = shape_key(G, int(info["levels"])) + "|ms_pull"
+    timer = timer or time_pull_shift
+    times = {}
+    for sh in shifts:
+        if not 1 <= int(sh) <= 31:
+            continue
+        times[int(sh)] = timer(G, sources, int(sh))
+        if log:
+            log(f"[autotune] {key} pull shift {sh} -> {times[int(sh)] * 1e3:.3f} ms")
+    best = min(times, key=times.get)
+    entry = {"shift": best, "time_s": times[best], "times_s": {str(k): t for k, t in times.items()},
+             "sources": len(sources)}
+    if cache:
+        store(cache, key, entry)
+    return dict(key=key, **entry)
+
+
+def lookup_pull_shift(G, levels: int, cache: str = DEFAULT_CACHE, default: int = 0) -> int:
+    """Cached multi-source pull shift for G's shape, else `default` (0 = the
+    library's n / 32)."""
+    if not os.path.exists(cache):
+        return default
+    try:
+        with open(cache) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return default
+    e = d.get(shape_key(G, levels) + "|ms_pull")
+    return int(e["shift"]) if e else default
+
+
 def lookup(G, levels: int, cache: str = DEFAULT_CACHE) -> Dict:
     """Cached parameters for G's shape, or {} (the library's defaults)."""
     if not os.path.exists(cache):
@@ -221,6 +290,8 @@ def main(argv=None):
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--batch", action="store_true",
                     help="tune the sources per multi-source call instead (256 sources per workload)")
+    ap.add_argument("--pull-shift", action="store_true",
+                    help="tune the multi-source pull threshold instead (64 sources per workload)")
     a = ap.parse_args(argv)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
     torch = _torch()
@@ -233,6 +304,13 @@ def main(argv=None):
     for w in a.workloads.split(","):
         g = graphgen.workload(w)
         G = P.Graph.from_graphgen(g)
+        if a.pull_shift:
+            r = tune_pull_shift(G, graphgen.pick_sources(g, 64, 123), cache=a.cache, log=log)
+            log(f"[autotune] {w}: best pull shift {r['shift']} "
+                f"({', '.join(f'{k}: {v * 1e3:.3f} ms' for k, v in r['times_s'].items())})")
+            out[w] = r
+            G.close()
+            continue
         if a.batch:
             src = graphgen.pick_sources(g, 256, 123)
             r = tune_batch_width(G, src, cache=a.cache, log=log)

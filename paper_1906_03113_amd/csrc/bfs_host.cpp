@@ -667,6 +667,9 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
                                    int32_t *const *level, int32_t *const *parent,
                                    bfs_run_options *opt, void *workspace, hipStream_t s,
                                    int32_t *vm_level = nullptr, int32_t *vm_parent = nullptr) {
+    const uint32_t pull_shift = (opt && opt->ms_pull_shift) ? opt->ms_pull_shift : 5u;
+    if (pull_shift > 31) return fail(BFS_EINVAL, "ms_pull_shift %u above 31", pull_shift);
+    if (opt && opt->variant > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", opt->variant);
     const bool vm = vm_level != nullptr;
     const MsLayout L = ms_layout(g->n, nq, !vm);
     char *b = (char *)workspace;
@@ -713,13 +716,13 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     HIP_TRY(launch_ms(p, 0, 0, grid, s));
     HIP_TRY(launch_ms(p, 1, 0, grid, s));
     // direction per level: push while the union frontier is small, pull (no
-    // atomics) once it holds more than n / 32 vertices (or as forced)
+    // atomics) once it holds more than n >> pull_shift vertices (or as forced)
     const uint32_t pol = opt ? opt->variant : kPush;
     uint32_t k = 0, frontier = 1;
     for (;; ++k) {
         if ((uint64_t)k > (uint64_t)g->n + 2) return fail(BFS_EHIP, "multi-source loop did not terminate");
         const bool pull = (pol == kPull) || ((pol == kHeuristic || pol == kLearned) &&
-                                             (uint64_t)frontier * 32 > (uint64_t)g->n);
+                                             ((uint64_t)frontier << pull_shift) > (uint64_t)g->n);
         if (pull) {
             HIP_TRY(launch_ms(p, 4, k, grid, s));
             HIP_TRY(launch_ms(p, 6, k, grid, s));

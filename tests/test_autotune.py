@@ -84,3 +84,28 @@ def test_batch_width_choice_and_cache(tmp_path, monkeypatch):
     assert tried == [64, 128] and r["width"] == 128
     assert A.lookup_batch_width(FakeGraph(), 7, cache) == 128
     assert A.lookup_batch_width(FakeGraph(), 7, str(tmp_path / "none.json")) == 64
+
+
+def test_pull_shift_choice_and_cache(tmp_path, monkeypatch):
+    """The fastest pull shift is cached under the shape key and returned by
+    lookup_pull_shift; shifts outside [1, 31] are not tried; cache=None
+    measures without writing."""
+    import paper_1906_03113_amd as P
+
+    class FakeGraph:
+        n, nnz, directed = 1 << 22, 128 << 20, False
+
+    monkeypatch.setattr(P, "bfs", lambda G, s, info=None, **kw: info.update(levels=7))
+    tried = []
+
+    def timer(G, sources, sh):
+        tried.append(sh)
+        return {5: 7.0, 7: 6.9, 9: 6.8}[sh]
+
+    cache = str(tmp_path / "t.json")
+    r = A.tune_pull_shift(FakeGraph(), list(range(64)), shifts=(0, 5, 7, 9, 32), cache=cache, timer=timer)
+    assert tried == [5, 7, 9] and r["shift"] == 9
+    assert A.lookup_pull_shift(FakeGraph(), 7, cache) == 9
+    assert A.lookup_pull_shift(FakeGraph(), 7, str(tmp_path / "none.json")) == 0
+    r = A.tune_pull_shift(FakeGraph(), list(range(64)), shifts=(5,), cache=None, timer=timer)
+    assert r["shift"] == 5 and A.lookup_pull_shift(FakeGraph(), 7, cache) == 9

@@ -121,3 +121,25 @@ def test_vertex_major_reuses_outputs(P):
     for q, s in enumerate(b):
         assert_same(g, s, (l[:, q].copy(), p[:, q].copy()), f"reuse/q{q}")
     assert np.all(l[:, len(b):] == -1) and np.all(p[:, len(b):] == -1)
+
+
+@pytest.mark.parametrize("name", ["rmat", "grid"])
+def test_ms_pull_shift_never_changes_results(P, name):
+    """The multi-source direction threshold (all push at 31 ... pull from a
+    frontier of n/2 at 1) changes no result, in either output layout; a shift
+    above 31 is rejected before any work."""
+    import torch
+    g = {"rmat": lambda: graphgen.rmat(13, 16, 51), "grid": lambda: graphgen.grid(60, 0.85, 52)}[name]()
+    G = P.Graph.from_graphgen(g)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = [int(s) for s in np.random.default_rng(53).choice(cand, size=70, replace=False)]
+    for sh in (1, 9, 31):
+        say(f"[batch] {name} pull shift {sh}")
+        lv, pa = P.bfs_batch(G, src, variant="heuristic", ms_pull_shift=sh)
+        vl, vp = P.bfs_batch_vm(G, src, variant="heuristic", ms_pull_shift=sh)
+        torch.cuda.synchronize()
+        for q in (0, 33, 69):
+            assert_same(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/sh{sh}/q{q}")
+        assert torch.equal(vl[:, :70], torch.stack(lv, 1)) and torch.equal(vp[:, :70], torch.stack(pa, 1))
+    with pytest.raises(P.BfsError):
+        P.bfs_batch_vm(G, src, variant="heuristic", ms_pull_shift=32)
