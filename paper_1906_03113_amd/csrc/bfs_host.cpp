@@ -198,6 +198,7 @@ MsLayout ms_layout(int32_t n, int32_t nq, bool staged) {
     L.f2 = take((size_t)n * 4);
     L.flag = take((size_t)n * 4);
     L.cnt = take(64);
+    L.fbits = take(((size_t)n + 63) / 64 * 8);
     L.slev = staged ? take((size_t)n * W * 64 * 4) : 0;
     L.spar = staged ? take((size_t)n * W * 64 * 4) : 0;
     L.lptr = take((size_t)nq * 8);
@@ -659,6 +660,11 @@ extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
     return ws_layout(g->n, g->nnz, kHeavyFloor).total + align256((size_t)nroots * 4);
 }
 
+// A multi-source pull level tests the union-frontier bitmap before each mask
+// gather when the frontier holds at most n >> kMsFbitsShift vertices (on
+// denser frontiers the extra dependent load costs more than it skips).
+constexpr uint32_t kMsFbitsShift = 6;
+
 // All queries on one graph: the multi-source kernels.
 // level / parent: per-source arrays (staged results, transposed at the end),
 // or with vm_level / vm_parent set, the caller's vertex-major arrays, written
@@ -690,6 +696,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     p.fq[2] = (int32_t *)(b + L.f2);
     p.flag = (uint32_t *)(b + L.flag);
     p.cnt = (uint32_t *)(b + L.cnt);
+    p.fbits = (unsigned long long *)(b + L.fbits);
     p.lo = g->lo;
     p.li = g->li;
     p.lomap = g->lomap;
@@ -724,6 +731,10 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
         const bool pull = (pol == kPull) || ((pol == kHeuristic || pol == kLearned) &&
                                              ((uint64_t)frontier << pull_shift) > (uint64_t)g->n);
         if (pull) {
+            // a sparse union frontier: the pull tests its bitmap before each
+            // mask gather (most in-neighbours are then skipped on chip)
+            p.use_fbits = ((uint64_t)frontier << kMsFbitsShift) <= (uint64_t)g->n ? 1u : 0u;
+            if (p.use_fbits) HIP_TRY(launch_ms(p, 8, k, grid, s));
             HIP_TRY(launch_ms(p, 4, k, grid, s));
             HIP_TRY(launch_ms(p, 6, k, grid, s));
             HIP_TRY(launch_ms(p, 5, k, grid, s));

@@ -128,10 +128,15 @@ struct MsLevel {
     uint32_t *host_status;         // pinned host: [0] level, [1] next frontier size
     uint32_t fill_levels;          // slev / spar are the caller's vertex-major outputs:
                                    // every level starts at -1 (no transpose at the end)
+    // union-frontier bitmap of the level a pull runs on (bit v = some source
+    // has v in its frontier), [ceil(n / 64)] words, built by k_ms_fbits when
+    // use_fbits is set: the pull tests it before gathering a frontier mask
+    unsigned long long *fbits;
+    uint32_t use_fbits;
 };
 
 struct MsLayout {
-    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, slev, spar, lptr, pptr, src, total;
+    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, fbits, slev, spar, lptr, pptr, src, total;
 };
 // staged = false: the results go straight to the caller's vertex-major
 // arrays, so the layout holds no staging (slev / spar are 0)

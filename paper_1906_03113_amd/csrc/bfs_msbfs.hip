@@ -53,6 +53,11 @@ __device__ __forceinline__ size_t stage(const MsLevel &p, int32_t v, uint32_t q)
     return (size_t)v * (p.W * 64u) + q;
 }
 
+// Whether u may hold frontier bits at this level (always, without the bitmap).
+__device__ __forceinline__ bool in_frontier(const MsLevel &p, int32_t u) {
+    return !p.use_fbits || ((p.fbits[(uint32_t)u >> 6] >> ((uint32_t)u & 63u)) & 1ull) != 0ull;
+}
+
 // One step of the settle scan by a group of G lanes (G = 16 or 64, aligned
 // within the wave) over in_idx[eb + lane-in-group] (lanes past e1 hold
 // nothing): each bit of rem held by some lane's cur mask goes to the lowest
@@ -69,7 +74,7 @@ __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const 
     unsigned long long hit = 0ull;
     if (e < e1) {
         u = p.in_idx[e];
-        hit = row(cur, u, p.W)[w] & rem;
+        if (in_frontier(p, u)) hit = row(cur, u, p.W)[w] & rem;
     }
     unsigned long long incl = hit;
 #pragma unroll
@@ -260,6 +265,25 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
     }
 }
 
+// The union-frontier bitmap of level k: bit v of fbits = some word of v's
+// level-k mask is nonzero.  A wave per 64 consecutive vertices (one lane
+// each), whose ballot is the word; every word is rewritten, so nothing needs
+// clearing.
+__global__ __launch_bounds__(kBlock) void k_ms_fbits(MsLevel p, uint32_t k) {
+    const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], k % 3);
+    const uint32_t W = p.W, lane = __lane_id();
+    const uint32_t nw = (uint32_t)(((size_t)p.n + 63) / 64);
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6, nwaves = (gridDim.x * kBlock) >> 6;
+    for (uint32_t i = wave; i < nw; i += nwaves) {           // uniform per wave
+        const uint32_t v = i * 64u + lane;
+        bool nz = false;
+        if (v < (uint32_t)p.n)
+            for (uint32_t w = 0; w < W; ++w) nz = nz || row(cur, (int32_t)v, W)[w] != 0ull;
+        const unsigned long long bm = __ballot(nz);
+        if (lane == 0) p.fbits[i] = bm;
+    }
+}
+
 // Level k, pull form (for large frontiers): every vertex v whose sources are
 // not all settled ORs, in ascending in-neighbour order, the frontier masks of
 // its in-neighbours restricted to the sources that have not reached it; each
@@ -352,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
 #pragma unroll
                         for (int j = 0; j < 4; ++j) uu[j] = p.in_idx[e + j < e1 ? e + j : e1 - 1];
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) mm[j] = row(cur, uu[j], W)[w];
+                        for (int j = 0; j < 4; ++j) mm[j] = in_frontier(p, uu[j]) ? row(cur, uu[j], W)[w] : 0ull;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             unsigned long long hit = mm[j] & rem;
@@ -600,6 +624,7 @@ hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hip
         case 4: hipLaunchKernelGGL(k_ms_pull, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 6: hipLaunchKernelGGL(k_ms_fixup, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 7: hipLaunchKernelGGL(k_ms_out, dim3(grid), dim3(kBlock), 0, s, p); break;
+        case 8: hipLaunchKernelGGL(k_ms_fbits, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         default: hipLaunchKernelGGL(k_ms_report, dim3(1), dim3(64), 0, s, p, k); break;
     }
     return hipGetLastError();
