@@ -61,6 +61,17 @@ def test_rmat22_batch_of_64():
     vl, vp = P.bfs_batch_vm(G, src, variant="push", level=vl, parent=vp)
     torch.cuda.synchronize()
     assert torch.equal(vl, torch.stack(lv, 1)) and torch.equal(vp, torch.stack(pa, 1))
+    # the pull thresholds bench.py picks between (n >> 9, n >> 11: level 1
+    # then runs as a pull over the union-frontier bitmap), both layouts
+    ref_l, ref_p = torch.stack(lv, 1), torch.stack(pa, 1)
+    for sh in (9, 11):
+        say(f"[full] rmat22 multi-source x64, pull shift {sh}")
+        vl, vp = P.bfs_batch_vm(G, src, variant="heuristic", ms_pull_shift=sh, level=vl, parent=vp)
+        l2, p2 = P.bfs_batch(G, src, variant="heuristic", ms_pull_shift=sh)
+        torch.cuda.synchronize()
+        assert torch.equal(vl, ref_l) and torch.equal(vp, ref_p)
+        assert torch.equal(torch.stack(l2, 1), ref_l) and torch.equal(torch.stack(p2, 1), ref_p)
+        del l2, p2
 
 
 def test_grid4096():
