@@ -665,6 +665,13 @@ extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
 // denser frontiers the extra dependent load costs more than it skips).
 constexpr uint32_t kMsFbitsShift = 6;
 
+// From level kMsGroupFrom on, push levels are launched kMsGroupLevels at a
+// time between two reads of the progress report (deep graphs: the round trip
+// per level would otherwise dominate); levels launched past the end of the
+// search find an empty frontier and change nothing.
+constexpr uint32_t kMsGroupFrom = 16;
+constexpr uint32_t kMsGroupLevels = 8;
+
 // All queries on one graph: the multi-source kernels.
 // level / parent: per-source arrays (staged results, transposed at the end),
 // or with vm_level / vm_parent set, the caller's vertex-major arrays, written
@@ -697,6 +704,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     p.flag = (uint32_t *)(b + L.flag);
     p.cnt = (uint32_t *)(b + L.cnt);
     p.fbits = (unsigned long long *)(b + L.fbits);
+    p.wide_steps = ((uint64_t)g->nnz < 8ull * (uint64_t)g->n) ? 1u : 0u;
     p.lo = g->lo;
     p.li = g->li;
     p.lomap = g->lomap;
@@ -739,14 +747,21 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
             HIP_TRY(launch_ms(p, 6, k, grid, s));
             HIP_TRY(launch_ms(p, 5, k, grid, s));
         } else {
-            HIP_TRY(launch_ms(p, 2, k, grid, s));
-            HIP_TRY(launch_ms(p, 3, k, grid, s));
+            const uint32_t group = (k >= kMsGroupFrom) ? kMsGroupLevels : 1u;
+            for (uint32_t i = 0; i < group; ++i) {
+                HIP_TRY(launch_ms(p, 2, k + i, grid, s));
+                HIP_TRY(launch_ms(p, 3, k + i, grid, s));
+            }
+            k += group - 1;
         }
         bool done = false;
         uint32_t lv = 0;
         st = wait_progress(hs, s, done, lv);
         if (st != BFS_OK) return st;
-        if (done) break;
+        if (done) {
+            k = lv - 1;                       // the level whose step found nothing
+            break;
+        }
         frontier = hs->h[1];
     }
     if (!vm) HIP_TRY(launch_ms(p, 7, k, grid, s));      // staged results -> per-source arrays

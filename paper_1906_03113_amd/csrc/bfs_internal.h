@@ -133,6 +133,8 @@ struct MsLevel {
     // use_fbits is set: the pull tests it before gathering a frontier mask
     unsigned long long *fbits;
     uint32_t use_fbits;
+    uint32_t wide_steps;           // push: 64 frontier columns per wave step always
+                                   // (average degree below 8), else sized to the list
 };
 
 struct MsLayout {

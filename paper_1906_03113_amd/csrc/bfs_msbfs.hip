@@ -138,19 +138,25 @@ __global__ __launch_bounds__(kBlock) void k_ms_roots(MsLevel p) {
     }
 }
 
-// Level k, push half.  Work items, one wave each: the frontier columns with
-// fewer than kMsLong entries (lanes over the entries), then the chunks of the
-// graph's long columns, skipped unless the column is in some frontier.  Per
+// Level k, push half.  Work items: the frontier list, up to 64 columns per
+// wave step - the entries of those with at most kMsShort entries dealt out one per
+// lane, each longer one below kMsLong entries taken by the whole wave - then
+// the chunks of the graph's long columns, a wave each, skipped unless the
+// column is in some frontier.  Per
 // entry (u, v): new = cur[u] & ~vis[v] is ORed into nxt[v], each of its bits q
 // takes atomicMin(parent_q(v), u) - over all the entries this is the smallest
 // frontier in-neighbour of v for q - and v is listed for level k+1 once,
 // through a per-wave LDS buffer flushed with one atomic per kMsFlush entries.
 // Also clears the masks of F_{k-1} (slot (k+2) % 3).
 constexpr uint32_t kMsWaveBuf = 256;
+constexpr int32_t kMsShort = 16;         // longest column a group of lanes takes
 constexpr uint32_t kMsFlush = kMsWaveBuf - 64;
 
 __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
     __shared__ int32_t s_buf[kBlock / 64][kMsWaveBuf];
+    __shared__ int32_t s_pre[kBlock / 64][64];         // per wave: short columns' entry offsets
+    __shared__ int32_t s_col[kBlock / 64][64];         // ... their column ids
+    __shared__ int32_t s_e0[kBlock / 64][64];          // ... and first entries
     const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
     const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s0);
     unsigned long long *nxt = pick3(p.m[0], p.m[1], p.m[2], s1);
@@ -166,7 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
         old[(size_t)u * W + (t % W)] = 0ull;
     }
     const uint32_t lane = __lane_id();
-    int32_t *buf = s_buf[threadIdx.x >> 6];
+    const uint32_t wid = threadIdx.x >> 6;
+    int32_t *buf = s_buf[wid];
     uint32_t nbuf = 0;                    // the same in every lane
     const uint32_t tag = k + 2;           // "listed for level k+1"
     auto flush = [&]() {
@@ -178,61 +185,125 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
         __builtin_amdgcn_wave_barrier();
         nbuf = 0;
     };
-    for (uint32_t it = gt >> 6; it < ncur + p.nlo_chunks; it += gs >> 6) {
-        int32_t u, e0, e1;
-        if (it < ncur) {
+    // one entry (u, v): the new bits of u's mask for v, their parents, the OR
+    // into nxt[v]; true if this lane lists v for level k+1
+    auto entry = [&](int32_t u, int32_t e, int32_t &v) -> bool {
+        const unsigned long long *cu = row(cur, u, W);
+        v = p.out_idx[e];
+        const unsigned long long *vv = row(p.vis, v, W);
+        unsigned long long *nv = row(nxt, v, W);
+        bool listed = false, any = false;
+        for (uint32_t w = 0; w < W; ++w) {
+            const unsigned long long nb = cu[w] & ~vv[w];
+            if (!nb) continue;
+            // parents only decrease, so a stale pre-read can only let
+            // an atomic through that was not needed
+            for (unsigned long long b = nb; b; b &= b - 1ull) {
+                uint32_t *at = &p.spar[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)];
+                if (*at > (uint32_t)u) atomicMin(at, (uint32_t)u);
+            }
+            if (W == 1) {
+                // the lane whose OR turns nxt[v] nonzero lists v; a
+                // pre-read (possibly stale: bits are only ever added)
+                // skips ORs that would add nothing
+                if (nb & ~nv[0]) listed = atomicOr(&nv[0], nb) == 0ull;
+            } else {
+                atomicOr(&nv[w], nb);
+                any = true;
+            }
+        }
+        if (W != 1) listed = any && atomicMax(&p.flag[v], tag) < tag;
+        return listed;
+    };
+    // the wave's listed vertices into its LDS buffer (called by whole waves)
+    auto emit = [&](bool listed, int32_t v) {
+        const unsigned long long bm = __ballot(listed);
+        if (bm) {
+            if (listed) buf[nbuf + lanes_below(bm)] = v;
+            nbuf += (uint32_t)__popcll(bm);
+            if (nbuf > kMsFlush) flush();
+        }
+    };
+    // the frontier list C columns per wave step, a lane per column: the
+    // entries of the short columns (at most kMsShort) are dealt out over the
+    // wave's lanes, one entry each, through an exclusive prefix sum of their
+    // lengths in LDS; then each longer column below kMsLong, the whole wave
+    // over its entries
+    int32_t *pre = s_pre[wid];
+    int32_t *cu_of = s_col[wid];
+    int32_t *e0_of = s_e0[wid];
+    // columns per wave step: 64 on graphs of low average degree (short
+    // columns only: fewer, fuller steps), else a power of two up to 64 such
+    // that the list spans about one step per wave (a short list of longer
+    // columns then keeps every wave busy)
+    const uint32_t nwaves = gs >> 6;
+    const uint32_t want = (ncur + nwaves - 1) / nwaves;
+    const uint32_t C = (p.wide_steps || want >= 64u) ? 64u
+                     : (want <= 1u ? 1u : 1u << (32 - __clz((int)(want - 1u))));
+    for (uint32_t b0 = (gt >> 6) * C; b0 < ncur; b0 += nwaves * C) {   // uniform per wave
+        const uint32_t it = b0 + lane;
+        int32_t u = -1, e0 = 0, d = 0;
+        if (lane < C && it < ncur) {
             u = fcur[it];
             e0 = p.out_ptr[u];
-            e1 = p.out_ptr[u + 1];
-            if ((uint32_t)(e1 - e0) >= kMsLong) continue;        // done by its chunks
-        } else {
-            const uint32_t c = it - ncur;
-            const MsLong L = p.lo[p.lomap[c]];
-            u = L.v;
-            bool in_f = false;
-            for (uint32_t w = 0; w < W; ++w) in_f = in_f || row(cur, u, W)[w] != 0ull;
-            if (!in_f) continue;
-            const int32_t r1 = p.out_ptr[u + 1];
-            e0 = p.out_ptr[u] + (int32_t)((c - L.chunk_base) * kMsChunk);
-            e1 = (e0 + (int32_t)kMsChunk < r1) ? e0 + (int32_t)kMsChunk : r1;
+            d = p.out_ptr[u + 1] - e0;
         }
-        const unsigned long long *cu = row(cur, u, W);
+        const int32_t ds = (d <= kMsShort) ? d : 0;
+        int32_t inc = ds;
+#pragma unroll
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+            const int32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        const int32_t total = __shfl(inc, 63, 64);
+        pre[lane] = inc - ds;
+        cu_of[lane] = u;
+        e0_of[lane] = e0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int32_t j0 = 0; j0 < total; j0 += 64) {                 // uniform
+            const int32_t j = j0 + (int32_t)lane;
+            int32_t v = -1;
+            bool listed = false;
+            if (j < total) {
+                // the column holding entry j: the last one whose prefix is <= j
+                uint32_t c = 0;
+#pragma unroll
+                for (uint32_t step = 32; step; step >>= 1)
+                    if (c + step < 64u && pre[c + step] <= j) c += step;
+                listed = entry(cu_of[c], e0_of[c] + (j - pre[c]), v);
+            }
+            emit(listed, v);
+        }
+        for (unsigned long long mm = __ballot(d > kMsShort && (uint32_t)d < kMsLong); mm; mm &= mm - 1ull) {
+            const int src = (int)__ffsll((long long)mm) - 1;
+            const int32_t mu = __shfl(u, src, 64), me0 = __shfl(e0, src, 64), md = __shfl(d, src, 64);
+            for (int32_t eb = 0; eb < md; eb += 64) {               // uniform
+                int32_t v = -1;
+                const bool listed = (eb + (int32_t)lane < md) ? entry(mu, me0 + eb + (int32_t)lane, v) : false;
+                emit(listed, v);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();                           // LDS reused by the next step
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the chunks of the graph's long columns, a wave each
+    for (uint32_t c = gt >> 6; c < p.nlo_chunks; c += gs >> 6) {
+        const MsLong L = p.lo[p.lomap[c]];
+        const int32_t u = L.v;
+        bool in_f = false;
+        for (uint32_t w = 0; w < W; ++w) in_f = in_f || row(cur, u, W)[w] != 0ull;
+        if (!in_f) continue;
+        const int32_t r1 = p.out_ptr[u + 1];
+        const int32_t e0 = p.out_ptr[u] + (int32_t)((c - L.chunk_base) * kMsChunk);
+        const int32_t e1 = (e0 + (int32_t)kMsChunk < r1) ? e0 + (int32_t)kMsChunk : r1;
         for (int32_t eb = e0; eb < e1; eb += 64) {       // uniform: whole waves step together
             const int32_t e = eb + (int32_t)lane;
-            bool listed = false;
             int32_t v = -1;
-            if (e < e1) {
-                v = p.out_idx[e];
-                const unsigned long long *vv = row(p.vis, v, W);
-                unsigned long long *nv = row(nxt, v, W);
-                bool any = false;
-                for (uint32_t w = 0; w < W; ++w) {
-                    const unsigned long long nb = cu[w] & ~vv[w];
-                    if (!nb) continue;
-                    // parents only decrease, so a stale pre-read can only let
-                    // an atomic through that was not needed
-                    for (unsigned long long b = nb; b; b &= b - 1ull) {
-                        uint32_t *at = &p.spar[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)];
-                        if (*at > (uint32_t)u) atomicMin(at, (uint32_t)u);
-                    }
-                    if (W == 1) {
-                        // the lane whose OR turns nxt[v] nonzero lists v; a
-                        // pre-read (possibly stale: bits are only ever added)
-                        // skips ORs that would add nothing
-                        if (nb & ~nv[0]) listed = atomicOr(&nv[0], nb) == 0ull;
-                    } else {
-                        atomicOr(&nv[w], nb);
-                        any = true;
-                    }
-                }
-                if (W != 1) listed = any && atomicMax(&p.flag[v], tag) < tag;
-            }
-            const unsigned long long bm = __ballot(listed);
-            if (bm) {
-                if (listed) buf[nbuf + lanes_below(bm)] = v;
-                nbuf += (uint32_t)__popcll(bm);
-                if (nbuf > kMsFlush) flush();
-            }
+            const bool listed = (e < e1) ? entry(u, e, v) : false;
+            emit(listed, v);
         }
     }
     if (nbuf) flush();
@@ -240,8 +311,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
 
 // Level k, settle half, one lane per newly listed vertex v: the new bits
 // (nxt[v]) join vis and get level k+1 (their parents were set by the push).
+// The progress report is written only for a level that had a frontier, so
+// levels launched past the end of the search (an empty frontier: push and
+// settle then change nothing) leave the last level's report in place.
 __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
-    const uint32_t s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
     const unsigned long long *nxt = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s1);
     const int32_t *fnxt = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s1);
     const uint32_t nnext = p.cnt[s1];
@@ -249,9 +323,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     if (gt == 0) {
         p.cnt[s2] = 0u;                       // the list of level k+2 starts empty
-        p.host_status[0] = k + 1;
-        p.host_status[1] = nnext;
-        __threadfence_system();
+        if (p.cnt[s0] != 0u) {
+            p.host_status[0] = k + 1;
+            p.host_status[1] = nnext;
+            __threadfence_system();
+        }
     }
     for (uint32_t i = gt; i < nnext; i += gs) {
         const int32_t v = fnxt[i];
