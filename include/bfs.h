@@ -213,9 +213,12 @@ size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots);
  * sources: host, num_sources ints in [0, n) (duplicates allowed).
  * level, parent: device int32[n * ld] each, caller-owned, 16-byte aligned.
  * workspace: bfs_batch_vm_workspace_size(g, num_sources) bytes or more,
- * 256-byte aligned.  opt: as for bfs_run_batch (variant, grid_blocks).
+ * 256-byte aligned.  opt: as for bfs_run_batch (variant, grid_blocks,
+ * ms_pull_shift); on return opt->levels = the largest level over the sources
+ * plus one.
  * Errors: BFS_EINVAL (NULL argument, num_sources < 1, misaligned or small
- * buffers, unknown variant), BFS_ERANGE (a source outside [0, n)), BFS_EHIP.
+ * buffers, unknown variant, ms_pull_shift above 31), BFS_ERANGE (a source
+ * outside [0, n)), BFS_EHIP.
  */
 bfs_status bfs_run_batch_vm(bfs_graph *g, int32_t num_sources, const int32_t *sources,
                             int32_t *level, int32_t *parent, bfs_run_options *opt,

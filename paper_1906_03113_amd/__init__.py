@@ -304,10 +304,13 @@ def batch_vm_workspace_size(g: Graph, num_sources: int) -> int:
 
 
 def bfs_batch_vm(g: Graph, sources: Sequence[int], variant="heuristic", level=None, parent=None,
-                 workspace: Optional[Workspace] = None, stream=None, **kw):
+                 workspace: Optional[Workspace] = None, stream=None, info: Optional[dict] = None,
+                 **kw):
     """Many sources on one graph with vertex-major results: returns (level,
     parent) as int32 cuda tensors of shape [n, ld], ld = 64 * ceil(len / 64);
-    column q holds source q's arrays (columns past the sources hold -1)."""
+    column q holds source q's arrays (columns past the sources hold -1).
+    `info`, if given, receives "levels" (the largest level over the sources
+    plus one)."""
     t = _torch()
     src = _i32_host(np.asarray(sources))
     ld = 64 * ((len(src) + 63) // 64)
@@ -328,4 +331,6 @@ def bfs_batch_vm(g: Graph, sources: Sequence[int], variant="heuristic", level=No
                                            ctypes.c_void_p(level.data_ptr()),
                                            ctypes.c_void_p(parent.data_ptr()), ctypes.byref(o),
                                            workspace.ptr, workspace.nbytes, _stream_handle(stream)))
+    if info is not None:
+        info["levels"] = int(o.levels)
     return level, parent

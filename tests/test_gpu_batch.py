@@ -143,3 +143,31 @@ def test_ms_pull_shift_never_changes_results(P, name):
         assert torch.equal(vl[:, :70], torch.stack(lv, 1)) and torch.equal(vp[:, :70], torch.stack(pa, 1))
     with pytest.raises(P.BfsError):
         P.bfs_batch_vm(G, src, variant="heuristic", ms_pull_shift=32)
+
+
+@pytest.mark.parametrize("name", ["er", "rmat", "grid_deep", "path"])
+def test_vertex_major_level_count(P, name):
+    """The level count a multi-source call reports is the largest level over
+    its sources plus one, also on deep graphs, where push levels are launched
+    several at a time and the last group runs past the end of the search."""
+    import torch
+    g = {"er": lambda: graphgen.erdos_renyi(3000, 5, 61),
+         "rmat": lambda: graphgen.rmat(12, 16, 62),
+         "grid_deep": lambda: graphgen.grid(40, 0.75, 63),
+         "path": lambda: graphgen.path_graph(203)}[name]()
+    G = P.Graph.from_graphgen(g)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = [int(s) for s in np.random.default_rng(64).choice(cand, size=min(40, len(cand)), replace=False)]
+    if name == "path":
+        src = [0, 101, 202]                  # eccentricities 202, 101, 202
+    for variant in ("push", "heuristic"):
+        info = {}
+        say(f"[batch-vm] level count {name} {variant}")
+        lv, pa = P.bfs_batch_vm(G, src, variant=variant, info=info)
+        torch.cuda.synchronize()
+        l = lv.cpu().numpy()
+        want = max(int(oracle.bfs_graph(g, s)[0].max()) for s in src) + 1
+        assert info["levels"] == want, (name, variant, info["levels"], want)
+        assert int(l[:, :len(src)].max()) + 1 == want
+        for q in (0, len(src) - 1):
+            assert_same(g, src[q], (l[:, q].copy(), pa[:, q].cpu().numpy().copy()), f"{name}/q{q}")
