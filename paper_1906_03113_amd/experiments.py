@@ -76,12 +76,22 @@ def many_sources(count: int = 256, seed: int = 41, log=print) -> Dict:
     log(f"[sources] {len(src)} sources in one call: {t_batch * 1e3:.2f} ms, {m / t_batch / 1e9:.2f} GTEPS")
     del lv, pa, wsb
     torch.cuda.empty_cache()
+    ld = 64 * ((len(src) + 63) // 64)
+    vl = torch.empty((n, ld), dtype=torch.int32, device="cuda")
+    vp = torch.empty((n, ld), dtype=torch.int32, device="cuda")
+    wsv = P.Workspace(P.batch_vm_workspace_size(G, len(src)))
+    t_vm = _timed(lambda: P.bfs_batch_vm(G, src, level=vl, parent=vp, workspace=wsv, variant="heuristic"))
+    log(f"[sources] {len(src)} sources in one call, vertex-major results: {t_vm * 1e3:.2f} ms, "
+        f"{m / t_vm / 1e9:.2f} GTEPS")
+    del vl, vp, wsv
+    torch.cuda.empty_cache()
     l1 = torch.empty(n, dtype=torch.int32, device="cuda")
     p1 = torch.empty(n, dtype=torch.int32, device="cuda")
     ws = P.Workspace(G.workspace_size(1))
     res = {"graph": "R-MAT scale 20, edgefactor 16, directed", "n": n, "nnz": g.nnz,
            "sources": len(src), "edges_m_c": m,
-           "one_call": {"ms": t_batch * 1e3, "gteps": m / t_batch / 1e9}}
+           "one_call": {"ms": t_batch * 1e3, "gteps": m / t_batch / 1e9},
+           "one_call_vertex_major": {"ms": t_vm * 1e3, "gteps": m / t_vm / 1e9}}
     for name, kw in (("one_at_a_time_push", dict(variant="push")),
                      ("one_at_a_time_heuristic_graph_loop",
                       dict(variant="heuristic", loop="graph", levels_per_sync=8))):
