@@ -623,45 +623,60 @@ __global__ __launch_bounds__(kBlock) void k_ms_fixup(MsLevel p, uint32_t k) {
 // stores where the caller's array is not 16-byte aligned or at the tail).
 // Entries whose vis bit is clear (never reached) become -1.
 __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
-    __shared__ int32_t t_lv[64][65];
-    __shared__ int32_t t_pa[64][65];
+    // one 64 x 64 tile (+1 column against bank conflicts), used for the
+    // levels and then for the parents: 16.6 KB per block, so that more blocks
+    // share a compute unit and keep more loads in flight
+    __shared__ int32_t t_x[64][65];
     const uint32_t W = p.W, S = W * 64u, tid = threadIdx.x;
     const uint32_t ntiles = (uint32_t)(((size_t)p.n + 63) / 64);
     const uint32_t g4 = (tid & 15u) * 4u;          // first of this lane's 4 columns
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int32_t v0 = (int32_t)(tile * 64u);
         for (uint32_t w = 0; w < W; ++w) {
+            int4 lv[4], pa[4];
+            uint32_t bits[4];
 #pragma unroll
-            for (uint32_t r = 0; r < 4; ++r) {            // staged rows -> tile[source][vertex]
-                const uint32_t vi = (tid >> 4) + 16u * r;
-                const int32_t v = v0 + (int32_t)vi;
-                int4 lv = make_int4(-1, -1, -1, -1), pa = lv;
-                uint32_t bits = 0;
-                if (v < p.n) bits = (uint32_t)(row(p.vis, v, W)[w] >> g4) & 15u;
-                if (bits) {
+            for (uint32_t r = 0; r < 4; ++r) {            // this lane's 4 sources of 4 staged rows
+                const int32_t v = v0 + (int32_t)((tid >> 4) + 16u * r);
+                lv[r] = make_int4(-1, -1, -1, -1);
+                pa[r] = lv[r];
+                bits[r] = 0;
+                if (v < p.n) bits[r] = (uint32_t)(row(p.vis, v, W)[w] >> g4) & 15u;
+                if (bits[r]) {
                     const size_t at = (size_t)v * S + w * 64u + g4;
-                    lv = *reinterpret_cast<const int4 *>(p.slev + at);
-                    pa = *reinterpret_cast<const int4 *>(p.spar + at);
+                    lv[r] = *reinterpret_cast<const int4 *>(p.slev + at);
+                    pa[r] = *reinterpret_cast<const int4 *>(p.spar + at);
                 }
-                t_lv[g4 + 0][vi] = (bits & 1u) ? lv.x : -1;
-                t_lv[g4 + 1][vi] = (bits & 2u) ? lv.y : -1;
-                t_lv[g4 + 2][vi] = (bits & 4u) ? lv.z : -1;
-                t_lv[g4 + 3][vi] = (bits & 8u) ? lv.w : -1;
-                t_pa[g4 + 0][vi] = (bits & 1u) ? pa.x : -1;
-                t_pa[g4 + 1][vi] = (bits & 2u) ? pa.y : -1;
-                t_pa[g4 + 2][vi] = (bits & 4u) ? pa.z : -1;
-                t_pa[g4 + 3][vi] = (bits & 8u) ? pa.w : -1;
             }
-            __syncthreads();
+            int4 out_l[4], out_p[4];
+            for (int half = 0; half < 2; ++half) {         // levels, then parents
 #pragma unroll
-            for (uint32_t r = 0; r < 4; ++r) {            // tile rows -> output rows
+                for (uint32_t r = 0; r < 4; ++r) {        // staged rows -> tile[source][vertex]
+                    const uint32_t vi = (tid >> 4) + 16u * r;
+                    const int4 x = half ? pa[r] : lv[r];
+                    t_x[g4 + 0][vi] = (bits[r] & 1u) ? x.x : -1;
+                    t_x[g4 + 1][vi] = (bits[r] & 2u) ? x.y : -1;
+                    t_x[g4 + 2][vi] = (bits[r] & 4u) ? x.z : -1;
+                    t_x[g4 + 3][vi] = (bits[r] & 8u) ? x.w : -1;
+                }
+                __syncthreads();
+#pragma unroll
+                for (uint32_t r = 0; r < 4; ++r) {        // tile rows, 4 vertices per lane
+                    const uint32_t qi = (tid >> 4) + 16u * r;
+                    const int4 y = make_int4(t_x[qi][g4], t_x[qi][g4 + 1], t_x[qi][g4 + 2], t_x[qi][g4 + 3]);
+                    if (half) out_p[r] = y;
+                    else out_l[r] = y;
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {            // output rows
                 const uint32_t qi = (tid >> 4) + 16u * r;
                 const uint32_t q = w * 64u + qi;
                 if (q >= p.nq) continue;
                 int32_t *lo = p.level[q] + v0 + g4;
                 int32_t *po = p.parent[q] + v0 + g4;
-                const int4 a = make_int4(t_lv[qi][g4], t_lv[qi][g4 + 1], t_lv[qi][g4 + 2], t_lv[qi][g4 + 3]);
-                const int4 b = make_int4(t_pa[qi][g4], t_pa[qi][g4 + 1], t_pa[qi][g4 + 2], t_pa[qi][g4 + 3]);
+                const int4 a = out_l[r], b = out_p[r];
                 const bool full = v0 + (int32_t)g4 + 3 < p.n;
                 if (full && ((reinterpret_cast<uintptr_t>(lo) | reinterpret_cast<uintptr_t>(po)) & 15u) == 0) {
                     *reinterpret_cast<int4 *>(lo) = a;
@@ -676,7 +691,6 @@ __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
                         }
                 }
             }
-            __syncthreads();
         }
     }
 }
