@@ -76,6 +76,7 @@ __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const 
         u = p.in_idx[e];
         if (in_frontier(p, u)) hit = row(cur, u, p.W)[w] & rem;
     }
+    if (__ballot(hit != 0ull) == 0ull) return 0ull;        // (uniform) nothing found in the wave
     unsigned long long incl = hit;
 #pragma unroll
     for (uint32_t d = 1; d < G; d <<= 1) {
