@@ -143,3 +143,21 @@ def test_header_is_plain_c(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, (r.returncode, r.stderr)
     assert "|" in r.stdout and r.stdout.split("|")[1].strip()
+
+
+def test_vertex_major_binding_checks_output_shapes():
+    """bfs_batch_vm refuses output tensors of the wrong shape, type or device
+    before anything reaches the library (no GPU needed)."""
+    import torch
+    import paper_1906_03113_amd as P
+
+    class FakeGraph:
+        n = 10
+        handle = None
+
+    good = dict(dtype=torch.int32)
+    for lv, pa in ((torch.empty((10, 64), **good), torch.empty((10, 64), **good)),      # host tensors
+                   (torch.empty((10, 63), **good), torch.empty((10, 64), **good)),      # wrong shape
+                   (torch.empty((10, 64), dtype=torch.int64), torch.empty((10, 64), **good))):
+        with pytest.raises(ValueError):
+            P.bfs_batch_vm(FakeGraph(), [0, 1], level=lv, parent=pa)
