@@ -728,6 +728,10 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     }
     HIP_TRY(hipMemcpyAsync(b + L.src, sources, (size_t)nq * 4, hipMemcpyHostToDevice, s));
     uint32_t grid = (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
+    // the long rows' later chunks in a launch of their own once they outnumber
+    // the grid's waves twice over (then skipping those a row's first chunk
+    // has settled saves whole rounds; below that the extra launch costs more)
+    p.long_split = ((uint64_t)(g->nli_chunks - g->nli) > 2ull * grid * 4u) ? 1u : 0u;
     HIP_TRY(launch_ms(p, 0, 0, grid, s));
     HIP_TRY(launch_ms(p, 1, 0, grid, s));
     // direction per level: push while the union frontier is small, pull (no
@@ -744,6 +748,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
             p.use_fbits = ((uint64_t)frontier << kMsFbitsShift) <= (uint64_t)g->n ? 1u : 0u;
             if (p.use_fbits) HIP_TRY(launch_ms(p, 8, k, grid, s));
             HIP_TRY(launch_ms(p, 4, k, grid, s));
+            if (p.long_split) HIP_TRY(launch_ms(p, 9, k, grid, s));   // long rows' later chunks
             HIP_TRY(launch_ms(p, 6, k, grid, s));
             HIP_TRY(launch_ms(p, 5, k, grid, s));
         } else {

@@ -135,6 +135,8 @@ struct MsLevel {
     uint32_t use_fbits;
     uint32_t wide_steps;           // push: 64 frontier columns per wave step always
                                    // (average degree below 8), else sized to the list
+    uint32_t long_split;           // pull: long rows' first chunks, then the later ones
+                                   // in a second launch (k_ms_pull_rest)
 };
 
 struct MsLayout {

@@ -373,6 +373,33 @@ __global__ __launch_bounds__(kBlock) void k_ms_fbits(MsLevel p, uint32_t k) {
 // grid: each chunk gives its first hits (atomicMin on the staged parent) and
 // ORs its bits into the next mask; k_ms_fixup then folds those into vis and
 // lists the rows.  Also clears F_{k-1}'s masks.
+// Chunk j (kMsChunk entries) of long row v, scanned by one wave in ascending
+// order until every unsettled source is found: first hits go to the staged
+// parents by atomicMin, the bits found are ORed into the next mask and, for
+// the row's first chunk (first = true), into vis as well.
+__device__ __forceinline__ void long_chunk(const MsLevel &p, const unsigned long long *cur,
+                                           unsigned long long *nxt, int32_t v, uint32_t j,
+                                           uint32_t k, bool first) {
+    const uint32_t W = p.W, tail = p.nq & 63u;
+    const int32_t r1 = p.in_ptr[v + 1];
+    const int32_t e0 = p.in_ptr[v] + (int32_t)(j * kMsChunk);
+    const int32_t e1 = (e0 + (int32_t)kMsChunk < r1) ? e0 + (int32_t)kMsChunk : r1;
+    unsigned long long *vis = row(p.vis, v, W);
+    for (uint32_t w = 0; w < W; ++w) {
+        const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+        unsigned long long rem = full & ~vis[w], found = 0ull;
+        for (int32_t eb = e0; eb < e1 && rem; eb += 64) {
+            const unsigned long long f = scan_step<64>(p, cur, v, w, eb, e1, rem, k + 1, false);
+            rem &= ~f;
+            found |= f;
+        }
+        if (found && __lane_id() == 0) {
+            atomicOr(&row(nxt, v, W)[w], found);
+            if (first) vis[w] |= found;
+        }
+    }
+}
+
 constexpr uint32_t kMsRows = 1024;       // rows per block chunk
 constexpr int32_t kMsSerial = 16;        // longest row one lane scans alone
 constexpr uint32_t kMsGroupRow = 64;     // longest row a group of 16 lanes scans
@@ -562,24 +589,39 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
         for (uint32_t i = tid; i < s_n; i += kBlock) fnxt[s_base + i] = s_list[i];
         __syncthreads();
     }
-    // chunks of the long rows, one wave each; vis is not written in this
-    // kernel for these rows, so every chunk sees the same unsettled bits
-    for (uint32_t c = gt >> 6; c < p.nli_chunks; c += gs >> 6) {
-        const MsLong L = p.li[p.limap[c]];
-        const int32_t v = L.v;
-        const int32_t r1 = p.in_ptr[v + 1];
-        const int32_t e0 = p.in_ptr[v] + (int32_t)((c - L.chunk_base) * kMsChunk);
-        const int32_t e1 = (e0 + (int32_t)kMsChunk < r1) ? e0 + (int32_t)kMsChunk : r1;
-        for (uint32_t w = 0; w < W; ++w) {
-            const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
-            unsigned long long rem = full & ~row(p.vis, v, W)[w], found = 0ull;
-            for (int32_t eb = e0; eb < e1 && rem; eb += 64) {
-                const unsigned long long f = scan_step<64>(p, cur, v, w, eb, e1, rem, lk, false);
-                rem &= ~f;
-                found |= f;
-            }
-            if (found && lane == 0) atomicOr(&row(nxt, v, W)[w], found);
+    // The long rows, one wave per chunk.  With long_split, only each row's
+    // first chunk here: it holds the row's smallest in-neighbours, so what
+    // it finds is final - those bits go into vis now (no other wave touches
+    // this row's vis in this kernel) and k_ms_pull_rest then scans the later
+    // chunks for the other sources only.  Without it, every chunk here, all
+    // looking for the same unsettled sources (vis is not written).
+    const uint32_t nitems = p.long_split ? p.nli : p.nli_chunks;
+    for (uint32_t c = gt >> 6; c < nitems; c += gs >> 6) {           // uniform per wave
+        int32_t v;
+        uint32_t j = 0;
+        if (p.long_split) {
+            v = p.li[c].v;
+        } else {
+            const MsLong L = p.li[p.limap[c]];
+            v = L.v;
+            j = c - L.chunk_base;
         }
+        long_chunk(p, cur, nxt, v, j, k, p.long_split != 0u);
+    }
+}
+
+// Level k, pull form, the later chunks of the long rows (after k_ms_pull):
+// each looks only for the sources the row's first chunk left unsettled (vis
+// holds those found there), gives its first hits to the staged parents by
+// atomicMin (the smallest over the chunks) and ORs its bits into the next
+// mask; k_ms_fixup then folds those into vis and lists the rows.
+__global__ __launch_bounds__(kBlock) void k_ms_pull_rest(MsLevel p, uint32_t k) {
+    const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], k % 3);
+    unsigned long long *nxt = pick3(p.m[0], p.m[1], p.m[2], (k + 1) % 3);
+    const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
+    for (uint32_t c = gt >> 6; c < p.nli_chunks; c += gs >> 6) {        // uniform per wave
+        const MsLong L = p.li[p.limap[c]];
+        if (c != L.chunk_base) long_chunk(p, cur, nxt, L.v, c - L.chunk_base, k, false);
     }
 }
 
@@ -716,6 +758,7 @@ hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hip
         case 6: hipLaunchKernelGGL(k_ms_fixup, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 7: hipLaunchKernelGGL(k_ms_out, dim3(grid), dim3(kBlock), 0, s, p); break;
         case 8: hipLaunchKernelGGL(k_ms_fbits, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        case 9: hipLaunchKernelGGL(k_ms_pull_rest, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         default: hipLaunchKernelGGL(k_ms_report, dim3(1), dim3(64), 0, s, p, k); break;
     }
     return hipGetLastError();

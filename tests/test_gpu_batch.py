@@ -171,3 +171,25 @@ def test_vertex_major_level_count(P, name):
         assert int(l[:, :len(src)].max()) + 1 == want
         for q in (0, len(src) - 1):
             assert_same(g, src[q], (l[:, q].copy(), pa[:, q].cpu().numpy().copy()), f"{name}/q{q}")
+
+
+@pytest.mark.parametrize("grid_blocks", [1, 3])
+@pytest.mark.parametrize("name", ["rmat", "rmatd"])
+def test_long_rows_split_across_launches(P, name, grid_blocks):
+    """A grid small enough that the long rows' later chunks outnumber its
+    waves: each long row's first chunk settles what it finds and a second
+    launch scans the later chunks for the rest; both output layouts, pull on
+    every level, against the oracle."""
+    import torch
+    g = {"rmat": lambda: graphgen.rmat(14, 16, 71),
+         "rmatd": lambda: graphgen.rmat(13, 16, 72, directed=True)}[name]()
+    G = P.Graph.from_graphgen(g)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = [int(s) for s in np.random.default_rng(73).choice(cand, size=70, replace=False)]
+    say(f"[batch] {name} long-row split, {grid_blocks} workgroups")
+    lv, pa = P.bfs_batch(G, src, variant="pull", grid_blocks=grid_blocks)
+    vl, vp = P.bfs_batch_vm(G, src, variant="pull", grid_blocks=grid_blocks)
+    torch.cuda.synchronize()
+    for q in (0, 35, 69):
+        assert_same(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/q{q}")
+    assert torch.equal(vl[:, :70], torch.stack(lv, 1)) and torch.equal(vp[:, :70], torch.stack(pa, 1))
