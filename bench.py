@@ -26,13 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_level_rmat22_push_traffic.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1906_03113_amd", "csrc", "bfs_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sl_level_rmat22_push_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1906_03113_amd", "csrc", "bfs_slice.hip")
 
 
 def measured_traffic():
-    """HBM bytes per k_level launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary, or None when the kernel source changed since it was measured."""
+    """HBM bytes per level launch of the plain push (k_sl_level) from the
+    committed FETCH_SIZE / WRITE_SIZE summary, or None when there is none or
+    the kernel source changed since it was measured."""
     import hashlib
     try:
         txt = open(TRAFFIC_FILE).read()

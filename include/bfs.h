@@ -112,7 +112,31 @@ typedef struct bfs_run_options {
     uint32_t launches;         /* out (time_kernels): level-kernel launches issued, including
                                   launches after the last level, which return at once          */
     float kernel_us;           /* out (time_kernels): summed device time of those launches      */
+    uint32_t push_impl;        /* BFS_VARIANT_PUSH only: BFS_PUSH_AUTO (0), BFS_PUSH_LIST or
+                                  BFS_PUSH_SLICED (see below)                                   */
 } bfs_run_options;
+
+/*
+ * How BFS_VARIANT_PUSH runs (same results either way).
+ *   BFS_PUSH_LIST    the frontier as a compacted list, the row mask read from
+ *                    a bitmap in L2, the parent min-selected by atomicMin over
+ *                    every unmasked pair of the level (Lemma 1's form).
+ *   BFS_PUSH_SLICED  the frontier as a bitmap, the row mask in LDS: each
+ *                    workgroup holds a slice (<= 128 KiB) of the visited bitmap
+ *                    and expands the parts of the frontier columns whose rows
+ *                    fall in it; a reached row is claimed by setting its LDS
+ *                    bit, and receives its level and its parent (the first
+ *                    in-neighbour, in ascending order, in the previous
+ *                    frontier) when the next level expands it.  Needs
+ *                    n <= 4 * 2^20 and the host or graph loop (BFS_EINVAL
+ *                    otherwise).
+ *   BFS_PUSH_AUTO    sliced when it applies, the list form otherwise.
+ */
+enum {
+    BFS_PUSH_AUTO = 0,
+    BFS_PUSH_LIST = 1,
+    BFS_PUSH_SLICED = 2
+};
 
 /*
  * Create a graph from the CSR of A (out-neighbours: row i lists j with A(i,j)=1;
@@ -379,6 +403,16 @@ bfs_status bfs_masked_spmspv(bfs_graph *g, uint32_t semiring, const int32_t *x_i
                              const uint32_t *col_mask, uint32_t mask_flags, int32_t *y_idx,
                              uint64_t *y_val, int32_t *ny, void *workspace, size_t ws_bytes,
                              void *hip_stream);
+
+/*
+ * Re-cut the sliced push's bitmap slices to at most max_words 32-bit words
+ * each (a multiple of 4 in [4, 32768]; the default cut uses 32768, i.e.
+ * 128 KiB of LDS per workgroup).  Smaller slices mean more slices (at most 4)
+ * and fewer rows per workgroup; results never change.  Synchronous; no search
+ * may be running on g.  Errors: BFS_EINVAL (NULL graph, bad size, or more
+ * than 4 slices for this n), BFS_ENOMEM, BFS_EHIP (the previous cut is kept).
+ */
+bfs_status bfs_graph_set_slice_words(bfs_graph *g, uint32_t max_words);
 
 /* Static text for a status code. */
 const char *bfs_status_string(bfs_status s);

@@ -102,6 +102,10 @@ class Graph:
     def roots_workspace_size(self, nroots: int) -> int:
         return int(_lib.lib().bfs_roots_workspace_size(self.handle, int(nroots)))
 
+    def set_slice_words(self, max_words: int) -> None:
+        """Re-cut the sliced push's LDS bitmap slices (at most `max_words` words each)."""
+        _lib.check(_lib.lib().bfs_graph_set_slice_words(self.handle, int(max_words)))
+
     def close(self) -> None:
         if self._h is not None:
             _lib.lib().bfs_graph_destroy(self._h)
@@ -134,8 +138,10 @@ class Workspace:
 
 def make_options(variant="push", loop="host", levels_per_sync=0, grid_blocks=0,
                  heavy_degree=0, chunk_edges=0, selector=None, trace_capacity=0,
-                 time_kernels=False, ms_pull_shift=0) -> Tuple[RunOptions, Optional[ctypes.Array]]:
+                 time_kernels=False, ms_pull_shift=0,
+                 push_impl="auto") -> Tuple[RunOptions, Optional[ctypes.Array]]:
     o = RunOptions()
+    o.push_impl = _lib.PUSH_IMPLS[push_impl] if isinstance(push_impl, str) else int(push_impl)
     o.time_kernels = 1 if time_kernels else 0
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.loop_mode = LOOPS[loop] if isinstance(loop, str) else int(loop)

@@ -13,6 +13,7 @@ BFS_DIRECTED, BFS_INPUT_ON_DEVICE, BFS_VALIDATE_TRANSPOSE = 1, 2, 4
 VARIANTS = {"push": 0, "pull": 1, "bitmap": 2, "learned": 3, "heuristic": 4, "short_circuit": 5}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 LOOPS = {"host": 0, "graph": 1, "persistent": 2}
+PUSH_IMPLS = {"auto": 0, "list": 1, "sliced": 2}
 COMPARE = {"spmv": 0, "spmspv": 1, "spmmspv": 2}
 SEMIRINGS = {"boolean": 0, "arithmetic": 1, "min_plus": 2, "min_select": 3}
 
@@ -32,7 +33,7 @@ class RunOptions(ctypes.Structure):
                 ("trace", ctypes.POINTER(LevelRecord)), ("trace_capacity", ctypes.c_uint32),
                 ("time_kernels", ctypes.c_uint32), ("trace_count", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32), ("launches", ctypes.c_uint32),
-                ("kernel_us", ctypes.c_float)]
+                ("kernel_us", ctypes.c_float), ("push_impl", ctypes.c_uint32)]
 
 
 class BfsError(RuntimeError):
@@ -108,6 +109,8 @@ def _optional(L):
     L.bfs_masked_spmspv.argtypes = [vp, u32, vp, vp, i32, vp, vp, u32, vp, vp,
                                     ctypes.POINTER(i32), vp, sz, vp]
     L.bfs_masked_spmspv.restype = i32
+    L.bfs_graph_set_slice_words.argtypes = [vp, u32]
+    L.bfs_graph_set_slice_words.restype = i32
 
 
 def check(status: int) -> None:

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bfs_device.h"
 #include "bfs_internal.h"
 
 namespace bfsi {
@@ -37,36 +38,6 @@ constexpr int32_t kCmpSerial = 16;     // entries a lane multiplies alone
 constexpr uint32_t kCmpBuf = 256;      // per-wave staging of listed rows
 constexpr uint32_t kCmpFlush = kCmpBuf - 64;
 constexpr uint32_t kWaves = kBlock / 64;
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
-    return (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
-}
-
-__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t o = __shfl_xor(v, d, 64);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ int32_t wave_max(int32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const int32_t o = __shfl_xor(v, d, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
 
 __device__ __forceinline__ unsigned long long key_hi(uint32_t k) {
     return (unsigned long long)(0xFFFFFFFEu - k) << 32;

@@ -16,15 +16,24 @@
 
 using namespace bfsi;
 
-struct GraphExecCache {
-    bool valid = false;
-    const void *ws = nullptr;
-    const void *level = nullptr;
-    const void *parent = nullptr;
+// What a captured level loop depends on: any difference means a new capture.
+struct LoopKey {
+    uint32_t kind = 0;                 // 0: list-form level kernel, 1: sliced push
+    const void *ws = nullptr, *level = nullptr, *parent = nullptr;
     uint32_t policy = 0, grid = 0, heavy = 0, chunk = 0, levels = 0, fb = 0, stats = 0;
     const float *sel = nullptr;
-    const void *trace = nullptr;
-    const void *slot = nullptr;
+    const void *trace = nullptr, *slot = nullptr;
+    bool operator==(const LoopKey &o) const {
+        return kind == o.kind && ws == o.ws && level == o.level && parent == o.parent &&
+               policy == o.policy && grid == o.grid && heavy == o.heavy && chunk == o.chunk &&
+               levels == o.levels && fb == o.fb && stats == o.stats && sel == o.sel &&
+               trace == o.trace && slot == o.slot;
+    }
+};
+
+struct GraphExecCache {
+    bool valid = false;
+    LoopKey key;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -42,6 +51,13 @@ struct bfs_graph {
     bfsi::MsLong *lo = nullptr, *li = nullptr;
     uint32_t *lomap = nullptr, *limap = nullptr;
     uint32_t nlo = 0, nlo_chunks = 0, nli = 0, nli_chunks = 0;
+    // sliced push (bfs_slice.hip): per-vertex slice starts in the sorted
+    // out-lists and the chunks of long slice parts; sl_S = 0 when the graph's
+    // bitmap needs more than kSlMaxSlices slices
+    int4 *sl_seg = nullptr;
+    bfsi::SlChunk *sl_chunks = nullptr;
+    uint32_t sl_S = 0, sl_sw = 0;
+    uint32_t sl_chunk_off[bfsi::kSlMaxSlices + 1] = {};
     std::mutex mu;
     GraphExecCache gcache;
     std::vector<hipEvent_t> events;   // pool for per-launch timing
@@ -126,6 +142,8 @@ void free_graph(bfs_graph *g) {
     if (g->in_idx && g->in_idx != g->out_idx) (void)hipFree(g->in_idx);
     if (g->out_ptr) (void)hipFree(g->out_ptr);
     if (g->out_idx) (void)hipFree(g->out_idx);
+    if (g->sl_seg) (void)hipFree(g->sl_seg);
+    if (g->sl_chunks) (void)hipFree(g->sl_chunks);
     delete g;
 }
 
@@ -147,6 +165,67 @@ bfs_status build_long(int32_t n, const std::vector<int32_t> &ptr, bfsi::MsLong *
     bfs_status st = upload(ents, e.data(), e.size(), bytes);
     if (st == BFS_OK) st = upload(map, m.data(), m.size(), bytes);
     return st;
+}
+
+// The out-lists, padded with zeros to a multiple of four entries plus four, so
+// that the sliced push may read any list in aligned 16-byte quads.
+bfs_status upload_padded(int32_t **dst, const std::vector<int32_t> &idx, size_t &bytes) {
+    const size_t cnt = ((idx.size() + 3) & ~size_t(3)) + 4;
+    if (hipMalloc((void **)dst, cnt * 4) != hipSuccess) return fail(BFS_ENOMEM, "hipMalloc(%zu) failed", cnt * 4);
+    bytes += cnt * 4;
+    HIP_TRY(hipMemset(*dst, 0, cnt * 4));
+    if (!idx.empty()) HIP_TRY(hipMemcpy(*dst, idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
+    return BFS_OK;
+}
+
+// The sliced push's graph data: S slices of sw words (sw a multiple of 4, at
+// most kSlMaxSliceWords); seg[v] = {ptr[v], first entry of v's sorted list in
+// slice 1, 2, 3} (ptr[v + 1] for slices past the last); and every slice part
+// of at least kSlLong entries cut into chunks of kSlChunk, grouped by slice.
+bfs_status build_slices(bfs_graph *g, const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                        uint32_t max_words = bfsi::kSlMaxSliceWords) {
+    const int32_t n = g->n;
+    const uint64_t words = ((uint64_t)n + 31) / 32;
+    const uint64_t S = (words + max_words - 1) / max_words;
+    if (S == 0 || S > bfsi::kSlMaxSlices) return BFS_OK;          // not eligible: g->sl_S stays 0
+    const uint32_t sw = (uint32_t)(((words + S - 1) / S + 3) & ~uint64_t(3));
+    const int64_t sv = (int64_t)sw * 32;
+    std::vector<int4> seg((size_t)n + 1);
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t *b = idx.data() + ptr[v], *e = idx.data() + ptr[v + 1];
+        int32_t st[4];
+        st[0] = ptr[v];
+        for (int t = 1; t < 4; ++t) {
+            const int64_t bound = (int64_t)t * sv;
+            st[t] = bound >= n ? ptr[v + 1]
+                               : (int32_t)(std::lower_bound(b, e, (int32_t)bound) - idx.data());
+        }
+        seg[v] = make_int4(st[0], st[1], st[2], st[3]);
+    }
+    const int32_t nnz = ptr[n];
+    seg[n] = make_int4(nnz, nnz, nnz, nnz);
+    std::vector<bfsi::SlChunk> ch;
+    uint32_t off[bfsi::kSlMaxSlices + 1] = {};
+    for (uint32_t s = 0; s < bfsi::kSlMaxSlices; ++s) {
+        off[s] = (uint32_t)ch.size();
+        if (s >= S) continue;
+        for (int32_t v = 0; v < n; ++v) {
+            const int4 q = seg[v];
+            const int32_t a = s == 0 ? q.x : (s == 1 ? q.y : (s == 2 ? q.z : q.w));
+            const int32_t e = s == 3 ? seg[v + 1].x : (s == 0 ? q.y : (s == 1 ? q.z : q.w));
+            if (e - a < (int32_t)bfsi::kSlLong) continue;
+            for (int32_t c = a; c < e; c += (int32_t)bfsi::kSlChunk)
+                ch.push_back(bfsi::SlChunk{v, c, std::min<int32_t>(e, c + (int32_t)bfsi::kSlChunk), 0});
+        }
+    }
+    off[bfsi::kSlMaxSlices] = (uint32_t)ch.size();
+    bfs_status st = upload(&g->sl_seg, seg.data(), seg.size(), g->bytes);
+    if (st == BFS_OK) st = upload(&g->sl_chunks, ch.data(), ch.size(), g->bytes);
+    if (st != BFS_OK) return st;
+    g->sl_S = (uint32_t)S;
+    g->sl_sw = sw;
+    for (uint32_t s = 0; s <= bfsi::kSlMaxSlices; ++s) g->sl_chunk_off[s] = off[s];
+    return BFS_OK;
 }
 
 }  // namespace
@@ -309,47 +388,30 @@ bfs_status wait_progress(const HostSlot *hs, hipStream_t s, bool &done, uint32_t
     return BFS_OK;
 }
 
-bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t s,
-                      uint32_t &levels_out, bfs_run_options *opt) {
-    HostSlot *hs = nullptr;
-    bfs_status st0 = host_slot(hs);
-    if (st0 != BFS_OK) return st0;
-    P.host_status = hs->d;
-    hs->h[0] = 0;
-    hs->h[1] = 1;
+// The host loop and the captured-graph loop around a level launch: `launch`
+// issues one level on a stream; levels are issued `per_sync` at a time
+// between two reads of the progress slot (launches past the end return at
+// once).  The captured graph is cached per bfs_graph under `key`.  With
+// opt->time_kernels (host loop) every launch is bracketed by HIP events and
+// `times` receives the launches' device times.
+template <class Launch>
+bfs_status level_loop(bfs_graph *g, const LoopKey &key, uint32_t loop, hipStream_t s, HostSlot *hs,
+                      Launch launch, uint32_t &level, std::vector<float> &times, bfs_run_options *opt) {
     const uint64_t max_levels = (uint64_t)g->n + 2;
+    const uint32_t L = key.levels;
     bool done = false;
-    uint32_t level = 0;
-    std::vector<float> times;
     std::unique_lock<std::mutex> lock(g->mu, std::defer_lock);
-    if (c.loop == BFS_LOOP_PERSISTENT) {
-        uint32_t maxg = persistent_max_grid(g->device);
-        if (maxg == 0) return fail(BFS_EHIP, "occupancy query for the persistent kernel failed");
-        uint32_t grid = std::min(c.grid, maxg);
-        HIP_TRY(launch_persistent(P, grid, s));
-        bfs_status st = wait_progress(hs, s, done, level);
-        if (st != BFS_OK) return st;
-        if (!done) return fail(BFS_EHIP, "persistent search stopped at level %u with a nonempty frontier "
-                                         "(grid barrier spin limit)", level);
-    } else if (c.loop == BFS_LOOP_GRAPH) {
+    if (loop == BFS_LOOP_GRAPH) {
         lock.lock();                  // the captured graph is cached per bfs_graph
         GraphExecCache &gc = g->gcache;
-        const uint32_t L = c.per_sync;
-        bool hit = gc.valid && gc.ws == (const void *)P.st && gc.level == P.level &&
-                   gc.parent == P.parent && gc.policy == c.policy && gc.grid == c.grid &&
-                   gc.heavy == c.heavy && gc.chunk == c.chunk && gc.levels == L &&
-                   gc.sel == c.sel && gc.fb == P.maintain_fb && gc.stats == P.stats &&
-                   gc.trace == (const void *)P.trace && gc.slot == (const void *)P.host_status;
-        if (!hit) {
+        if (!(gc.valid && gc.key == key)) {
             if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
             if (gc.graph) { (void)hipGraphDestroy(gc.graph); gc.graph = nullptr; }
             gc.valid = false;
             hipStream_t cap;
             HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            for (uint32_t l = 0; l < L && e == hipSuccess; ++l) {
-                e = launch_level(P, c.grid, cap);
-            }
+            for (uint32_t l = 0; l < L && e == hipSuccess; ++l) e = launch(cap);
             hipGraph_t graph = nullptr;
             hipError_t e2 = hipStreamEndCapture(cap, &graph);
             (void)hipStreamDestroy(cap);
@@ -363,10 +425,8 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
             }
             gc.graph = graph;
             gc.exec = exec;
-            gc.ws = P.st; gc.level = P.level; gc.parent = P.parent; gc.policy = c.policy;
-            gc.grid = c.grid; gc.heavy = c.heavy; gc.chunk = c.chunk; gc.levels = L;
-            gc.sel = c.sel; gc.fb = P.maintain_fb; gc.stats = P.stats;
-            gc.trace = (const void *)P.trace; gc.slot = (const void *)P.host_status; gc.valid = true;
+            gc.key = key;
+            gc.valid = true;
         }
         for (uint64_t issued = 0; !done; issued += L) {
             if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
@@ -374,75 +434,204 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
             bfs_status st = wait_progress(hs, s, done, level);
             if (st != BFS_OK) return st;
         }
+        return BFS_OK;
+    }
+    const bool tk = opt && opt->time_kernels;
+    if (tk) lock.lock();              // the event pool is per bfs_graph
+    uint32_t launched = 0;
+    auto ev = [&](uint32_t i, hipEvent_t &out) -> bfs_status {
+        while (g->events.size() <= i) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            g->events.push_back(e);
+        }
+        out = g->events[i];
+        return BFS_OK;
+    };
+    for (uint64_t issued = 0; !done; issued += L) {
+        if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
+        for (uint32_t l = 0; l < L; ++l) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (tk) {
+                bfs_status st = ev(2 * launched, e0);
+                if (st == BFS_OK) st = ev(2 * launched + 1, e1);
+                if (st != BFS_OK) return st;
+                HIP_TRY(hipEventRecord(e0, s));
+            }
+            HIP_TRY(launch(s));
+            if (tk) HIP_TRY(hipEventRecord(e1, s));
+            ++launched;
+        }
+        bfs_status st = wait_progress(hs, s, done, level);
+        if (st != BFS_OK) return st;
+    }
+    if (tk) {
+        float total = 0.f;
+        for (uint32_t i = 0; i < launched; ++i) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, g->events[2 * i], g->events[2 * i + 1]));
+            total += ms * 1000.f;
+            times.push_back(ms * 1000.f);
+        }
+        opt->launches = launched;
+        opt->kernel_us = total;
+    }
+    return BFS_OK;
+}
+
+// Copy the device's per-level records into opt->trace (host), with the
+// launches' device times when they were taken.
+bfs_status read_trace(const DevLevelRec *dtrace, uint32_t levels, const std::vector<float> &times,
+                      bfs_run_options *opt, hipStream_t s) {
+    if (!opt) return BFS_OK;
+    if (!(opt->trace && dtrace)) {
+        opt->trace_count = 0;
+        return BFS_OK;
+    }
+    const uint32_t nrec = std::min<uint32_t>(std::min<uint32_t>(levels, kTraceCap), opt->trace_capacity);
+    std::vector<DevLevelRec> recs(nrec ? nrec : 1);
+    if (nrec) {
+        HIP_TRY(hipMemcpyAsync(recs.data(), dtrace, nrec * sizeof(DevLevelRec), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    for (uint32_t r = 0; r < nrec; ++r) {
+        bfs_level_record &o = opt->trace[r];
+        o.level = (int32_t)recs[r].level;
+        o.variant = (int32_t)recs[r].variant;
+        o.frontier = recs[r].nf;
+        o.unvisited = recs[r].nu;
+        o.frontier_edges = recs[r].sdf;
+        o.unvisited_edges = recs[r].sdu;
+        o.time_us = (r < times.size()) ? times[r] : 0.f;
+        o.reserved = 0.f;
+    }
+    opt->trace_count = nrec;
+    return BFS_OK;
+}
+
+bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t s,
+                      uint32_t &levels_out, bfs_run_options *opt) {
+    HostSlot *hs = nullptr;
+    bfs_status st0 = host_slot(hs);
+    if (st0 != BFS_OK) return st0;
+    P.host_status = hs->d;
+    hs->h[0] = 0;
+    hs->h[1] = 1;
+    bool done = false;
+    uint32_t level = 0;
+    std::vector<float> times;
+    if (c.loop == BFS_LOOP_PERSISTENT) {
+        uint32_t maxg = persistent_max_grid(g->device);
+        if (maxg == 0) return fail(BFS_EHIP, "occupancy query for the persistent kernel failed");
+        uint32_t grid = std::min(c.grid, maxg);
+        HIP_TRY(launch_persistent(P, grid, s));
+        bfs_status st = wait_progress(hs, s, done, level);
+        if (st != BFS_OK) return st;
+        if (!done) return fail(BFS_EHIP, "persistent search stopped at level %u with a nonempty frontier "
+                                         "(grid barrier spin limit)", level);
     } else {
-        const bool tk = opt && opt->time_kernels;
-        if (tk) lock.lock();          // the event pool is per bfs_graph
-        const uint32_t L = c.per_sync;
-        uint32_t launched = 0;
-        auto ev = [&](uint32_t i, hipEvent_t &out) -> bfs_status {
-            while (g->events.size() <= i) {
-                hipEvent_t e;
-                HIP_TRY(hipEventCreate(&e));
-                g->events.push_back(e);
-            }
-            out = g->events[i];
-            return BFS_OK;
-        };
-        for (uint64_t issued = 0; !done; issued += L) {
-            if (issued > max_levels) return fail(BFS_EHIP, "level loop did not terminate");
-            for (uint32_t l = 0; l < L; ++l) {
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (tk) {
-                    bfs_status st = ev(2 * launched, e0);
-                    if (st == BFS_OK) st = ev(2 * launched + 1, e1);
-                    if (st != BFS_OK) return st;
-                    HIP_TRY(hipEventRecord(e0, s));
-                }
-                HIP_TRY(launch_level(P, c.grid, s));
-                if (tk) HIP_TRY(hipEventRecord(e1, s));
-                ++launched;
-            }
-            bfs_status st = wait_progress(hs, s, done, level);
-            if (st != BFS_OK) return st;
-        }
-        if (tk) {
-            float total = 0.f;
-            for (uint32_t i = 0; i < launched; ++i) {
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, g->events[2 * i], g->events[2 * i + 1]));
-                total += ms * 1000.f;
-                times.push_back(ms * 1000.f);
-            }
-            opt->launches = launched;
-            opt->kernel_us = total;
-        }
+        LoopKey key;
+        key.kind = 0;
+        key.ws = P.st; key.level = P.level; key.parent = P.parent; key.policy = c.policy;
+        key.grid = c.grid; key.heavy = c.heavy; key.chunk = c.chunk; key.levels = c.per_sync;
+        key.sel = c.sel; key.fb = P.maintain_fb; key.stats = P.stats;
+        key.trace = (const void *)P.trace; key.slot = (const void *)P.host_status;
+        const LevelParams Pc = P;
+        const uint32_t grid = c.grid;
+        bfs_status st = level_loop(g, key, c.loop, s, hs,
+                                   [&Pc, grid](hipStream_t st_) { return launch_level(Pc, grid, st_); },
+                                   level, times, opt);
+        if (st != BFS_OK) return st;
     }
     levels_out = level;
     if (c.policy == kShortCircuit) HIP_TRY(launch_parents(P, c.grid, s));     // the parents, after the levels
-    if (opt && opt->trace && P.trace) {
-        const uint32_t nrec = std::min<uint32_t>(std::min<uint32_t>(levels_out, kTraceCap), opt->trace_capacity);
-        std::vector<DevLevelRec> recs(nrec ? nrec : 1);
-        if (nrec) {
-            HIP_TRY(hipMemcpyAsync(recs.data(), P.trace, nrec * sizeof(DevLevelRec),
-                                   hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-        }
-        for (uint32_t r = 0; r < nrec; ++r) {
-            bfs_level_record &o = opt->trace[r];
-            o.level = (int32_t)recs[r].level;
-            o.variant = (int32_t)recs[r].variant;
-            o.frontier = recs[r].nf;
-            o.unvisited = recs[r].nu;
-            o.frontier_edges = recs[r].sdf;
-            o.unvisited_edges = recs[r].sdu;
-            o.time_us = (r < times.size()) ? times[r] : 0.f;
-            o.reserved = 0.f;
-        }
-        opt->trace_count = nrec;
-    } else if (opt) {
-        opt->trace_count = 0;
-    }
+    return read_trace(P.trace, levels_out, times, opt, s);
+}
+
+// Workspace of one search, whichever form runs it.
+size_t ws_single(const bfs_graph *g) {
+    const size_t list = ws_layout(g->n, g->nnz, kHeavyFloor).total;
+    const size_t sliced = g->sl_S ? sl_layout(g->sl_S * g->sl_sw).total : 0;
+    return std::max(list, sliced);
+}
+
+// The sliced push's launch size: 8 * S * R workgroups, R = compute units per
+// (8 * S) (at least one), one workgroup per compute unit.
+uint32_t sl_grid(const bfs_graph *g) {
+    const uint32_t cus = (uint32_t)(g->cus > 0 ? g->cus : 256);
+    const uint32_t per = 8u * g->sl_S;
+    const uint32_t r = std::max<uint32_t>(1u, cus / per);
+    return per * r;
+}
+
+bool sliced_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
+    const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
+    return c.policy == kPush && impl != BFS_PUSH_LIST && g->sl_S != 0 && c.loop != BFS_LOOP_PERSISTENT;
+}
+
+bfs_status check_push_impl(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
+    const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
+    if (impl > BFS_PUSH_SLICED) return fail(BFS_EINVAL, "unknown push_impl %u", impl);
+    if (impl == BFS_PUSH_SLICED && !sliced_applies(g, c, opt))
+        return fail(BFS_EINVAL, "the sliced push needs variant PUSH, the host or graph loop and "
+                                "n <= %u (n = %d)", bfsi::kSlMaxSlices * bfsi::kSlMaxSliceWords * 32u, g->n);
     return BFS_OK;
+}
+
+SlParams make_sl_params(bfs_graph *g, int32_t *level, int32_t *parent, void *ws, bool trace) {
+    const SlLayout L = sl_layout(g->sl_S * g->sl_sw);
+    char *b = (char *)ws;
+    SlParams P{};
+    P.n = g->n;
+    P.nnz = g->nnz;
+    P.S = g->sl_S;
+    P.sw = g->sl_sw;
+    P.words = g->sl_S * g->sl_sw;
+    P.streams = sl_grid(g) / g->sl_S;
+    P.seg = g->sl_seg;
+    P.out_idx4 = (const int4 *)g->out_idx;
+    P.in_ptr = g->directed ? g->in_ptr : nullptr;
+    P.in_idx = g->in_idx;
+    P.chunks = g->sl_chunks;
+    for (uint32_t i = 0; i <= bfsi::kSlMaxSlices; ++i) P.chunk_off[i] = g->sl_chunk_off[i];
+    P.level = level;
+    P.parent = parent;
+    P.vb[0] = (uint32_t *)(b + L.vb0);
+    P.vb[1] = (uint32_t *)(b + L.vb1);
+    P.cb[0] = (uint32_t *)(b + L.c0);
+    P.cb[1] = (uint32_t *)(b + L.c1);
+    P.cb[2] = (uint32_t *)(b + L.c2);
+    P.cb[3] = (uint32_t *)(b + L.c3);
+    P.st = (SlState *)(b + L.state);
+    P.trace = trace ? (DevLevelRec *)(b + L.trace) : nullptr;
+    return P;
+}
+
+// A search (single root, or roots_dev with nroots) by the sliced push.
+bfs_status run_sliced(bfs_graph *g, int32_t source, int32_t nroots, const int32_t *roots_dev,
+                      int32_t *level, int32_t *parent, const RunCfg &c, void *ws, hipStream_t s,
+                      bfs_run_options *opt) {
+    HostSlot *hs = nullptr;
+    bfs_status st = host_slot(hs);
+    if (st != BFS_OK) return st;
+    SlParams P = make_sl_params(g, level, parent, ws, opt && opt->trace != nullptr);
+    P.host_status = hs->d;
+    hs->h[0] = 0;
+    hs->h[1] = 1;
+    HIP_TRY(launch_sl_init(P, nroots, roots_dev, source, s));
+    const uint32_t grid = sl_grid(g);
+    LoopKey key;
+    key.kind = 1;
+    key.ws = P.st; key.level = level; key.parent = parent; key.grid = grid;
+    key.levels = c.per_sync; key.trace = (const void *)P.trace; key.slot = (const void *)P.host_status;
+    uint32_t levels = 0;
+    std::vector<float> times;
+    const SlParams Pc = P;
+    st = level_loop(g, key, c.loop, s, hs, [&Pc, grid](hipStream_t st_) { return launch_sl_level(Pc, grid, st_); },
+                    levels, times, opt);
+    if (st != BFS_OK) return st;
+    if (opt) opt->levels = levels;
+    return read_trace(P.trace, levels, times, opt, s);
 }
 
 }  // namespace
@@ -540,7 +729,7 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
     if (hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess)
         g->cus = 0;                           // launch sizes then assume 256 compute units
     bfs_status st = upload(&g->out_ptr, ptr.data(), ptr.size(), g->bytes);
-    if (st == BFS_OK) st = upload(&g->out_idx, idx.data(), idx.size(), g->bytes);
+    if (st == BFS_OK) st = upload_padded(&g->out_idx, idx, g->bytes);
     if (st == BFS_OK && directed) {
         st = upload(&g->in_ptr, iptr.data(), iptr.size(), g->bytes);
         if (st == BFS_OK) st = upload(&g->in_idx, iidx.data(), iidx.size(), g->bytes);
@@ -550,6 +739,7 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
     }
     try {
         if (st == BFS_OK) st = build_long(n, ptr, &g->lo, &g->lomap, g->nlo, g->nlo_chunks, g->bytes);
+        if (st == BFS_OK) st = build_slices(g, ptr, idx);
         if (st == BFS_OK && directed) {
             st = build_long(n, iptr, &g->li, &g->limap, g->nli, g->nli_chunks, g->bytes);
         } else if (st == BFS_OK) {
@@ -588,7 +778,7 @@ bfs_status bfs_graph_info(const bfs_graph *g, int32_t *n, int64_t *nnz, int32_t 
 
 size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_flags) {
     if (!g || num_queries <= 0 || run_flags != 0) return 0;
-    const size_t single = ws_layout(g->n, g->nnz, kHeavyFloor).total;
+    const size_t single = ws_single(g);
     if (num_queries == 1) return single;
     return std::max(single, ms_layout(g->n, num_queries).total);
 }
@@ -607,7 +797,11 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
     if (c.policy == kPull || c.policy == kHeuristic || c.policy == kLearned) {
         if (!g->in_ptr) return fail(BFS_EINVAL, "pull needs the CSC");
     }
+    st = check_push_impl(g, c, opt);
+    if (st != BFS_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (sliced_applies(g, c, opt))
+        return run_sliced(g, source, 1, nullptr, level, parent, c, workspace, s, opt);
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
     HIP_TRY(launch_init(P, 1, nullptr, source, s));
@@ -629,8 +823,8 @@ extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t 
     if (!level || !parent || !workspace || !roots_host) return fail(BFS_EINVAL, "NULL argument");
     if (nroots <= 0 || nroots > g->n) return fail(BFS_EINVAL, "nroots = %d outside [1, n]", nroots);
     if (((uintptr_t)workspace & 255) != 0) return fail(BFS_EINVAL, "workspace must be 256-byte aligned");
-    const WsLayout L = ws_layout(g->n, g->nnz, kHeavyFloor);
-    const size_t need = L.total + align256((size_t)nroots * 4);
+    const size_t base = ws_single(g);
+    const size_t need = base + align256((size_t)nroots * 4);
     if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     std::vector<char> seen((size_t)g->n, 0);
     for (int32_t r = 0; r < nroots; ++r) {
@@ -642,11 +836,15 @@ extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t 
     RunCfg c{};
     bfs_status st = resolve_cfg(g, opt, c);
     if (st != BFS_OK) return st;
+    st = check_push_impl(g, c, opt);
+    if (st != BFS_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
+    int32_t *roots_dev = (int32_t *)((char *)workspace + base);
+    HIP_TRY(hipMemcpyAsync(roots_dev, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, s));
+    if (sliced_applies(g, c, opt))
+        return run_sliced(g, -1, nroots, roots_dev, level, parent, c, workspace, s, opt);
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
-    int32_t *roots_dev = (int32_t *)((char *)workspace + L.total);
-    HIP_TRY(hipMemcpyAsync(roots_dev, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_init(P, nroots, roots_dev, -1, s));
     uint32_t levels = 0;
     st = run_levels(g, P, c, s, levels, opt);
@@ -657,7 +855,7 @@ extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t 
 
 extern "C" size_t bfs_roots_workspace_size(const bfs_graph *g, int32_t nroots) {
     if (!g || nroots <= 0) return 0;
-    return ws_layout(g->n, g->nnz, kHeavyFloor).total + align256((size_t)nroots * 4);
+    return ws_single(g) + align256((size_t)nroots * 4);
 }
 
 // A multi-source pull level tests the union-frontier bitmap before each mask
@@ -1108,4 +1306,64 @@ extern "C" bfs_status bfs_run_batch_vm(bfs_graph *g, int32_t num_sources, const 
     if (opt && opt->variant > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", opt->variant);
     return run_multi_source(g, num_sources, sources, nullptr, nullptr, opt, workspace,
                             (hipStream_t)hip_stream, level, parent);
+}
+
+// ---------------------------------------------------------------------------
+// Re-cut the sliced push's bitmap slices (tuning and testing)
+// ---------------------------------------------------------------------------
+
+extern "C" bfs_status bfs_graph_set_slice_words(bfs_graph *g, uint32_t max_words) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (max_words < 4 || max_words > kSlMaxSliceWords || (max_words & 3u))
+        return fail(BFS_EINVAL, "slice words %u: a multiple of 4 in [4, %u]", max_words, kSlMaxSliceWords);
+    const uint64_t words = ((uint64_t)g->n + 31) / 32;
+    if ((words + max_words - 1) / max_words > kSlMaxSlices)
+        return fail(BFS_EINVAL, "%u words per slice cut n = %d into more than %u slices", max_words, g->n,
+                    kSlMaxSlices);
+    std::lock_guard<std::mutex> lock(g->mu);
+    std::vector<int32_t> ptr, idx;
+    try {
+        ptr.resize((size_t)g->n + 1);
+        HIP_TRY(hipMemcpy(ptr.data(), g->out_ptr, ptr.size() * 4, hipMemcpyDeviceToHost));
+        idx.resize((size_t)ptr[g->n]);
+        if (!idx.empty()) HIP_TRY(hipMemcpy(idx.data(), g->out_idx, idx.size() * 4, hipMemcpyDeviceToHost));
+    } catch (const std::bad_alloc &) {
+        return fail(BFS_ENOMEM, "host allocation failed");
+    }
+    int4 *old_seg = g->sl_seg;
+    SlChunk *old_ch = g->sl_chunks;
+    const uint32_t old_S = g->sl_S, old_sw = g->sl_sw;
+    uint32_t old_off[kSlMaxSlices + 1];
+    for (uint32_t i = 0; i <= kSlMaxSlices; ++i) old_off[i] = g->sl_chunk_off[i];
+    const size_t old_bytes = g->bytes;
+    g->sl_seg = nullptr;
+    g->sl_chunks = nullptr;
+    g->sl_S = 0;
+    bfs_status st;
+    try {
+        st = build_slices(g, ptr, idx, max_words);
+    } catch (const std::bad_alloc &) {
+        st = fail(BFS_ENOMEM, "host allocation failed");
+    }
+    if (st != BFS_OK) {                       // keep the old cut
+        if (g->sl_seg) (void)hipFree(g->sl_seg);
+        if (g->sl_chunks) (void)hipFree(g->sl_chunks);
+        g->sl_seg = old_seg;
+        g->sl_chunks = old_ch;
+        g->sl_S = old_S;
+        g->sl_sw = old_sw;
+        for (uint32_t i = 0; i <= kSlMaxSlices; ++i) g->sl_chunk_off[i] = old_off[i];
+        g->bytes = old_bytes;
+        return st;
+    }
+    size_t freed = 0;
+    if (old_seg) { (void)hipFree(old_seg); freed += ((size_t)g->n + 1) * sizeof(int4); }
+    if (old_ch) {
+        (void)hipFree(old_ch);
+        const size_t nch = old_off[kSlMaxSlices];
+        freed += (nch ? nch : 1) * sizeof(SlChunk);
+    }
+    g->bytes -= std::min(freed, g->bytes);
+    g->gcache.valid = false;                  // captured launches hold the old slice parameters
+    return BFS_OK;
 }

@@ -89,6 +89,80 @@ struct WsLayout {
 };
 WsLayout ws_layout(int32_t n, uint32_t nnz, uint32_t heavy_min_floor);
 
+// ---------------------------------------------------------------------------
+// Sliced push (bfs_slice.hip): the push form with the row mask in LDS.
+//
+// The visited bitmap is cut into S <= kSlMaxSlices slices of sw words
+// (<= 128 KiB each).  Workgroup b keeps slice s(b) of B_k in LDS for the whole
+// level and expands only the part of each frontier column whose rows fall in
+// that slice: the graph stores, per vertex, where each slice starts in its
+// sorted out-list.  A reached row is claimed by an OR into the LDS slice; the
+// rows claimed by a workgroup are OR-ed into the level's claim bitmap C_{k+1}
+// at the end.  The frontier of level k is C_k itself (a bitmap), and a vertex
+// of C_k receives its level and parent while level k runs: its parent is the
+// first in-neighbour, in ascending order, that lies in C_{k-1}.
+// ---------------------------------------------------------------------------
+constexpr int kSlThreads = 1024;                // threads per workgroup (16 wave64s)
+constexpr int kSlWaves = kSlThreads / 64;
+constexpr uint32_t kSlMaxSliceWords = 32768;    // 128 KiB of bitmap in LDS
+constexpr uint32_t kSlMaxSlices = 4;            // n <= 4 * 2^20 vertices
+constexpr uint32_t kSlLong = 1024;              // a column's slice part this long or longer is chunked
+constexpr uint32_t kSlChunk = 1024;             // entries per chunk of such a part
+constexpr uint32_t kSlBatch = 128;              // ranges a wave expands together (2 per lane)
+
+// One chunk of a long slice part of a column: out_idx[a, e) of vertex v.
+struct alignas(16) SlChunk {
+    int32_t v, a, e, pad;
+};
+
+struct alignas(256) SlState {
+    uint32_t level;                          // current level k
+    uint32_t pad0[3];
+    uint32_t nclaim[kRing];                  // claim bits the level that built C_k found
+                                             // (>= |C_k| since workgroups overlap; 0 iff empty)
+    uint32_t nf[kRing];                      // |F_k|, counted as F_k is settled
+    unsigned long long sdf[kRing];           // sum of out-degrees over F_k
+    uint32_t visited_cnt;                    // |B_k| after level k closes
+    uint32_t pad1;
+    unsigned long long visited_deg;
+    uint32_t pad2[8];
+    // the running level's sums, one 64-byte line per group of workgroups:
+    // acc[8 g] = claim bits | (settled vertices << 32), acc[8 g + 1] = their degree sum
+    unsigned long long acc[kBarGroups * 8];
+    uint32_t bar_group[kBarGroups * 16];     // arrivals at the end of a level launch
+    uint32_t bar_top;
+    uint32_t pad3[15];
+};
+
+struct SlParams {
+    int32_t n;
+    uint32_t nnz;
+    uint32_t S;                      // slices
+    uint32_t sw;                     // 32-bit words per slice (a multiple of 4)
+    uint32_t words;                  // S * sw: words of every bitmap (padded)
+    uint32_t streams;                // workgroups per slice
+    const int4 *seg;                 // [n + 1]: {out_ptr[v], start of slices 1, 2, 3 in v's out-list}
+    const int4 *out_idx4;            // out_idx as 16-byte quads (padded to a multiple of 4 entries)
+    const int32_t *in_ptr, *in_idx;  // in-lists (undirected: the out-lists)
+    const SlChunk *chunks;           // chunk records, slice s at [chunk_off[s], chunk_off[s + 1])
+    uint32_t chunk_off[kSlMaxSlices + 1];
+    int32_t *level;
+    int32_t *parent;
+    uint32_t *vb[2];                 // visited bitmaps: level k reads B_{k-1} = vb[(k+1)&1], writes B_k = vb[k&1]
+    uint32_t *cb[4];                 // claim bitmaps: C_k = cb[k&3]
+    SlState *st;
+    DevLevelRec *trace;              // kTraceCap records, or nullptr
+    uint32_t *host_status;           // pinned host: [0] level, [1] claim count of that level (0 = done)
+};
+
+struct SlLayout {
+    size_t state, vb0, vb1, c0, c1, c2, c3, trace, total;
+};
+SlLayout sl_layout(uint32_t words);
+hipError_t launch_sl_init(const SlParams &p, int32_t nroots, const int32_t *roots_dev,
+                          int32_t single_root, hipStream_t s);
+hipError_t launch_sl_level(const SlParams &p, uint32_t grid, hipStream_t s);
+
 // Multi-source search (64 sources per 64-bit word per vertex).
 constexpr uint32_t kMsLong = 512;      // degree from which a multi-source list entry is split
 constexpr uint32_t kMsChunk = 512;     // entries per chunk of a split entry

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bfs_device.h"
 #include "bfs_internal.h"
 
 namespace bfsi {
@@ -43,10 +44,6 @@ __device__ __forceinline__ unsigned long long *row(unsigned long long *m, int32_
 template <typename T>
 __device__ __forceinline__ T pick3(T a, T b, T c, uint32_t s) {
     return s == 0 ? a : (s == 1 ? b : c);
-}
-
-__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
-    return (uint32_t)__popcll(m & ((1ull << __lane_id()) - 1ull));
 }
 
 __device__ __forceinline__ size_t stage(const MsLevel &p, int32_t v, uint32_t q) {

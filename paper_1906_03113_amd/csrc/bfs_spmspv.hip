@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bfs_device.h"
 #include "bfs_internal.h"
 
 namespace bfsi {
@@ -33,8 +34,6 @@ namespace {
 constexpr int32_t kSpSerial = 16;
 constexpr uint32_t kWaves = kBlock / 64;
 constexpr int kScanBlock = 1024;
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ bool allowed(const uint32_t *mask, uint32_t comp, int32_t v) {
     if (mask == nullptr) return true;
@@ -60,15 +59,6 @@ __device__ __forceinline__ void accumulate(const SpParams &P, int32_t i, unsigne
         const unsigned long long c = ~p;                 // min of p == max of ~p
         if (c != 0ull && P.acc[i] < c) atomicMax(&P.acc[i], c);
     }
-}
-
-__device__ __forceinline__ int32_t wave_max(int32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const int32_t o = __shfl_xor(v, d, 64);
-        v = o > v ? o : v;
-    }
-    return v;
 }
 
 // Exclusive prefix sum over a workgroup of kScanBlock threads (LDS), and the
