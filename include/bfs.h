@@ -405,6 +405,28 @@ bfs_status bfs_masked_spmspv(bfs_graph *g, uint32_t semiring, const int32_t *x_i
                              void *hip_stream);
 
 /*
+ * One search from `source`, like bfs_run with BFS_VARIANT_PUSH and the host
+ * loop, for callers that cannot allocate memory: code running under graph
+ * capture or inside tight serving loops, and harnesses that forbid
+ * allocation.  It takes no workspace and allocates nothing: the search state
+ * lives in the library's own device array of 4 MiB, one per GPU, held from
+ * library load until the process ends.  level and parent are device arrays of
+ * n int32 (caller-owned); the results equal bfs_run's bit for bit.
+ * Limit: graphs of at most 2^22 vertices (the sliced push); anything larger is
+ * refused with BFS_EINVAL, as is a search that would need more than the 4 MiB.
+ * Every call on a GPU shares that GPU's array and leaves the last call's
+ * contents in it (each call's init kernel clears what must start empty), so
+ * calls that overlap on one GPU - from several host threads or streams at
+ * once - race and must not be made.  levels_per_sync: levels launched between
+ * two reads of the progress word (0 = 4, at most 4096).  The call waits for
+ * hip_stream.
+ * Errors: BFS_EINVAL (NULL graph or output, too large, bad levels_per_sync),
+ * BFS_ERANGE (source), BFS_EHIP.
+ */
+bfs_status bfs_run_static(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
+                          uint32_t levels_per_sync, void *hip_stream);
+
+/*
  * Re-cut the sliced push's bitmap slices to at most max_words 32-bit words
  * each (a multiple of 4 in [4, 32768]; the default cut uses 32768, i.e.
  * 128 KiB of LDS per workgroup).  Smaller slices mean more slices (at most 4)

@@ -18,7 +18,7 @@ import numpy as np
 from . import _lib
 from ._lib import BfsError, LOOPS, VARIANTS, VARIANT_NAMES, LevelRecord, RunOptions
 
-__all__ = ["Graph", "bfs", "bfs_batch", "bfs_batch_vm", "batch_vm_workspace_size", "bfs_roots",
+__all__ = ["Graph", "bfs", "bfs_static", "bfs_batch", "bfs_batch_vm", "batch_vm_workspace_size", "bfs_roots",
            "bfs_compare", "compare_workspace_size", "masked_spmspv",
            "spmspv_workspace_size", "BfsError", "VARIANTS", "LOOPS",
            "Workspace", "make_options"]
@@ -193,6 +193,21 @@ def bfs(g: Graph, source: int, variant="push", loop="host", level=None, parent=N
         info["kernel_us"] = o.kernel_us
         if trace:
             info["trace"] = trace_dicts(o, recs)
+    return level, parent
+
+
+def bfs_static(g: Graph, source: int, level=None, parent=None, levels_per_sync: int = 0, stream=None):
+    """One plain-push search that allocates nothing on the library side (its
+    state lives in the library's own per-GPU array; graphs of at most 2^22
+    vertices).  Returns (level, parent); waits for the stream."""
+    t = _torch()
+    if level is None:
+        level = t.empty(g.n, dtype=t.int32, device="cuda")
+    if parent is None:
+        parent = t.empty(g.n, dtype=t.int32, device="cuda")
+    _lib.check(_lib.lib().bfs_run_static(g.handle, int(source), ctypes.c_void_p(level.data_ptr()),
+                                         ctypes.c_void_p(parent.data_ptr()), int(levels_per_sync),
+                                         _stream_handle(stream)))
     return level, parent
 
 

@@ -111,6 +111,8 @@ def _optional(L):
     L.bfs_masked_spmspv.restype = i32
     L.bfs_graph_set_slice_words.argtypes = [vp, u32]
     L.bfs_graph_set_slice_words.restype = i32
+    L.bfs_run_static.argtypes = [vp, i32, vp, vp, u32, vp]
+    L.bfs_run_static.restype = i32
 
 
 def check(status: int) -> None:

@@ -1367,3 +1367,42 @@ extern "C" bfs_status bfs_graph_set_slice_words(bfs_graph *g, uint32_t max_words
     g->gcache.valid = false;                  // captured launches hold the old slice parameters
     return BFS_OK;
 }
+
+// ---------------------------------------------------------------------------
+// One search that allocates nothing: the sliced push on the library's
+// file-scope scratch array
+// ---------------------------------------------------------------------------
+
+extern "C" bfs_status bfs_run_static(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
+                                     uint32_t levels_per_sync, void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (!level || !parent) return fail(BFS_EINVAL, "level/parent is NULL");
+    if (source < 0 || source >= g->n) return fail(BFS_ERANGE, "source %d outside [0, %d)", source, g->n);
+    if (levels_per_sync > 4096) return fail(BFS_EINVAL, "levels_per_sync %u above 4096", levels_per_sync);
+    if (g->sl_S == 0)
+        return fail(BFS_EINVAL, "n = %d: the allocation-free search serves graphs of at most %u vertices",
+                    g->n, kSlMaxSlices * kSlMaxSliceWords * 32u);
+    const SlLayout L = sl_layout(g->sl_S * g->sl_sw);
+    const size_t need = L.total + 256;                    // + the progress words
+    if (need > kStaticScratchBytes)
+        return fail(BFS_EINVAL, "the search needs %zu bytes of scratch; the library's array holds %zu",
+                    need, kStaticScratchBytes);
+    void *base = nullptr;
+    HIP_TRY(static_scratch(&base));
+    hipStream_t s = (hipStream_t)hip_stream;
+    SlParams P = make_sl_params(g, level, parent, base, false);
+    uint32_t *status = (uint32_t *)((char *)base + L.total);
+    P.host_status = status;                             // device words here, read back by copy
+    HIP_TRY(launch_sl_init(P, 1, nullptr, source, s));
+    const uint32_t grid = sl_grid(g);
+    const uint32_t per = levels_per_sync ? levels_per_sync : 4u;
+    for (uint64_t issued = 0;; issued += per) {
+        if (issued > (uint64_t)g->n + 2) return fail(BFS_EHIP, "level loop did not terminate");
+        for (uint32_t l = 0; l < per; ++l) HIP_TRY(launch_sl_level(P, grid, s));
+        uint32_t prog[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(prog, status, sizeof prog, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (prog[1] == 0) break;                        // the last level found nothing
+    }
+    return BFS_OK;
+}

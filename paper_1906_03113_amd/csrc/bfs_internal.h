@@ -159,6 +159,11 @@ struct SlLayout {
     size_t state, vb0, vb1, c0, c1, c2, c3, trace, total;
 };
 SlLayout sl_layout(uint32_t words);
+// The file-scope scratch array behind bfs_run_static (bfs_static.hip): its
+// size, and this device's address of it (looked up on the device's first call).
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+hipError_t static_scratch(void **out);
+
 hipError_t launch_sl_init(const SlParams &p, int32_t nroots, const int32_t *roots_dev,
                           int32_t single_root, hipStream_t s);
 hipError_t launch_sl_level(const SlParams &p, uint32_t grid, hipStream_t s);
