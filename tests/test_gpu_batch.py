@@ -6,7 +6,7 @@ import pytest
 
 import graphgen
 import oracle
-from tests.gpu_common import assert_same, need_gpu, say
+from tests.gpu_common import assert_same, check_all, compare_all, need_gpu, oracle_all, say
 
 pytestmark = pytest.mark.gpu
 
@@ -133,14 +133,14 @@ def test_ms_pull_shift_never_changes_results(P, name):
     G = P.Graph.from_graphgen(g)
     cand = np.nonzero(g.out_degree() > 0)[0]
     src = [int(s) for s in np.random.default_rng(53).choice(cand, size=70, replace=False)]
+    want = oracle_all(g, src)
     for sh in (1, 9, 31):
         say(f"[batch] {name} pull shift {sh}")
         lv, pa = P.bfs_batch(G, src, variant="heuristic", ms_pull_shift=sh)
         vl, vp = P.bfs_batch_vm(G, src, variant="heuristic", ms_pull_shift=sh)
         torch.cuda.synchronize()
-        for q in (0, 33, 69):
-            assert_same(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/sh{sh}/q{q}")
-        assert torch.equal(vl[:, :70], torch.stack(lv, 1)) and torch.equal(vp[:, :70], torch.stack(pa, 1))
+        compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/sh{sh}")
+        compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"{name}/sh{sh}/vm")
     with pytest.raises(P.BfsError):
         P.bfs_batch_vm(G, src, variant="heuristic", ms_pull_shift=32)
 
@@ -190,6 +190,31 @@ def test_long_rows_split_across_launches(P, name, grid_blocks):
     lv, pa = P.bfs_batch(G, src, variant="pull", grid_blocks=grid_blocks)
     vl, vp = P.bfs_batch_vm(G, src, variant="pull", grid_blocks=grid_blocks)
     torch.cuda.synchronize()
-    for q in (0, 35, 69):
-        assert_same(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/q{q}")
-    assert torch.equal(vl[:, :70], torch.stack(lv, 1)) and torch.equal(vp[:, :70], torch.stack(pa, 1))
+    check_all(g, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/split")
+    check_all(g, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"{name}/split/vm")
+
+
+def test_self_loops_multi_source(P):
+    """Self-loops at every vertex (the sources included), duplicate entries:
+    every multi-source query, both layouts and every direction policy, equals
+    the oracle's search of the clean graph."""
+    import torch
+    clean = graphgen.rmat(12, 8, 81)
+    rows = []
+    for v in range(clean.n):
+        r = list(clean.idx[clean.ptr[v]:clean.ptr[v + 1]])
+        rows.append(sorted(r + r[: len(r) // 4] + [v]))
+    ptr = np.zeros(clean.n + 1, np.int32)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([x for r in rows for x in r], np.int32)
+    G = P.Graph.from_csr(clean.n, ptr, idx)
+    cand = np.nonzero(clean.out_degree() > 0)[0]
+    src = [int(s) for s in np.random.default_rng(82).choice(cand, size=70, replace=False)]
+    want = oracle_all(clean, src)
+    for variant in ("push", "pull", "heuristic"):
+        say(f"[batch] self-loops at every vertex, {variant}")
+        lv, pa = P.bfs_batch(G, src, variant=variant)
+        vl, vp = P.bfs_batch_vm(G, src, variant=variant)
+        torch.cuda.synchronize()
+        compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"loops/{variant}")
+        compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"loops/{variant}/vm")

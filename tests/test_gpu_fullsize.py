@@ -10,7 +10,7 @@ import pytest
 import graphgen
 import oracle
 from oracle import certify
-from tests.gpu_common import need_gpu, run_gpu, say
+from tests.gpu_common import check_all, compare_all, need_gpu, oracle_all, run_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -38,40 +38,56 @@ def test_rmat22():
             _check(g, s, run_gpu(P, G, s, **kw), f"rmat22/{s}/{kw.get('variant')}", cert=(i == 0 and kw["variant"] == "push"))
 
 
-def test_rmat22_batch_of_64():
+def test_rmat22_plain_push_every_source():
+    """The plain push as bench.py times it (the sliced form, host loop), from
+    every one of the 64 sources, and the list form from the first 8: whole
+    arrays against the oracle."""
     P = need_gpu()
     import torch
     g = graphgen.workload("rmat22")
     G = P.Graph.from_graphgen(g)
     src = [int(s) for s in graphgen.pick_sources(g, 64, 22)]
-    say("[full] rmat22 multi-source x64")
-    lv, pa = P.bfs_batch(G, src, variant="heuristic")
-    torch.cuda.synchronize()
-    for q in (0, 17, 63):                     # sampled queries, whole arrays
-        _check(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"rmat22 batch q{q}")
-    # the vertex-major form bench.py times beside it: sampled columns against
-    # the oracle, every column against the per-source arrays checked above
-    say("[full] rmat22 multi-source x64, vertex-major results")
-    vl, vp = P.bfs_batch_vm(G, src, variant="heuristic")
-    torch.cuda.synchronize()
-    for q in (5, 40):
-        _check(g, src[q], (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"rmat22 vm q{q}")
-    assert torch.equal(vl, torch.stack(lv, 1)) and torch.equal(vp, torch.stack(pa, 1))
-    say("[full] rmat22 multi-source x64, vertex-major results, push every level")
-    vl, vp = P.bfs_batch_vm(G, src, variant="push", level=vl, parent=vp)
-    torch.cuda.synchronize()
-    assert torch.equal(vl, torch.stack(lv, 1)) and torch.equal(vp, torch.stack(pa, 1))
-    # the pull thresholds bench.py picks between (n >> 9, n >> 11: level 1
-    # then runs as a pull over the union-frontier bitmap), both layouts
-    ref_l, ref_p = torch.stack(lv, 1), torch.stack(pa, 1)
-    for sh in (9, 11):
-        say(f"[full] rmat22 multi-source x64, pull shift {sh}")
-        vl, vp = P.bfs_batch_vm(G, src, variant="heuristic", ms_pull_shift=sh, level=vl, parent=vp)
-        l2, p2 = P.bfs_batch(G, src, variant="heuristic", ms_pull_shift=sh)
+    say("[full] rmat22 oracle from the 64 sources (host threads)")
+    want = oracle_all(g, src)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ws = P.Workspace(G.workspace_size(1))
+
+    def run(q, impl):
+        P.bfs(G, src[q], level=lv, parent=pa, workspace=ws, variant="push", push_impl=impl)
         torch.cuda.synchronize()
-        assert torch.equal(vl, ref_l) and torch.equal(vp, ref_p)
-        assert torch.equal(torch.stack(l2, 1), ref_l) and torch.equal(torch.stack(p2, 1), ref_p)
-        del l2, p2
+        return lv.cpu().numpy(), pa.cpu().numpy()
+
+    say("[full] rmat22 sliced push x64")
+    compare_all(want, src, lambda q: run(q, "sliced"), "rmat22 sliced push")
+    say("[full] rmat22 list push x8")
+    compare_all(want[:8], src[:8], lambda q: run(q, "list"), "rmat22 list push")
+
+
+def test_rmat22_batch_of_64():
+    """All 64 sources in one call, every query against the oracle: per-source
+    and vertex-major results, every direction threshold bench.py chooses
+    between (pull from n >> 5, 9, 11, 13 on) and push on every level."""
+    P = need_gpu()
+    import torch
+    g = graphgen.workload("rmat22")
+    G = P.Graph.from_graphgen(g)
+    src = [int(s) for s in graphgen.pick_sources(g, 64, 22)]
+    lv = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in src]
+    pa = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in src]
+    vl = torch.empty((g.n, 64), dtype=torch.int32, device="cuda")
+    vp = torch.empty((g.n, 64), dtype=torch.int32, device="cuda")
+    say("[full] rmat22 oracle from the 64 sources (host threads)")
+    want = oracle_all(g, src)
+    for kw in (dict(variant="heuristic", ms_pull_shift=5), dict(variant="heuristic", ms_pull_shift=9),
+               dict(variant="heuristic", ms_pull_shift=11), dict(variant="heuristic", ms_pull_shift=13),
+               dict(variant="push")):
+        say(f"[full] rmat22 multi-source x64 {kw}")
+        P.bfs_batch(G, src, levels=lv, parents=pa, **kw)
+        P.bfs_batch_vm(G, src, level=vl, parent=vp, **kw)
+        torch.cuda.synchronize()
+        compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"rmat22 batch {kw}")
+        compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"rmat22 vm {kw}")
 
 
 def test_grid4096():
@@ -153,7 +169,7 @@ def test_masked_spmspv_full_size():
 
 def test_rmat20d_batch_of_256():
     """256 sources in one call on directed R-MAT s20 (4 mask words per vertex),
-    the launch the batching measurement times; sampled queries, whole arrays."""
+    the launch the batching measurement times; every query against the oracle."""
     P = need_gpu()
     import torch
     g = graphgen.workload("rmat20d")
@@ -162,8 +178,7 @@ def test_rmat20d_batch_of_256():
     say("[full] rmat20d multi-source x256")
     lv, pa = P.bfs_batch(G, src, variant="heuristic")
     torch.cuda.synchronize()
-    for q in (0, 63, 64, 130, 255):
-        _check(g, src[q], (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"rmat20d batch q{q}")
+    check_all(g, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), "rmat20d batch")
 
 
 def test_er_pack_of_64_graphs():

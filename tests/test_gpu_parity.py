@@ -118,8 +118,9 @@ def test_edge_cases(P):
     idx = np.array([x for r in rows for x in r], np.int32)
     G = P.Graph.from_csr(clean.n, ptr, idx)
     for v in VARIANTS:
-        say(f"[parity] messy variant={v}")
-        assert_same(clean, 5, run_gpu(P, G, 5, variant=v), f"messy/{v}")
+        for s in (5, 0, 7, 1995):              # 0, 7 and 1995 carry a self-loop
+            say(f"[parity] messy s={s} variant={v}")
+            assert_same(clean, s, run_gpu(P, G, s, variant=v), f"messy/{s}/{v}")
     # directed, CSC built by the library vs given
     gd = graphgen.rmat(12, 8, 4, directed=True)
     G1 = P.Graph.from_csr(gd.n, gd.ptr, gd.idx, directed=True)
