@@ -8,9 +8,11 @@ JSON line on stdout; progress goes to stderr.
 
 value = GTEPS = sum over the step's searches of m_c (edges of the reached
 component, each undirected edge once) / wall time of the step.
-roofline = the level kernel (k_level): algorithmic bytes per launch / mean
-launch duration, the durations from HIP events around every launch in the
-timed region.
+roofline = the plain push's kernels: the algorithmic bytes of a search (the
+method's column reads, frontier traffic and outputs, plus the initialisation of
+the outputs and bitmaps) / the device time of its init and level launches, the
+durations from HIP events around every launch of one extra, separately timed
+step.
 cpu_baseline = the CPU oracle (queue BFS + min-parent pass, one thread pinned
 to one core) timed on a bounded sample of the same searches.
 """
@@ -145,7 +147,7 @@ def main():
         for s in sources:
             info = {} if info_acc is not None else None
             P.bfs(G, int(s), level=level, parent=parent, workspace=ws, info=info,
-                  time_kernels=timek, **kw)
+                  time_kernels=info_acc is not None, **kw)
             if info_acc is not None:
                 info_acc.append(info)
 
@@ -162,42 +164,55 @@ def main():
         step()
         torch.cuda.synchronize()
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
-    infos = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
-        step(infos)
+        step()
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     dt = (t_end - t_start) / args.steps
     gteps = total_m / dt / 1e9
     log(f"[bench] {args.steps} steps: {dt * 1e3:.3f} ms/step, {gteps:.2f} GTEPS")
 
+    # the same step once more with every launch bracketed by HIP events (on
+    # the stream the kernels run on): the level kernel's launch durations and
+    # the init launch's, for the roofline
     roofline = None
-    if timek and infos:
+    if timek:
+        infos = []
+        step(infos)
+        torch.cuda.synchronize()
         launches = sum(i["launches"] for i in infos)
-        kern_us = sum(i["kernel_us"] for i in infos)
-        # algorithmic bytes of the level kernel per search (the method's own traffic):
-        # 4 B per entry of every reached column, 8 B for its two row pointers,
-        # 8 B to write and read it in the frontier list, 8 B for its level and parent
-        b_search = [4 * nz + 24 * nc for nz, nc in zip(nnz_c, n_c)]
-        bytes_total = float(sum(b_search)) * args.steps
-        avg_bytes = bytes_total / launches
-        avg_us = kern_us / launches
-        ach = avg_bytes / (avg_us * 1e-6) / 1e9
-        traffic = measured_traffic() if (args.workload == "rmat22" and args.variant == "push") else None
+        level_us = sum(i["kernel_us"] for i in infos)
+        init_us = sum(i["init_us"] for i in infos)
+        nsearch = len(infos)
+        # algorithmic bytes of one search (the method's own traffic): 4 B per
+        # entry of every reached column, 8 B for its two row pointers, 8 B to
+        # write and read it as a frontier entry, 8 B for its level and parent,
+        # and the initialisation of both outputs (8 n) and of two bitmaps (n / 4)
+        b_search = [4 * nz + 24 * nc + 8 * g.n + g.n // 4 for nz, nc in zip(nnz_c, n_c)]
+        bytes_total = float(sum(b_search))
+        kern_us = level_us + init_us
+        ach = bytes_total / (kern_us * 1e-6) / 1e9
+        sliced = args.variant == "push" and g.n <= 4 * 32768 * 32 and args.loop in ("host", "graph")
+        kname = "k_sl_level" if sliced else "k_level"
+        traffic = measured_traffic() if (args.workload == "rmat22" and sliced) else None
+        per_search = [i["kernel_us"] + i["init_us"] for i in infos]
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "k_level", "launches_per_search": round(launches / (len(sources) * args.steps), 2),
-                    "mean_launch_us": round(avg_us, 3),
-                    "algorithmic_bytes_per_launch": round(avg_bytes),
-                    "kernel_us_per_search": round(kern_us / (len(sources) * args.steps), 2),
-                    "median_kernel_us_per_search": round(float(np.median([i["kernel_us"] for i in infos])), 2),
-                    # the same bytes over the whole timed step (init, host round trips included)
-                    "end_to_end_GBps": round(bytes_total / (dt * args.steps) / 1e9, 1),
-                    "end_to_end_frac": round(bytes_total / (dt * args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
-        log(f"[bench] k_level: {launches} launches, mean {avg_us:.2f} us, {ach:.1f} GB/s algorithmic "
-            f"({ach / HBM_PEAK_GBS * 100:.1f}% of 8 TB/s)")
+                    "kernel": kname, "init_kernel": "k_sl_init" if sliced else "k_init",
+                    "algorithmic_bytes_per_search": round(bytes_total / nsearch),
+                    "kernel_us_per_search": round(kern_us / nsearch, 2),
+                    "level_kernel_us_per_search": round(level_us / nsearch, 2),
+                    "init_us_per_search": round(init_us / nsearch, 2),
+                    "median_kernel_us_per_search": round(float(np.median(per_search)), 2),
+                    "launches_per_search": round(launches / nsearch, 2),
+                    "mean_launch_us": round(level_us / max(launches, 1), 3),
+                    # the same bytes over the whole untimed step (host round trips included)
+                    "end_to_end_GBps": round(bytes_total / dt / 1e9, 1),
+                    "end_to_end_frac": round(bytes_total / dt / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"[bench] {kname}: {launches} launches, {kern_us / nsearch:.1f} us per search "
+            f"(init {init_us / nsearch:.1f}), {ach:.1f} GB/s algorithmic ({ach / HBM_PEAK_GBS * 100:.1f}% of 8 TB/s)")
 
     # per-level view of the first search (stderr only)
     info = {}

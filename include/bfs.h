@@ -114,6 +114,8 @@ typedef struct bfs_run_options {
     float kernel_us;           /* out (time_kernels): summed device time of those launches      */
     uint32_t push_impl;        /* BFS_VARIANT_PUSH only: BFS_PUSH_AUTO (0), BFS_PUSH_LIST or
                                   BFS_PUSH_SLICED (see below)                                   */
+    float init_us;             /* out (time_kernels, bfs_run): device time of the search's
+                                  initialisation launch (outputs to -1, bitmaps cleared)        */
 } bfs_run_options;
 
 /*
@@ -194,8 +196,15 @@ bfs_status bfs_run(bfs_graph *g, int32_t source,
  * per vertex (one pass over a column serves every source whose frontier holds
  * it).  opt->variant picks the direction per level: PUSH (default) scatters
  * the frontier masks along out-edges; PULL lets every unsettled vertex gather
- * its in-neighbours' masks in ascending order; HEURISTIC / LEARNED push while
- * the union frontier holds at most n/32 vertices and pull after.  Queries on
+ * its in-neighbours' masks in ascending order; HEURISTIC pushes while the
+ * union frontier holds at most n >> ms_pull_shift vertices and pulls after;
+ * LEARNED asks the selector network (opt->selector) before every level (a
+ * one-wave launch over the level's multi-source features, see
+ * bfs_ms_profile_levels) and runs the argmin of its push and pull outputs,
+ * push when an output is not finite and on every level when opt->selector is
+ * NULL; from level 16 on, a push decision covers the next 8 levels.  With
+ * opt->trace set, record k holds level k's direction (variant 0 push, 1 pull)
+ * and, where the host read it, the union frontier's size.  Queries on
  * different graphs are run one after another on the stream.
  * The result for query q is bit-identical to bfs_run(graphs[q], sources[q]).
  * workspace: bfs_workspace_size(graphs[0], num_queries, 0) bytes when all
@@ -309,6 +318,33 @@ bfs_status bfs_profile_levels(bfs_graph *g, int32_t source, int32_t *level, int3
                               void *workspace, size_t ws_bytes, void *snapshot, size_t snap_bytes,
                               int32_t reps, bfs_level_record *records, uint32_t capacity,
                               uint32_t *count, void *hip_stream);
+
+/* Bytes of the snapshot buffer bfs_ms_profile_levels needs (0 on a bad argument). */
+size_t bfs_ms_profile_snapshot_size(const bfs_graph *g, int32_t num_sources);
+
+/*
+ * Exhaustive per-level timing of the multi-source searches (the training data
+ * of BFS_VARIANT_LEARNED in bfs_run_batch / bfs_run_batch_vm): runs the
+ * searches from `sources` as bfs_run_batch_vm does; before each level it saves
+ * the whole search state (workspace and outputs) into `snapshot`, times that
+ * one level in the push and in the pull direction (best of `reps` runs, each
+ * from the restored state, device time between two events) and advances with
+ * the faster one.  records (host) receives two records per level (variant 0 =
+ * push, 1 = pull; time_us) holding the features the learned direction reads:
+ * frontier = size of the union frontier F_k (vertices in some source's
+ * frontier), frontier_edges = the sum of their out-degrees, unvisited = the
+ * summed union-frontier sizes of levels 0..k, unvisited_edges = num_sources.
+ * *count = records written (at most capacity).  level, parent, workspace: as
+ * for bfs_run_batch_vm (workspace of bfs_batch_vm_workspace_size bytes);
+ * snapshot: device, bfs_ms_profile_snapshot_size bytes, 256-byte aligned;
+ * reps in [1, 1000].  The final level / parent equal bfs_run_batch_vm's.
+ * Errors: BFS_EINVAL, BFS_ERANGE, BFS_EHIP.
+ */
+bfs_status bfs_ms_profile_levels(bfs_graph *g, int32_t num_sources, const int32_t *sources,
+                                 int32_t *level, int32_t *parent, void *workspace, size_t ws_bytes,
+                                 void *snapshot, size_t snap_bytes, int32_t reps,
+                                 bfs_level_record *records, uint32_t capacity, uint32_t *count,
+                                 void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * The comparison searches (Experiments section, Table 2).  Not the method:

@@ -191,6 +191,7 @@ def bfs(g: Graph, source: int, variant="push", loop="host", level=None, parent=N
         info["levels"] = o.levels
         info["launches"] = o.launches
         info["kernel_us"] = o.kernel_us
+        info["init_us"] = o.init_us
         if trace:
             info["trace"] = trace_dicts(o, recs)
     return level, parent
@@ -234,10 +235,20 @@ def bfs_roots(g: Graph, roots: Sequence[int], variant="push", loop="host", level
     return level, parent
 
 
+def _ms_trace(o: RunOptions, recs) -> list:
+    """The multi-source trace: level k's direction and, where the host read it,
+    the union frontier's size (0 elsewhere)."""
+    return [dict(level=recs[r].level, direction=("push", "pull")[recs[r].variant],
+                 frontier=recs[r].frontier) for r in range(o.trace_count)]
+
+
 def bfs_batch(graphs, sources: Sequence[int], variant="push", loop="host", levels=None,
-              parents=None, workspace: Optional[Workspace] = None, stream=None, **kw):
+              parents=None, workspace: Optional[Workspace] = None, stream=None,
+              info: Optional[dict] = None, trace: bool = False, **kw):
     """Many searches in one call: query q = (graphs[q], sources[q]).  `graphs` may be
-    a single Graph (every query on it).  Returns lists of (level, parent) tensors."""
+    a single Graph (every query on it).  Returns lists of (level, parent) tensors.
+    `info`, if given, receives "levels" and, with trace=True (one graph), "trace":
+    each level's direction (see bfs_run_batch)."""
     t = _torch()
     nq = len(sources)
     if isinstance(graphs, Graph):
@@ -254,9 +265,13 @@ def bfs_batch(graphs, sources: Sequence[int], variant="push", loop="host", level
     S = (ctypes.c_int32 * nq)(*[int(s) for s in sources])
     Lp = (ctypes.c_void_p * nq)(*[x.data_ptr() for x in levels])
     Pp = (ctypes.c_void_p * nq)(*[x.data_ptr() for x in parents])
-    o, _ = make_options(variant, loop, **kw)
+    o, recs = make_options(variant, loop, trace_capacity=(max(gr.n for gr in graphs) + 2) if trace else 0, **kw)
     _lib.check(_lib.lib().bfs_run_batch(nq, H, S, Lp, Pp, ctypes.byref(o), workspace.ptr,
                                         workspace.nbytes, _stream_handle(stream)))
+    if info is not None:
+        info["levels"] = int(o.levels)
+        if trace:
+            info["trace"] = _ms_trace(o, recs)
     return levels, parents
 
 
@@ -326,12 +341,12 @@ def batch_vm_workspace_size(g: Graph, num_sources: int) -> int:
 
 def bfs_batch_vm(g: Graph, sources: Sequence[int], variant="heuristic", level=None, parent=None,
                  workspace: Optional[Workspace] = None, stream=None, info: Optional[dict] = None,
-                 **kw):
+                 trace: bool = False, **kw):
     """Many sources on one graph with vertex-major results: returns (level,
     parent) as int32 cuda tensors of shape [n, ld], ld = 64 * ceil(len / 64);
     column q holds source q's arrays (columns past the sources hold -1).
     `info`, if given, receives "levels" (the largest level over the sources
-    plus one)."""
+    plus one) and, with trace=True, "trace" (each level's direction)."""
     t = _torch()
     src = _i32_host(np.asarray(sources))
     ld = 64 * ((len(src) + 63) // 64)
@@ -347,11 +362,13 @@ def bfs_batch_vm(g: Graph, sources: Sequence[int], variant="heuristic", level=No
     need = batch_vm_workspace_size(g, len(src))
     if workspace is None or not workspace.fits(need):
         workspace = Workspace(need)
-    o, _ = make_options(variant, "host", **kw)
+    o, recs = make_options(variant, "host", trace_capacity=(g.n + 2) if trace else 0, **kw)
     _lib.check(_lib.lib().bfs_run_batch_vm(g.handle, len(src), src.ctypes.data_as(ctypes.c_void_p),
                                            ctypes.c_void_p(level.data_ptr()),
                                            ctypes.c_void_p(parent.data_ptr()), ctypes.byref(o),
                                            workspace.ptr, workspace.nbytes, _stream_handle(stream)))
     if info is not None:
         info["levels"] = int(o.levels)
+        if trace:
+            info["trace"] = _ms_trace(o, recs)
     return level, parent

@@ -33,7 +33,8 @@ class RunOptions(ctypes.Structure):
                 ("trace", ctypes.POINTER(LevelRecord)), ("trace_capacity", ctypes.c_uint32),
                 ("time_kernels", ctypes.c_uint32), ("trace_count", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32), ("launches", ctypes.c_uint32),
-                ("kernel_us", ctypes.c_float), ("push_impl", ctypes.c_uint32)]
+                ("kernel_us", ctypes.c_float), ("push_impl", ctypes.c_uint32),
+                ("init_us", ctypes.c_float)]
 
 
 class BfsError(RuntimeError):
@@ -95,6 +96,11 @@ def _optional(L):
     L.bfs_profile_levels.argtypes = [vp, i32, vp, vp, vp, sz, vp, sz, i32,
                                      ctypes.POINTER(LevelRecord), u32, ctypes.POINTER(u32), vp]
     L.bfs_profile_levels.restype = i32
+    L.bfs_ms_profile_snapshot_size.argtypes = [vp, i32]
+    L.bfs_ms_profile_snapshot_size.restype = sz
+    L.bfs_ms_profile_levels.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp, sz, i32,
+                                        ctypes.POINTER(LevelRecord), u32, ctypes.POINTER(u32), vp]
+    L.bfs_ms_profile_levels.restype = i32
     L.bfs_batch_vm_workspace_size.argtypes = [vp, i32]
     L.bfs_batch_vm_workspace_size.restype = sz
     L.bfs_run_batch_vm.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(RunOptions), vp, sz, vp]

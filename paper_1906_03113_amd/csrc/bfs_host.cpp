@@ -61,6 +61,7 @@ struct bfs_graph {
     std::mutex mu;
     GraphExecCache gcache;
     std::vector<hipEvent_t> events;   // pool for per-launch timing
+    hipEvent_t init_ev[2] = {nullptr, nullptr};   // around the init launch (time_kernels)
 };
 
 namespace {
@@ -132,6 +133,8 @@ void free_graph(bfs_graph *g) {
     if (!g) return;
     // teardown: errors here have nowhere to go, the memory is released either way
     for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : g->init_ev)
+        if (e) (void)hipEventDestroy(e);
     if (g->gcache.exec) (void)hipGraphExecDestroy(g->gcache.exec);
     if (g->gcache.graph) (void)hipGraphDestroy(g->gcache.graph);
     if (g->li && g->li != g->lo) (void)hipFree(g->li);
@@ -277,6 +280,7 @@ MsLayout ms_layout(int32_t n, int32_t nq, bool staged) {
     L.f2 = take((size_t)n * 4);
     L.flag = take((size_t)n * 4);
     L.cnt = take(64);
+    L.mstat = take(kMsStatWords * 8);
     L.fbits = take(((size_t)n + 63) / 64 * 8);
     L.slev = staged ? take((size_t)n * W * 64 * 4) : 0;
     L.spar = staged ? take((size_t)n * W * 64 * 4) : 0;
@@ -479,6 +483,28 @@ bfs_status level_loop(bfs_graph *g, const LoopKey &key, uint32_t loop, hipStream
     return BFS_OK;
 }
 
+// Issue a search's init launch(es); with opt->time_kernels, bracket them with
+// the graph's init events and report their device time in opt->init_us.
+template <class Launch>
+bfs_status timed_init(bfs_graph *g, bfs_run_options *opt, hipStream_t s, Launch launch) {
+    const bool tk = opt && opt->time_kernels;
+    if (!tk) {
+        HIP_TRY(launch());
+        return BFS_OK;
+    }
+    std::lock_guard<std::mutex> lock(g->mu);
+    for (hipEvent_t &e : g->init_ev)
+        if (!e) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventRecord(g->init_ev[0], s));
+    HIP_TRY(launch());
+    HIP_TRY(hipEventRecord(g->init_ev[1], s));
+    HIP_TRY(hipEventSynchronize(g->init_ev[1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, g->init_ev[0], g->init_ev[1]));
+    opt->init_us = ms * 1000.f;
+    return BFS_OK;
+}
+
 // Copy the device's per-level records into opt->trace (host), with the
 // launches' device times when they were taken.
 bfs_status read_trace(const DevLevelRec *dtrace, uint32_t levels, const std::vector<float> &times,
@@ -618,7 +644,8 @@ bfs_status run_sliced(bfs_graph *g, int32_t source, int32_t nroots, const int32_
     P.host_status = hs->d;
     hs->h[0] = 0;
     hs->h[1] = 1;
-    HIP_TRY(launch_sl_init(P, nroots, roots_dev, source, s));
+    st = timed_init(g, opt, s, [&]() { return launch_sl_init(P, nroots, roots_dev, source, s); });
+    if (st != BFS_OK) return st;
     const uint32_t grid = sl_grid(g);
     LoopKey key;
     key.kind = 1;
@@ -804,7 +831,8 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
         return run_sliced(g, source, 1, nullptr, level, parent, c, workspace, s, opt);
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
-    HIP_TRY(launch_init(P, 1, nullptr, source, s));
+    st = timed_init(g, opt, s, [&]() { return launch_init(P, 1, nullptr, source, s); });
+    if (st != BFS_OK) return st;
     uint32_t levels = 0;
     st = run_levels(g, P, c, s, levels, opt);
     if (st != BFS_OK) return st;
@@ -870,21 +898,29 @@ constexpr uint32_t kMsFbitsShift = 6;
 constexpr uint32_t kMsGroupFrom = 16;
 constexpr uint32_t kMsGroupLevels = 8;
 
-// All queries on one graph: the multi-source kernels.
-// level / parent: per-source arrays (staged results, transposed at the end),
-// or with vm_level / vm_parent set, the caller's vertex-major arrays, written
-// in place.
-static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sources,
-                                   int32_t *const *level, int32_t *const *parent,
-                                   bfs_run_options *opt, void *workspace, hipStream_t s,
-                                   int32_t *vm_level = nullptr, int32_t *vm_parent = nullptr) {
-    const uint32_t pull_shift = (opt && opt->ms_pull_shift) ? opt->ms_pull_shift : 5u;
-    if (pull_shift > 31) return fail(BFS_EINVAL, "ms_pull_shift %u above 31", pull_shift);
-    if (opt && opt->variant > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", opt->variant);
+// A multi-source level's record when tracing: the direction it ran in and,
+// where the host read it before the level, the union frontier's size.
+static void ms_note(bfs_run_options *opt, uint32_t k, int32_t variant, uint32_t frontier) {
+    if (!opt || !opt->trace || k >= opt->trace_capacity) return;
+    bfs_level_record &r = opt->trace[k];
+    r = bfs_level_record{};
+    r.level = (int32_t)k;
+    r.variant = variant;
+    r.frontier = frontier;
+}
+
+// The multi-source parameter block over `workspace` (layout ms_layout), the
+// per-source output pointers and the sources uploaded on s.  level / parent:
+// per-source arrays (staged results), or with vm_level / vm_parent set, the
+// caller's vertex-major arrays, written in place.
+static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
+                             int32_t *const *level, int32_t *const *parent, void *workspace,
+                             hipStream_t s, int32_t *vm_level, int32_t *vm_parent, uint32_t grid,
+                             MsLevel &p, HostSlot *&hs) {
     const bool vm = vm_level != nullptr;
     const MsLayout L = ms_layout(g->n, nq, !vm);
     char *b = (char *)workspace;
-    MsLevel p{};
+    p = MsLevel{};
     p.n = g->n;
     p.W = (uint32_t)(((size_t)nq + 63) / 64);
     p.nq = (uint32_t)nq;
@@ -901,6 +937,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     p.fq[2] = (int32_t *)(b + L.f2);
     p.flag = (uint32_t *)(b + L.flag);
     p.cnt = (uint32_t *)(b + L.cnt);
+    p.mstat = (unsigned long long *)(b + L.mstat);
     p.fbits = (unsigned long long *)(b + L.fbits);
     p.wide_steps = ((uint64_t)g->nnz < 8ull * (uint64_t)g->n) ? 1u : 0u;
     p.lo = g->lo;
@@ -916,7 +953,6 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     p.level = (int32_t *const *)(b + L.lptr);
     p.parent = (int32_t *const *)(b + L.pptr);
     p.sources = (const int32_t *)(b + L.src);
-    HostSlot *hs = nullptr;
     bfs_status st = host_slot(hs);
     if (st != BFS_OK) return st;
     p.host_status = hs->d;
@@ -925,38 +961,84 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
         HIP_TRY(hipMemcpyAsync(b + L.pptr, parent, (size_t)nq * 8, hipMemcpyHostToDevice, s));
     }
     HIP_TRY(hipMemcpyAsync(b + L.src, sources, (size_t)nq * 4, hipMemcpyHostToDevice, s));
-    uint32_t grid = (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
     // the long rows' later chunks in a launch of their own once they outnumber
     // the grid's waves twice over (then skipping those a row's first chunk
     // has settled saves whole rounds; below that the extra launch costs more)
     p.long_split = ((uint64_t)(g->nli_chunks - g->nli) > 2ull * grid * 4u) ? 1u : 0u;
+    return BFS_OK;
+}
+
+// One multi-source level k in the pull form (frontier = the union frontier's
+// size, which decides whether the pull tests the frontier bitmap first) or in
+// the push form.
+static hipError_t ms_level(MsLevel &p, uint32_t k, bool pull, uint32_t frontier, uint32_t grid,
+                           hipStream_t s) {
+    hipError_t e;
+    if (pull) {
+        // a sparse union frontier: the pull tests its bitmap before each
+        // mask gather (most in-neighbours are then skipped on chip)
+        p.use_fbits = ((uint64_t)frontier << kMsFbitsShift) <= (uint64_t)p.n ? 1u : 0u;
+        if (p.use_fbits && (e = launch_ms(p, 8, k, grid, s)) != hipSuccess) return e;
+        if ((e = launch_ms(p, 4, k, grid, s)) != hipSuccess) return e;
+        if (p.long_split && (e = launch_ms(p, 9, k, grid, s)) != hipSuccess) return e;
+        if ((e = launch_ms(p, 6, k, grid, s)) != hipSuccess) return e;
+        return launch_ms(p, 5, k, grid, s);
+    }
+    if ((e = launch_ms(p, 2, k, grid, s)) != hipSuccess) return e;
+    return launch_ms(p, 3, k, grid, s);
+}
+
+static uint32_t ms_grid(const bfs_graph *g, const bfs_run_options *opt) {
+    return (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
+}
+
+// All queries on one graph: the multi-source kernels (outputs as ms_prepare).
+static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sources,
+                                   int32_t *const *level, int32_t *const *parent,
+                                   bfs_run_options *opt, void *workspace, hipStream_t s,
+                                   int32_t *vm_level = nullptr, int32_t *vm_parent = nullptr) {
+    const uint32_t pull_shift = (opt && opt->ms_pull_shift) ? opt->ms_pull_shift : 5u;
+    if (pull_shift > 31) return fail(BFS_EINVAL, "ms_pull_shift %u above 31", pull_shift);
+    if (opt && opt->variant > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", opt->variant);
+    const uint32_t grid = ms_grid(g, opt);
+    if (grid == 0 || grid > 65535) return fail(BFS_EINVAL, "grid_blocks %u outside [1, 65535]", grid);
+    MsLevel p;
+    HostSlot *hs = nullptr;
+    bfs_status st = ms_prepare(g, nq, sources, level, parent, workspace, s, vm_level, vm_parent, grid, p, hs);
+    if (st != BFS_OK) return st;
+    // direction per level: HEURISTIC pushes while the union frontier is
+    // small and pulls (no atomics) once it holds more than n >> pull_shift
+    // vertices; LEARNED takes the network's argmin over push and pull, which
+    // a one-wave launch after each level's list leaves in the progress slot
+    // (push on every level without a network); PUSH / PULL as forced
+    const uint32_t pol = opt ? opt->variant : kPush;
+    const bool learned = pol == kLearned && opt->selector != nullptr;
+    p.mlp = learned ? opt->selector : nullptr;
     HIP_TRY(launch_ms(p, 0, 0, grid, s));
     HIP_TRY(launch_ms(p, 1, 0, grid, s));
-    // direction per level: push while the union frontier is small, pull (no
-    // atomics) once it holds more than n >> pull_shift vertices (or as forced)
-    const uint32_t pol = opt ? opt->variant : kPush;
-    uint32_t k = 0, frontier = 1;
+    uint32_t k = 0, frontier = 1, dir = 0;
+    if (learned) {
+        HIP_TRY(launch_ms(p, 10, 0, grid, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        dir = hs->h[2];
+    }
     for (;; ++k) {
         if ((uint64_t)k > (uint64_t)g->n + 2) return fail(BFS_EHIP, "multi-source loop did not terminate");
-        const bool pull = (pol == kPull) || ((pol == kHeuristic || pol == kLearned) &&
-                                             ((uint64_t)frontier << pull_shift) > (uint64_t)g->n);
+        const bool pull = learned ? dir == 1u
+                                  : (pol == kPull) || (pol == kHeuristic &&
+                                                       ((uint64_t)frontier << pull_shift) > (uint64_t)g->n);
         if (pull) {
-            // a sparse union frontier: the pull tests its bitmap before each
-            // mask gather (most in-neighbours are then skipped on chip)
-            p.use_fbits = ((uint64_t)frontier << kMsFbitsShift) <= (uint64_t)g->n ? 1u : 0u;
-            if (p.use_fbits) HIP_TRY(launch_ms(p, 8, k, grid, s));
-            HIP_TRY(launch_ms(p, 4, k, grid, s));
-            if (p.long_split) HIP_TRY(launch_ms(p, 9, k, grid, s));   // long rows' later chunks
-            HIP_TRY(launch_ms(p, 6, k, grid, s));
-            HIP_TRY(launch_ms(p, 5, k, grid, s));
+            HIP_TRY(ms_level(p, k, true, frontier, grid, s));
+            ms_note(opt, k, 1, frontier);
         } else {
             const uint32_t group = (k >= kMsGroupFrom) ? kMsGroupLevels : 1u;
             for (uint32_t i = 0; i < group; ++i) {
-                HIP_TRY(launch_ms(p, 2, k + i, grid, s));
-                HIP_TRY(launch_ms(p, 3, k + i, grid, s));
+                HIP_TRY(ms_level(p, k + i, false, 0, grid, s));
+                ms_note(opt, k + i, 0, i == 0 ? frontier : 0u);
             }
             k += group - 1;
         }
+        if (learned) HIP_TRY(launch_ms(p, 10, k + 1, grid, s));   // the next level's direction
         bool done = false;
         uint32_t lv = 0;
         st = wait_progress(hs, s, done, lv);
@@ -966,11 +1048,12 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
             break;
         }
         frontier = hs->h[1];
+        dir = hs->h[2];
     }
-    if (!vm) HIP_TRY(launch_ms(p, 7, k, grid, s));      // staged results -> per-source arrays
+    if (vm_level == nullptr) HIP_TRY(launch_ms(p, 7, k, grid, s));   // staged results -> per-source arrays
     if (opt) {
         opt->levels = k + 1;
-        opt->trace_count = 0;
+        opt->trace_count = opt->trace ? std::min<uint32_t>(k + 1, opt->trace_capacity) : 0u;
     }
     return BFS_OK;
 }
@@ -1306,6 +1389,129 @@ extern "C" bfs_status bfs_run_batch_vm(bfs_graph *g, int32_t num_sources, const 
     if (opt && opt->variant > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", opt->variant);
     return run_multi_source(g, num_sources, sources, nullptr, nullptr, opt, workspace,
                             (hipStream_t)hip_stream, level, parent);
+}
+
+// ---------------------------------------------------------------------------
+// Exhaustive per-level timing of the multi-source directions
+// ---------------------------------------------------------------------------
+
+static size_t ms_vm_bytes(const bfs_graph *g, int32_t nq) {
+    const size_t ld = 64 * (((size_t)nq + 63) / 64);
+    return (size_t)g->n * ld * 4;
+}
+
+extern "C" size_t bfs_ms_profile_snapshot_size(const bfs_graph *g, int32_t num_sources) {
+    if (!g || num_sources <= 0) return 0;
+    return align256(ms_layout(g->n, num_sources, false).total) + 2 * align256(ms_vm_bytes(g, num_sources));
+}
+
+extern "C" bfs_status bfs_ms_profile_levels(bfs_graph *g, int32_t num_sources, const int32_t *sources,
+                                            int32_t *level, int32_t *parent, void *workspace,
+                                            size_t ws_bytes, void *snapshot, size_t snap_bytes,
+                                            int32_t reps, bfs_level_record *records, uint32_t capacity,
+                                            uint32_t *count, void *hip_stream) {
+    if (!g) return fail(BFS_EINVAL, "graph is NULL");
+    if (num_sources <= 0) return fail(BFS_EINVAL, "num_sources = %d", num_sources);
+    if (!sources || !level || !parent || !workspace || !snapshot || !count)
+        return fail(BFS_EINVAL, "NULL argument");
+    if (capacity > 0 && !records) return fail(BFS_EINVAL, "records is NULL");
+    if (((uintptr_t)workspace & 255) != 0 || ((uintptr_t)snapshot & 255) != 0)
+        return fail(BFS_EINVAL, "workspace and snapshot must be 256-byte aligned");
+    if (((uintptr_t)level & 15) != 0 || ((uintptr_t)parent & 15) != 0)
+        return fail(BFS_EINVAL, "level / parent must be 16-byte aligned");
+    if (reps < 1 || reps > 1000) return fail(BFS_EINVAL, "reps %d outside [1, 1000]", reps);
+    for (int32_t q = 0; q < num_sources; ++q)
+        if (sources[q] < 0 || sources[q] >= g->n)
+            return fail(BFS_ERANGE, "source %d (%d) outside [0, %d)", q, sources[q], g->n);
+    const size_t wsb = ms_layout(g->n, num_sources, false).total;
+    if (ws_bytes < wsb) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, wsb);
+    const size_t snap_need = bfs_ms_profile_snapshot_size(g, num_sources);
+    if (snap_bytes < snap_need) return fail(BFS_EINVAL, "snapshot has %zu bytes, needs %zu", snap_bytes, snap_need);
+    *count = 0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const uint32_t grid = ms_grid(g, nullptr);
+    MsLevel p;
+    HostSlot *hs = nullptr;
+    bfs_status st = ms_prepare(g, num_sources, sources, nullptr, nullptr, workspace, s, level, parent,
+                               grid, p, hs);
+    if (st != BFS_OK) return st;
+    const size_t outb = ms_vm_bytes(g, num_sources);
+    char *snap = (char *)snapshot;
+    char *snap_lv = snap + align256(wsb), *snap_pa = snap_lv + align256(outb);
+    auto copy_state = [&](bool save) -> hipError_t {
+        hipError_t e;
+        if ((e = hipMemcpyAsync(save ? snap : (char *)workspace, save ? (char *)workspace : snap, wsb,
+                                hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(save ? snap_lv : (char *)level, save ? (char *)level : snap_lv, outb,
+                                hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+        return hipMemcpyAsync(save ? snap_pa : (char *)parent, save ? (char *)parent : snap_pa, outb,
+                              hipMemcpyDeviceToDevice, s);
+    };
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto done_events = [&]() {
+        for (hipEvent_t &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    HIP_TRY(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        done_events();
+        return fail(BFS_EHIP, "hipEventCreate failed");
+    }
+    bfs_status result = BFS_OK;
+    auto run = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = launch_ms(p, 0, 0, grid, s)) != hipSuccess) return e;
+        if ((e = launch_ms(p, 1, 0, grid, s)) != hipSuccess) return e;
+        uint32_t cnt[4];
+        std::vector<unsigned long long> stat(kMsStatWords);
+        for (uint32_t k = 0;; ++k) {
+            if ((uint64_t)k > (uint64_t)g->n + 2) {
+                result = fail(BFS_EHIP, "multi-source profile loop did not terminate");
+                return hipSuccess;
+            }
+            if ((e = hipMemcpyAsync(cnt, p.cnt, sizeof cnt, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(stat.data(), p.mstat, stat.size() * 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+            const uint32_t t = k % 3, f = cnt[t];
+            if (f == 0) return hipSuccess;
+            unsigned long long sd = 0;
+            for (int gi = 0; gi < kMsDegGroups; ++gi) sd += stat[(t * kMsDegGroups + gi) * 8];
+            if ((e = copy_state(true)) != hipSuccess) return e;
+            float best[2] = {0.f, 0.f};
+            for (int form = 0; form < 2; ++form) {
+                for (int32_t r = 0; r < reps; ++r) {
+                    if ((e = copy_state(false)) != hipSuccess) return e;
+                    if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+                    if ((e = ms_level(p, k, form == 1, f, grid, s)) != hipSuccess) return e;
+                    if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+                    if ((e = hipEventSynchronize(ev[1])) != hipSuccess) return e;
+                    float ms = 0.f;
+                    if ((e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) return e;
+                    if (r == 0 || ms * 1e3f < best[form]) best[form] = ms * 1e3f;
+                }
+            }
+            for (int form = 0; form < 2; ++form) {
+                if (*count >= capacity) break;
+                bfs_level_record &rec = records[(*count)++];
+                rec = bfs_level_record{};
+                rec.level = (int32_t)k;
+                rec.variant = form;
+                rec.frontier = f;
+                rec.unvisited = (uint32_t)std::min<unsigned long long>(stat[kMsCumF], 0xffffffffull);
+                rec.frontier_edges = sd;
+                rec.unvisited_edges = (uint64_t)num_sources;
+                rec.time_us = best[form];
+            }
+            // advance with the faster direction, from the saved state
+            if ((e = copy_state(false)) != hipSuccess) return e;
+            if ((e = ms_level(p, k, best[1] < best[0], f, grid, s)) != hipSuccess) return e;
+        }
+    };
+    const hipError_t e = run();
+    done_events();
+    if (e != hipSuccess) return fail(BFS_EHIP, "HIP error %s", hipGetErrorString(e));
+    return result;
 }
 
 // ---------------------------------------------------------------------------

@@ -64,40 +64,6 @@ __device__ __forceinline__ float level_feature(uint32_t i, float nf, float sdf, 
     }
 }
 
-// The selector network 12 -> 32 (ReLU) -> 32 (ReLU) -> 3, row-major weights
-// [out][in] followed by the biases, then the feature mean and inverse std.
-// Evaluated by one wave: lane o < 32 holds hidden unit o, inputs are passed
-// between lanes with shuffles (no arrays, so nothing spills).  Returns, in
-// every lane, the argmin of the three predicted log-times, or -1 when an
-// output is not finite.
-__device__ __forceinline__ int mlp_argmin(const float *w, float feat) {
-    const float *W1 = w, *b1 = W1 + kMlpIn * kMlpH, *W2 = b1 + kMlpH,
-                *b2 = W2 + kMlpH * kMlpH, *W3 = b2 + kMlpH, *b3 = W3 + kMlpH * kMlpOut;
-    const float *mean = w + kMlpParams, *istd = mean + kMlpIn;
-    const uint32_t lane = lane_id();
-    const uint32_t li = lane < (uint32_t)kMlpIn ? lane : 0u;
-    const float x = (lane < (uint32_t)kMlpIn) ? (feat - mean[li]) * istd[li] : 0.f;
-    const uint32_t o = lane & (kMlpH - 1);
-    float a = b1[o];
-    for (int i = 0; i < kMlpIn; ++i) a = fmaf(W1[o * kMlpIn + i], __shfl(x, i, 64), a);
-    const float h1 = a > 0.f ? a : 0.f;
-    float c = b2[o];
-    for (int i = 0; i < kMlpH; ++i) c = fmaf(W2[o * kMlpH + i], __shfl(h1, i, 64), c);
-    const float h2 = (c > 0.f ? c : 0.f) * (lane < (uint32_t)kMlpH ? 1.f : 0.f);
-    int best = 0;
-    float bestv = 0.f;
-    bool ok = true;
-    for (int u = 0; u < kMlpOut; ++u) {
-        float y = W3[u * kMlpH + o] * h2;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) y += __shfl_xor(y, d, 64);
-        y += b3[u];
-        if (!(y == y) || y > 1e30f || y < -1e30f) ok = false;
-        if (u == 0 || y < bestv) { bestv = y; best = u; }
-    }
-    return ok ? best : -1;
-}
-
 // The form level k runs, decided once per level by one full wave (all 64
 // lanes call it with the same counters) before the level's launch: the
 // forced form, the edge-ratio rule, or the network's argmin.

@@ -119,6 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
     if (p.fill_levels)                                  // the caller's arrays: unreached = -1
         for (size_t i = gid; i < ns; i += stride) reinterpret_cast<int4 *>(p.slev)[i] = make_int4(-1, -1, -1, -1);
     if (gid < 4) p.cnt[gid] = 0u;
+    if (gid < (size_t)kMsStatWords) p.mstat[gid] = 0ull;
 }
 
 // Sources: bit q set in cur and vis of its vertex, level 0, parent itself; each
@@ -132,7 +133,12 @@ __global__ __launch_bounds__(kBlock) void k_ms_roots(MsLevel p) {
         atomicOr(&row(p.vis, s, p.W)[q >> 6], bit);
         p.slev[stage(p, s, q)] = 0;
         p.spar[stage(p, s, q)] = (uint32_t)s;
-        if (atomicMax(&p.flag[s], 1u) < 1u) p.fq[0][atomicAdd(&p.cnt[0], 1u)] = s;
+        if (atomicMax(&p.flag[s], 1u) < 1u) {
+            p.fq[0][atomicAdd(&p.cnt[0], 1u)] = s;
+            atomicAdd(&p.mstat[(q % kMsDegGroups) * 8],
+                      (unsigned long long)(p.out_ptr[s + 1] - p.out_ptr[s]));
+            atomicAdd(&p.mstat[kMsCumF], 1ull);
+        }
     }
 }
 
@@ -307,6 +313,25 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
     if (nbuf) flush();
 }
 
+// The out-degree sum d of the calling block's share of list slot t, into the
+// block's group line of mstat (one atomic per block).  Every thread calls it.
+__device__ __forceinline__ void add_degrees(const MsLevel &p, uint32_t t, unsigned long long d) {
+    __shared__ unsigned long long s_d[kBlock / 64];
+    d = wave_sum64(d);
+    if (__lane_id() == 0) s_d[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < kBlock / 64; ++w) sum += s_d[w];
+        if (sum) atomicAdd(&p.mstat[(t * kMsDegGroups + blockIdx.x % kMsDegGroups) * 8], sum);
+    }
+}
+
+// The group lines of list slot t to zero (called by one thread).
+__device__ __forceinline__ void clear_degrees(const MsLevel &p, uint32_t t) {
+    for (int g = 0; g < kMsDegGroups; ++g) p.mstat[(t * kMsDegGroups + g) * 8] = 0ull;
+}
+
 // Level k, settle half, one lane per newly listed vertex v: the new bits
 // (nxt[v]) join vis and get level k+1 (their parents were set by the push).
 // The progress report is written only for a level that had a frontier, so
@@ -321,14 +346,18 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     if (gt == 0) {
         p.cnt[s2] = 0u;                       // the list of level k+2 starts empty
+        clear_degrees(p, s2);
+        p.mstat[kMsCumF] += nnext;
         if (p.cnt[s0] != 0u) {
             p.host_status[0] = k + 1;
             p.host_status[1] = nnext;
             __threadfence_system();
         }
     }
+    unsigned long long deg = 0;
     for (uint32_t i = gt; i < nnext; i += gs) {
         const int32_t v = fnxt[i];
+        deg += (unsigned long long)(p.out_ptr[v + 1] - p.out_ptr[v]);
         for (uint32_t w = 0; w < W; ++w) {
             const unsigned long long nb = row(nxt, v, W)[w];
             if (!nb) continue;
@@ -337,6 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
                 p.slev[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)] = (int32_t)(k + 1);
         }
     }
+    add_degrees(p, s1, deg);
 }
 
 // The union-frontier bitmap of level k: bit v of fbits = some word of v's
@@ -735,14 +765,70 @@ __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
     }
 }
 
-// After a pull level: the lists of level k+2 start empty; report to the host.
-__global__ void k_ms_report(MsLevel p, uint32_t k) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const uint32_t s2 = (k + 2) % 3;
-    p.cnt[s2] = 0u;
-    p.host_status[0] = k + 1;
-    p.host_status[1] = p.cnt[(k + 1) % 3];
-    __threadfence_system();
+// After a pull level: the lists of level k+2 start empty; report to the host;
+// the out-degree sum of the level-(k+1) list.
+__global__ __launch_bounds__(kBlock) void k_ms_report(MsLevel p, uint32_t k) {
+    const uint32_t s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const uint32_t nnext = p.cnt[s1];
+    const int32_t *fnxt = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s1);
+    const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
+    if (gt == 0) {
+        p.cnt[s2] = 0u;
+        clear_degrees(p, s2);
+        p.mstat[kMsCumF] += nnext;
+        p.host_status[0] = k + 1;
+        p.host_status[1] = nnext;
+        __threadfence_system();
+    }
+    unsigned long long deg = 0;
+    for (uint32_t i = gt; i < nnext; i += gs) {
+        const int32_t v = fnxt[i];
+        deg += (unsigned long long)(p.out_ptr[v + 1] - p.out_ptr[v]);
+    }
+    add_degrees(p, s1, deg);
+}
+
+// The direction of level k (one wave): the network's argmin between push (0)
+// and pull (1) over the level's twelve features, push when an output is not
+// finite (or without a network); written to host_status[2].  Features, from
+// f = |F_k| (the union frontier), d = its out-degree sum, c = the summed union
+// frontier sizes of levels 0..k, the number of sources, k, n and nnz.
+__device__ __forceinline__ float ms_feature(uint32_t i, float f, float sd, float cum, float q, float k,
+                                            float n, float nnz) {
+    switch (i) {
+        case 0: return logf(1.f + f);
+        case 1: return logf(1.f + sd);
+        case 2: return logf(1.f + cum);
+        case 3: return logf(1.f + q);
+        case 4: return logf(1.f + k);
+        case 5: return nnz / n;
+        case 6: return logf((f + 1.f) / n);
+        case 7: return logf((sd + 1.f) / (nnz + 1.f));
+        case 8: return logf((cum + 1.f) / n);
+        case 9: return logf((sd + 1.f) / (f + 1.f));
+        case 10: return logf((f + 1.f) * q / n);
+        case 11: return logf((sd + 1.f) / (nnz - sd + 1.f));
+        default: return 0.f;
+    }
+}
+
+__global__ void k_ms_decide(MsLevel p, uint32_t k) {
+    const uint32_t t = k % 3;
+    const uint32_t f = p.cnt[t];
+    unsigned long long sd = 0;
+    for (int g = 0; g < kMsDegGroups; ++g) sd += p.mstat[(t * kMsDegGroups + g) * 8];
+    const unsigned long long cum = p.mstat[kMsCumF];
+    uint32_t v = 0;
+    if (p.mlp != nullptr) {
+        const float feat = ms_feature(__lane_id(), (float)f, (float)sd, (float)cum, (float)p.nq,
+                                      (float)k, (float)p.n, (float)p.out_ptr[p.n]);
+        const int b = mlp_argmin(p.mlp, feat, 2);
+        v = b < 0 ? 0u : (uint32_t)b;
+    }
+    if (threadIdx.x == 0) {
+        p.host_status[2] = v;
+        __threadfence_system();
+    }
 }
 
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s) {
@@ -756,7 +842,8 @@ hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hip
         case 7: hipLaunchKernelGGL(k_ms_out, dim3(grid), dim3(kBlock), 0, s, p); break;
         case 8: hipLaunchKernelGGL(k_ms_fbits, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 9: hipLaunchKernelGGL(k_ms_pull_rest, dim3(grid), dim3(kBlock), 0, s, p, k); break;
-        default: hipLaunchKernelGGL(k_ms_report, dim3(1), dim3(64), 0, s, p, k); break;
+        case 10: hipLaunchKernelGGL(k_ms_decide, dim3(1), dim3(64), 0, s, p, k); break;
+        default: hipLaunchKernelGGL(k_ms_report, dim3(grid), dim3(kBlock), 0, s, p, k); break;
     }
     return hipGetLastError();
 }

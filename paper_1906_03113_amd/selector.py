@@ -232,6 +232,154 @@ def load_weights(path: str = DEFAULT_WEIGHTS):
     return torch.tensor(w, device="cuda")
 
 
+# ---- the multi-source direction ------------------------------------------------------------
+#
+# bfs_run_batch / bfs_run_batch_vm under BFS_VARIANT_LEARNED ask the same network
+# (its first two outputs: push, pull) before every level, over features of the
+# union frontier F (vertices in some source's frontier).  Training data come from
+# bfs_ms_profile_levels, which times both directions of every level from the
+# same saved state.
+
+MS_WEIGHTS = os.path.join(HERE, "selector_ms_weights.json")
+MS_DIRECTIONS = ("push", "pull")
+
+
+def ms_features(frontier, frontier_edges, listed, sources, level, n, nnz) -> np.ndarray:
+    """The twelve multi-source level features (the device's definitions), float64
+    [rows, 12]: f = |F_k|, d = out-degree sum over F_k, c = summed union-frontier
+    sizes of levels 0..k, q = number of sources, k, n, nnz."""
+    f = np.asarray(frontier, np.float64)
+    d = np.asarray(frontier_edges, np.float64)
+    c = np.asarray(listed, np.float64)
+    q = np.asarray(sources, np.float64)
+    k = np.asarray(level, np.float64)
+    n = np.full(f.shape, float(n)) if np.ndim(n) == 0 else np.asarray(n, np.float64)
+    nnz = np.full(f.shape, float(nnz)) if np.ndim(nnz) == 0 else np.asarray(nnz, np.float64)
+    return np.stack([np.log1p(f), np.log1p(d), np.log1p(c), np.log1p(q), np.log1p(k), nnz / n,
+                     np.log((f + 1) / n), np.log((d + 1) / (nnz + 1)), np.log((c + 1) / n),
+                     np.log((d + 1) / (f + 1)), np.log((f + 1) * q / n),
+                     np.log((d + 1) / (nnz - d + 1))], axis=-1)
+
+
+def ms_profile(G, sources: Sequence[int], reps: int = 2, out=None) -> List[Dict]:
+    """Per-level device times of both directions for one multi-source call (see
+    bfs_ms_profile_levels).  out: optional (level, parent) int32 cuda tensors of
+    shape [n, 64 * ceil(len / 64)] that receive the results."""
+    torch = _torch()
+    from . import Workspace, batch_vm_workspace_size
+    L = _lib.lib()
+    src = np.ascontiguousarray(np.asarray(sources, np.int32))
+    nq = len(src)
+    ld = 64 * ((nq + 63) // 64)
+    if out is None:
+        out = (torch.empty((G.n, ld), dtype=torch.int32, device="cuda"),
+               torch.empty((G.n, ld), dtype=torch.int32, device="cuda"))
+    level, parent = out
+    ws = Workspace(batch_vm_workspace_size(G, nq))
+    snap = Workspace(int(L.bfs_ms_profile_snapshot_size(G.handle, nq)))
+    cap = 2 * 100000
+    recs = (_lib.LevelRecord * cap)()
+    cnt = ctypes.c_uint32(0)
+    s = torch.cuda.current_stream()
+    _lib.check(L.bfs_ms_profile_levels(G.handle, nq, src.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.c_void_p(level.data_ptr()), ctypes.c_void_p(parent.data_ptr()),
+                                       ws.ptr, ws.nbytes, snap.ptr, snap.nbytes, int(reps), recs, cap,
+                                       ctypes.byref(cnt), ctypes.c_void_p(int(s.cuda_stream))))
+    torch.cuda.synchronize()
+    del ws, snap
+    res: Dict[int, Dict] = {}
+    for i in range(cnt.value):
+        r = recs[i]
+        d = res.setdefault(r.level, dict(level=r.level, frontier=r.frontier, frontier_edges=r.frontier_edges,
+                                         listed=r.unvisited, sources=r.unvisited_edges,
+                                         times=[math.nan] * N_OUT))
+        d["times"][r.variant] = r.time_us
+    return [res[k] for k in sorted(res)]
+
+
+def ms_dataset(levels: Sequence[Dict], n: int, nnz: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(features [rows,12], log-time targets [rows,3], mask [rows,3]); the third
+    output is never a target (the multi-source search has two directions)."""
+    if not levels:
+        return np.zeros((0, N_IN)), np.zeros((0, N_OUT)), np.zeros((0, N_OUT))
+    X = ms_features([d["frontier"] for d in levels], [d["frontier_edges"] for d in levels],
+                    [d["listed"] for d in levels], [d["sources"] for d in levels],
+                    [d["level"] for d in levels], n, nnz)
+    T = np.array([d["times"] for d in levels], dtype=np.float64)
+    T[:, 2] = np.nan
+    M = np.isfinite(T) & (T > 0)
+    T = np.where(M, np.log(np.where(M, T, 1.0)), 0.0)
+    return X, T, M.astype(np.float64)
+
+
+def ms_choose(blob: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """The device's decision: argmin over the push and pull outputs."""
+    y = predict(blob, X)[:, :2]
+    return np.argmin(y, axis=1)
+
+
+def ms_heuristic_choice(X: np.ndarray, shift: int = 5) -> np.ndarray:
+    """What BFS_VARIANT_HEURISTIC picks from the same rows: pull once the union
+    frontier holds more than n >> shift vertices (read back from features 0 and 6)."""
+    f = np.expm1(X[:, 0])
+    n = (f + 1) / np.exp(X[:, 6])
+    return ((np.round(f) * 2.0 ** shift) > np.round(n)).astype(np.int64)
+
+
+def ms_training_sets(include_large: bool = True):
+    """(train, held-out) lists of (name, graph builder, source batches); a batch
+    is (count, seed) of seeded picks.  Held out: R-MAT scales and batch sizes
+    never trained on."""
+    import graphgen
+    train = [("er16k", lambda: graphgen.workload("er16k"), [(64, 1), (256, 2)]),
+             ("grid512", lambda: graphgen.grid(512, 0.9, 3), [(16, 3), (64, 4)]),
+             ("rmatd16", lambda: graphgen.rmat(16, 16, 1, directed=True), [(64, 5), (256, 6)])]
+    if include_large:
+        train += [("rmat22", lambda: graphgen.workload("rmat22"), [(64, 7), (16, 8)]),
+                  ("rmat20d", lambda: graphgen.workload("rmat20d"), [(256, 9), (64, 10)]),
+                  ("rmat19", lambda: graphgen.rmat(19, 16, 7), [(128, 11)]),
+                  ("grid1024", lambda: graphgen.grid(1024, 0.9, 5), [(16, 12)])]
+    held = [(f"rmat{sc}", (lambda sc=sc: graphgen.rmat(sc, 16, 2000 + sc)), [(64, 20 + sc), (192, 40 + sc)])
+            for sc in ((16, 18) if not include_large else (16, 17, 18, 21))]
+    return train, held
+
+
+def ms_collect(entries, reps: int = 2, log=None):
+    import graphgen
+    from . import Graph
+    Xs, Ts, Ms = [], [], []
+    for name, build, batches in entries:
+        g = build() if callable(build) else build
+        G = Graph.from_graphgen(g)
+        for count, seed in batches:
+            src = graphgen.pick_sources(g, count, seed)
+            lv = ms_profile(G, src, reps)
+            X, T, M = ms_dataset(lv, g.n, g.nnz)
+            Xs.append(X); Ts.append(T); Ms.append(M)
+            if log:
+                log(f"[selector-ms] {name} {count} sources: {len(lv)} levels")
+        G.close()
+        del g
+    return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Ms)
+
+
+def ms_main(args, log):
+    train_e, held_e = ms_training_sets(include_large=not args.small)
+    X, T, M = ms_collect(train_e, log=log)
+    Xh, Th, Mh = ms_collect(held_e, log=log)
+    log(f"[selector-ms] training rows {len(X)}, held-out rows {len(Xh)}")
+    w = train(X, T, M, steps=args.steps, log=log)
+    res = {}
+    for tag, (x, t, m) in (("train", (X, T, M)), ("held_out", (Xh, Th, Mh))):
+        res[tag] = regret(ms_choose(w, x), t, m)
+        res[tag]["heuristic_regret"] = regret(ms_heuristic_choice(x), t, m)["regret"]
+        log(f"[selector-ms] {tag}: {res[tag]}")
+    meta = dict(res, train_rows=int(len(X)), held_rows=int(len(Xh)),
+                outputs="push, pull (the third output is unused)")
+    save_weights(args.ms_out, w, meta)
+    print(json.dumps(res))
+
+
 # ---- the training recipe ----------------------------------------------------------------
 
 def training_graphs(include_large: bool = True):
@@ -300,10 +448,16 @@ def main(argv=None):
     ap.add_argument("--cap", type=int, default=300, help="levels kept per training search")
     ap.add_argument("--eval", action="store_true",
                     help="only measure the held-out regret of the weights in --out (no training)")
+    ap.add_argument("--multi-source", action="store_true",
+                    help="train the multi-source direction (push / pull) instead")
+    ap.add_argument("--ms-out", default=MS_WEIGHTS)
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch = _torch()
     torch.cuda.init()                 # the device context first, before any CPU-heavy setup
+    if args.multi_source:
+        ms_main(args, log)
+        return
     train_g, held_g = training_graphs(include_large=not args.small)
     if args.eval:
         with open(args.out) as f:

@@ -1,0 +1,221 @@
+"""The learned direction of the multi-source searches on the GPU: whatever the
+network's weights, every query's result equals the single-source oracle; the
+search follows the network's decisions (not the edge-ratio rule); the
+exhaustive per-level profile gives the oracle's results and the features the
+device reads; trained weights beat push on every level on held-out graphs."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+from oracle import mlp_ref
+from tests.gpu_common import compare_all, need_gpu, oracle_all, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    return need_gpu()
+
+
+def _out_bias(blob):
+    """Index of the first output bias in a weight blob."""
+    return mlp_ref.N_TRAIN - 3
+
+
+def _blob(kind, seed=0):
+    """Weights of a given behaviour: every level push / pull, the frontier rule
+    (pull once |F| > n / 32, through feature 6 = log((|F|+1)/n)), random, NaN."""
+    rng = np.random.default_rng(seed)
+    blob = np.zeros(mlp_ref.N_TOTAL, np.float64)
+    blob[mlp_ref.N_TRAIN + 12:] = 1.0                 # inverse std; means stay 0
+    ob = _out_bias(blob)
+    if kind == "push":
+        blob[ob:ob + 3] = [0.0, 1.0, 5.0]
+    elif kind == "pull":
+        blob[ob:ob + 3] = [1.0, 0.0, 5.0]
+    elif kind == "rule":
+        # hidden unit 0 = relu(x6 + log 32); second layer copies it; pull = 1e-3 - 10 h
+        blob[0 * 12 + 6] = 1.0
+        blob[12 * 32 + 0] = math.log(32.0)
+        w2 = 12 * 32 + 32
+        blob[w2 + 0] = 1.0                            # W2[0][0]
+        w3 = w2 + 32 * 32 + 32
+        blob[w3 + 32 + 0] = -10.0                     # W3[1][0]
+        blob[ob:ob + 3] = [0.0, 1e-3, 5.0]
+    elif kind == "random":
+        blob[:mlp_ref.N_TRAIN] = rng.normal(0, 0.5, mlp_ref.N_TRAIN)
+        blob[mlp_ref.N_TRAIN:mlp_ref.N_TRAIN + 12] = rng.normal(0, 1, 12)
+        blob[mlp_ref.N_TRAIN + 12:] = rng.uniform(0.2, 1.5, 12)
+    elif kind == "nan":
+        blob[:mlp_ref.N_TRAIN] = rng.normal(0, 0.5, mlp_ref.N_TRAIN)
+        blob[ob] = np.nan
+    else:
+        raise ValueError(kind)
+    return blob.astype(np.float32)
+
+
+def _graphs():
+    return {"rmat13": graphgen.rmat(13, 16, 61),
+            "rmatd12": graphgen.rmat(12, 16, 62, directed=True),
+            "grid60": graphgen.grid(60, 0.85, 63)}
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    return _graphs()
+
+
+def _sources(g, nq, seed):
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = np.random.default_rng(seed).choice(cand, size=nq, replace=True)
+    src[1] = src[0]                                  # a duplicate source
+    return [int(s) for s in src]
+
+
+@pytest.mark.parametrize("kind", ["push", "pull", "rule", "random", "nan", "trained"])
+def test_weights_never_change_results(P, graphs, kind):
+    import torch
+    from paper_1906_03113_amd import selector as S
+    if kind == "trained":
+        if not os.path.exists(S.MS_WEIGHTS):
+            pytest.skip("no trained multi-source weights in the tree")
+        w = S.load_weights(S.MS_WEIGHTS)
+    else:
+        w = torch.tensor(_blob(kind, seed=7), device="cuda")
+    for (name, g), nq in zip(graphs.items(), (64, 130, 63)):
+        src = _sources(g, nq, 70 + nq)
+        want = oracle_all(g, src)
+        say(f"[ms-learned] {kind} weights {name} nq={nq}")
+        G = P.Graph.from_graphgen(g)
+        info = {}
+        lv, pa = P.bfs_batch(G, src, variant="learned", selector=w, info=info, trace=True)
+        vi = {}
+        vl, vp = P.bfs_batch_vm(G, src, variant="learned", selector=w, info=vi, trace=True)
+        torch.cuda.synchronize()
+        compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{kind}/{name}")
+        compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"{kind}/{name}/vm")
+        dirs = [r["direction"] for r in info["trace"]]
+        assert len(dirs) == info["levels"] == vi["levels"]
+        assert dirs == [r["direction"] for r in vi["trace"]]
+        if kind in ("push", "nan"):
+            assert set(dirs) == {"push"}, dirs
+        if kind == "pull":
+            assert set(dirs) == {"pull"}, dirs
+        if kind == "rule":
+            # the network's decision where the host read the frontier (the
+            # first level of a group), against the rule it encodes (pull once
+            # (|F| + 1) * 32 > n), away from the rule's float32 boundary
+            for r in info["trace"][1:]:
+                ratio = (r["frontier"] + 1) * 32.0 / g.n
+                if r["frontier"] and abs(ratio - 1.0) > 0.01:
+                    assert r["direction"] == ("pull" if ratio > 1.0 else "push"), r
+
+
+def test_learned_without_weights_is_push(P, graphs):
+    """LEARNED with no network pushes on every level (the fallback), in both layouts."""
+    import torch
+    g = graphs["rmat13"]
+    G = P.Graph.from_graphgen(g)
+    src = _sources(g, 64, 5)
+    want = oracle_all(g, src)
+    say("[ms-learned] no weights")
+    info = {}
+    lv, pa = P.bfs_batch(G, src, variant="learned", info=info, trace=True)
+    torch.cuda.synchronize()
+    compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), "noweights")
+    assert {r["direction"] for r in info["trace"]} == {"push"}
+    hi = {}
+    P.bfs_batch(G, src, variant="heuristic", info=hi, trace=True)
+    assert "pull" in {r["direction"] for r in hi["trace"]}      # the rule would have pulled
+
+
+@pytest.mark.parametrize("name,nq", [("rmat13", 64), ("grid60", 16), ("rmatd12", 100)])
+def test_ms_profile_levels(P, graphs, name, nq):
+    """The exhaustive profile: the oracle's results, two timed directions per
+    level, and the level statistics the device's features read."""
+    import torch
+    from paper_1906_03113_amd import selector as S
+    g = graphs[name]
+    G = P.Graph.from_graphgen(g)
+    src = _sources(g, nq, 90 + nq)
+    want = oracle_all(g, src)
+    ld = 64 * ((nq + 63) // 64)
+    lv = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
+    pa = torch.empty((g.n, ld), dtype=torch.int32, device="cuda")
+    say(f"[ms-profile] {name} nq={nq}")
+    levels = S.ms_profile(G, src, reps=2, out=(lv, pa))
+    compare_all(want, src, lambda q: (lv[:, q].cpu().numpy(), pa[:, q].cpu().numpy()), f"profile/{name}")
+    W = np.stack([wl for wl, _ in want])                    # [nq, n]
+    depth = int(W.max()) + 1
+    assert [d["level"] for d in levels] == list(range(depth))
+    deg = np.diff(g.ptr.astype(np.int64))
+    listed = 0
+    for d in levels:
+        F = np.any(W == d["level"], axis=0)
+        listed += int(F.sum())
+        assert d["frontier"] == int(F.sum())
+        assert d["frontier_edges"] == int(deg[F].sum())
+        assert d["listed"] == listed
+        assert d["sources"] == nq
+        assert all(np.isfinite(t) and t > 0 for t in d["times"][:2])
+    X, T, M = S.ms_dataset(levels, g.n, g.nnz)
+    assert X.shape == (depth, 12) and M[:, :2].all() and not M[:, 2].any()
+
+
+def test_trained_direction_gains_over_push(P):
+    """On held-out R-MAT graphs and batch sizes, the trained network's per-level
+    directions cost less device time than pushing every level (exhaustive
+    per-level timing of both directions)."""
+    from paper_1906_03113_amd import selector as S
+    if not os.path.exists(S.MS_WEIGHTS):
+        pytest.skip("no trained multi-source weights in the tree")
+    import json
+    w = np.asarray(json.load(open(S.MS_WEIGHTS))["weights"], np.float32)
+    Xs, Ts, Ms = [], [], []
+    for scale, nq in ((15, 64), (17, 128)):
+        g = graphgen.rmat(scale, 16, 5150 + scale)
+        G = P.Graph.from_graphgen(g)
+        src = graphgen.pick_sources(g, nq, 31)
+        say(f"[ms-learned] gain rmat{scale} nq={nq}")
+        X, T, M = S.ms_dataset(S.ms_profile(G, src, reps=2), g.n, g.nnz)
+        Xs.append(X); Ts.append(T); Ms.append(M)
+        G.close()
+    X, T, M = np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Ms)
+    r = S.regret(S.ms_choose(w, X), T, M)
+    say(f"[ms-learned] held-out: {r}")
+    assert r["chosen_us"] < r["push_us"], r
+
+
+@pytest.mark.parametrize("seed", [7, 8, 9])
+def test_device_decisions_match_features(P, graphs, seed):
+    """The direction the device picks at each level (below level 16, where
+    every level is decided) is the argmin of the network over the features the
+    training code computes from the profile's level statistics: the device's
+    features and the training features are the same numbers."""
+    import torch
+    from paper_1906_03113_amd import selector as S
+    blob = _blob("random", seed=seed)
+    w = torch.tensor(blob, device="cuda")
+    checked = 0
+    for name, nq in (("rmat13", 64), ("rmatd12", 100)):
+        g = graphs[name]
+        G = P.Graph.from_graphgen(g)
+        src = _sources(g, nq, 200 + seed)
+        say(f"[ms-learned] decisions {name} seed={seed}")
+        levels = S.ms_profile(G, src, reps=1)
+        X, _, _ = S.ms_dataset(levels, g.n, g.nnz)
+        y = S.predict(blob, X)[:, :2]
+        info = {}
+        P.bfs_batch(G, src, variant="learned", selector=w, info=info, trace=True)
+        torch.cuda.synchronize()
+        for r in info["trace"][:16]:
+            k = r["level"]
+            if abs(y[k, 0] - y[k, 1]) < 1e-3 * (1 + abs(y[k, 0])):
+                continue                               # a near tie: float32 order may decide
+            assert r["direction"] == S.MS_DIRECTIONS[int(np.argmin(y[k]))], (name, k, y[k])
+            checked += 1
+    assert checked > 0
