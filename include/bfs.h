@@ -333,7 +333,13 @@ size_t bfs_ms_profile_snapshot_size(const bfs_graph *g, int32_t num_sources);
  * push, 1 = pull; time_us) holding the features the learned direction reads:
  * frontier = size of the union frontier F_k (vertices in some source's
  * frontier), frontier_edges = the sum of their out-degrees, unvisited = the
- * summed union-frontier sizes of levels 0..k, unvisited_edges = num_sources.
+ * summed union-frontier sizes of levels 0..k, unvisited_edges = the (vertex,
+ * source) pairs not reached through level k (n * num_sources minus those
+ * reached).  The learned direction's twelve features are built from these,
+ * num_sources, k, n and nnz: log(1+f), log(1+d), log(1+c), log(1+q),
+ * log(1+k), nnz/n, log((f+1)/n), log((d+1)/(nnz+1)), log((u+1)/(n q)),
+ * log((d+1)/(f+1)), log((f+1) q/n), log((d+1)/(nnz-d+1)) with f, d, c, u
+ * the four statistics in that order and q = num_sources.
  * *count = records written (at most capacity).  level, parent, workspace: as
  * for bfs_run_batch_vm (workspace of bfs_batch_vm_workspace_size bytes);
  * snapshot: device, bfs_ms_profile_snapshot_size bytes, 256-byte aligned;

@@ -1475,8 +1475,13 @@ extern "C" bfs_status bfs_ms_profile_levels(bfs_graph *g, int32_t num_sources, c
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
             const uint32_t t = k % 3, f = cnt[t];
             if (f == 0) return hipSuccess;
-            unsigned long long sd = 0;
-            for (int gi = 0; gi < kMsDegGroups; ++gi) sd += stat[(t * kMsDegGroups + gi) * 8];
+            unsigned long long sd = 0, listed = 0, reached = 0;
+            for (int gi = 0; gi < kMsDegGroups; ++gi) {
+                sd += stat[ms_line((int)t, gi)];
+                listed += stat[ms_line(kMsCumSlot, gi)];
+                reached += stat[ms_line(kMsCumSlot, gi) + 1];
+            }
+            const unsigned long long pairs = (unsigned long long)g->n * (unsigned long long)num_sources;
             if ((e = copy_state(true)) != hipSuccess) return e;
             float best[2] = {0.f, 0.f};
             for (int form = 0; form < 2; ++form) {
@@ -1498,9 +1503,9 @@ extern "C" bfs_status bfs_ms_profile_levels(bfs_graph *g, int32_t num_sources, c
                 rec.level = (int32_t)k;
                 rec.variant = form;
                 rec.frontier = f;
-                rec.unvisited = (uint32_t)std::min<unsigned long long>(stat[kMsCumF], 0xffffffffull);
+                rec.unvisited = (uint32_t)std::min<unsigned long long>(listed, 0xffffffffull);
                 rec.frontier_edges = sd;
-                rec.unvisited_edges = (uint64_t)num_sources;
+                rec.unvisited_edges = pairs > reached ? pairs - reached : 0ull;
                 rec.time_us = best[form];
             }
             // advance with the faster direction, from the saved state

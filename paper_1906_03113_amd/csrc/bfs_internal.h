@@ -216,21 +216,22 @@ struct MsLevel {
                                    // (average degree below 8), else sized to the list
     uint32_t long_split;           // pull: long rows' first chunks, then the later ones
                                    // in a second launch (k_ms_pull_rest)
-    // level statistics for the learned direction (layout below): the out-degree
-    // sum of each level's union frontier, accumulated as the level's list is
-    // settled or reported, and the summed sizes of the lists built so far
+    // level statistics for the learned direction (layout below), accumulated
+    // as each level's list is settled or reported
     unsigned long long *mstat;
     const float *mlp;              // selector weights for the learned direction, or nullptr
 };
 
-// Layout of mstat: for list slot t (= level % 3) and group g < kMsDegGroups,
-// the degree sum of that slot's union frontier accumulated by group g lies at
-// mstat[(t * kMsDegGroups + g) * 8] (one 64-byte line each, so the blocks'
-// atomics spread over 16 lines); then, at mstat[kMsCumF], the summed sizes of
-// the union frontiers listed so far (levels 0..k once level k's list is built).
+// Layout of mstat: 64-byte group lines ms_line(t, g) for g < kMsDegGroups
+// (the blocks' atomics spread over 16 lines).  Slots t < 3 hold the list of
+// level k with t = k % 3: word 0 = the out-degree sum of that union frontier,
+// word 1 = the (vertex, source) pairs it newly reaches (the popcount of its
+// masks).  Slot 3 holds the running totals through the last list built: word 0
+// = the summed union-frontier sizes, word 1 = the pairs reached.
 constexpr int kMsDegGroups = 16;
-constexpr int kMsCumF = 3 * kMsDegGroups * 8;
-constexpr int kMsStatWords = kMsCumF + 8;
+constexpr int kMsCumSlot = 3;
+constexpr int kMsStatWords = 4 * kMsDegGroups * 8;
+__host__ __device__ constexpr int ms_line(int t, int g) { return (t * kMsDegGroups + g) * 8; }
 
 struct MsLayout {
     size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, mstat, fbits, slev, spar, lptr, pptr, src, total;

@@ -133,11 +133,13 @@ __global__ __launch_bounds__(kBlock) void k_ms_roots(MsLevel p) {
         atomicOr(&row(p.vis, s, p.W)[q >> 6], bit);
         p.slev[stage(p, s, q)] = 0;
         p.spar[stage(p, s, q)] = (uint32_t)s;
+        const int g = (int)(q % kMsDegGroups);
+        atomicAdd(&p.mstat[ms_line(0, g) + 1], 1ull);              // one pair per source
+        atomicAdd(&p.mstat[ms_line(kMsCumSlot, g) + 1], 1ull);
         if (atomicMax(&p.flag[s], 1u) < 1u) {
             p.fq[0][atomicAdd(&p.cnt[0], 1u)] = s;
-            atomicAdd(&p.mstat[(q % kMsDegGroups) * 8],
-                      (unsigned long long)(p.out_ptr[s + 1] - p.out_ptr[s]));
-            atomicAdd(&p.mstat[kMsCumF], 1ull);
+            atomicAdd(&p.mstat[ms_line(0, g)], (unsigned long long)(p.out_ptr[s + 1] - p.out_ptr[s]));
+            atomicAdd(&p.mstat[ms_line(kMsCumSlot, g)], 1ull);
         }
     }
 }
@@ -313,23 +315,42 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
     if (nbuf) flush();
 }
 
-// The out-degree sum d of the calling block's share of list slot t, into the
-// block's group line of mstat (one atomic per block).  Every thread calls it.
-__device__ __forceinline__ void add_degrees(const MsLevel &p, uint32_t t, unsigned long long d) {
-    __shared__ unsigned long long s_d[kBlock / 64];
+// The calling block's share of list slot t's statistics (out-degree sum d,
+// new pairs c) into the block's group lines of mstat, slot t and the running
+// totals (one atomic per word per block).  Every thread calls it.
+__device__ __forceinline__ void add_stats(const MsLevel &p, uint32_t t, unsigned long long d,
+                                          unsigned long long c) {
+    __shared__ unsigned long long s_d[kBlock / 64][2];
     d = wave_sum64(d);
-    if (__lane_id() == 0) s_d[threadIdx.x >> 6] = d;
+    c = wave_sum64(c);
+    if (__lane_id() == 0) {
+        s_d[threadIdx.x >> 6][0] = d;
+        s_d[threadIdx.x >> 6][1] = c;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long sum = 0;
-        for (int w = 0; w < kBlock / 64; ++w) sum += s_d[w];
-        if (sum) atomicAdd(&p.mstat[(t * kMsDegGroups + blockIdx.x % kMsDegGroups) * 8], sum);
+        unsigned long long sd = 0, sc = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            sd += s_d[w][0];
+            sc += s_d[w][1];
+        }
+        const int g = (int)(blockIdx.x % kMsDegGroups);
+        if (sd) atomicAdd(&p.mstat[ms_line((int)t, g)], sd);
+        if (sc) {
+            atomicAdd(&p.mstat[ms_line((int)t, g) + 1], sc);
+            atomicAdd(&p.mstat[ms_line(kMsCumSlot, g) + 1], sc);
+        }
     }
 }
 
-// The group lines of list slot t to zero (called by one thread).
-__device__ __forceinline__ void clear_degrees(const MsLevel &p, uint32_t t) {
-    for (int g = 0; g < kMsDegGroups; ++g) p.mstat[(t * kMsDegGroups + g) * 8] = 0ull;
+// List slot t's statistics to zero and the list's size into the running
+// total (called by one thread, before the list's statistics are added).
+__device__ __forceinline__ void start_stats(const MsLevel &p, uint32_t t_clear, uint32_t listed) {
+    for (int g = 0; g < kMsDegGroups; ++g) {
+        p.mstat[ms_line((int)t_clear, g)] = 0ull;
+        p.mstat[ms_line((int)t_clear, g) + 1] = 0ull;
+    }
+    atomicAdd(&p.mstat[ms_line(kMsCumSlot, 0)], (unsigned long long)listed);
 }
 
 // Level k, settle half, one lane per newly listed vertex v: the new bits
@@ -346,27 +367,27 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     if (gt == 0) {
         p.cnt[s2] = 0u;                       // the list of level k+2 starts empty
-        clear_degrees(p, s2);
-        p.mstat[kMsCumF] += nnext;
+        start_stats(p, s2, nnext);
         if (p.cnt[s0] != 0u) {
             p.host_status[0] = k + 1;
             p.host_status[1] = nnext;
             __threadfence_system();
         }
     }
-    unsigned long long deg = 0;
+    unsigned long long deg = 0, pairs = 0;
     for (uint32_t i = gt; i < nnext; i += gs) {
         const int32_t v = fnxt[i];
         deg += (unsigned long long)(p.out_ptr[v + 1] - p.out_ptr[v]);
         for (uint32_t w = 0; w < W; ++w) {
             const unsigned long long nb = row(nxt, v, W)[w];
             if (!nb) continue;
+            pairs += (unsigned long long)__popcll(nb);
             row(p.vis, v, W)[w] |= nb;
             for (unsigned long long b = nb; b; b &= b - 1ull)
                 p.slev[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)] = (int32_t)(k + 1);
         }
     }
-    add_degrees(p, s1, deg);
+    add_stats(p, s1, deg, pairs);
 }
 
 // The union-frontier bitmap of level k: bit v of fbits = some word of v's
@@ -766,48 +787,51 @@ __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
 }
 
 // After a pull level: the lists of level k+2 start empty; report to the host;
-// the out-degree sum of the level-(k+1) list.
+// the statistics of the level-(k+1) list.
 __global__ __launch_bounds__(kBlock) void k_ms_report(MsLevel p, uint32_t k) {
     const uint32_t s1 = (k + 1) % 3, s2 = (k + 2) % 3;
     const uint32_t nnext = p.cnt[s1];
     const int32_t *fnxt = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s1);
+    const unsigned long long *nxt = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s1);
+    const uint32_t W = p.W;
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     if (gt == 0) {
         p.cnt[s2] = 0u;
-        clear_degrees(p, s2);
-        p.mstat[kMsCumF] += nnext;
+        start_stats(p, s2, nnext);
         p.host_status[0] = k + 1;
         p.host_status[1] = nnext;
         __threadfence_system();
     }
-    unsigned long long deg = 0;
+    unsigned long long deg = 0, pairs = 0;
     for (uint32_t i = gt; i < nnext; i += gs) {
         const int32_t v = fnxt[i];
         deg += (unsigned long long)(p.out_ptr[v + 1] - p.out_ptr[v]);
+        for (uint32_t w = 0; w < W; ++w) pairs += (unsigned long long)__popcll(row(nxt, v, W)[w]);
     }
-    add_degrees(p, s1, deg);
+    add_stats(p, s1, deg, pairs);
 }
 
 // The direction of level k (one wave): the network's argmin between push (0)
 // and pull (1) over the level's twelve features, push when an output is not
 // finite (or without a network); written to host_status[2].  Features, from
 // f = |F_k| (the union frontier), d = its out-degree sum, c = the summed union
-// frontier sizes of levels 0..k, the number of sources, k, n and nnz.
-__device__ __forceinline__ float ms_feature(uint32_t i, float f, float sd, float cum, float q, float k,
-                                            float n, float nnz) {
+// frontier sizes of levels 0..k, u = the (vertex, source) pairs not reached
+// through level k, q sources, k, n and nnz.
+__device__ __forceinline__ float ms_feature(uint32_t i, float f, float d, float c, float u, float q,
+                                            float k, float n, float nnz) {
     switch (i) {
         case 0: return logf(1.f + f);
-        case 1: return logf(1.f + sd);
-        case 2: return logf(1.f + cum);
+        case 1: return logf(1.f + d);
+        case 2: return logf(1.f + c);
         case 3: return logf(1.f + q);
         case 4: return logf(1.f + k);
         case 5: return nnz / n;
         case 6: return logf((f + 1.f) / n);
-        case 7: return logf((sd + 1.f) / (nnz + 1.f));
-        case 8: return logf((cum + 1.f) / n);
-        case 9: return logf((sd + 1.f) / (f + 1.f));
+        case 7: return logf((d + 1.f) / (nnz + 1.f));
+        case 8: return logf((u + 1.f) / (n * q));
+        case 9: return logf((d + 1.f) / (f + 1.f));
         case 10: return logf((f + 1.f) * q / n);
-        case 11: return logf((sd + 1.f) / (nnz - sd + 1.f));
+        case 11: return logf((d + 1.f) / (nnz - d + 1.f));
         default: return 0.f;
     }
 }
@@ -815,12 +839,17 @@ __device__ __forceinline__ float ms_feature(uint32_t i, float f, float sd, float
 __global__ void k_ms_decide(MsLevel p, uint32_t k) {
     const uint32_t t = k % 3;
     const uint32_t f = p.cnt[t];
-    unsigned long long sd = 0;
-    for (int g = 0; g < kMsDegGroups; ++g) sd += p.mstat[(t * kMsDegGroups + g) * 8];
-    const unsigned long long cum = p.mstat[kMsCumF];
+    unsigned long long d = 0, c = 0, r = 0;
+    for (int g = 0; g < kMsDegGroups; ++g) {
+        d += p.mstat[ms_line((int)t, g)];
+        c += p.mstat[ms_line(kMsCumSlot, g)];
+        r += p.mstat[ms_line(kMsCumSlot, g) + 1];
+    }
+    const unsigned long long pairs = (unsigned long long)p.n * p.nq;
+    const unsigned long long u = pairs > r ? pairs - r : 0ull;
     uint32_t v = 0;
     if (p.mlp != nullptr) {
-        const float feat = ms_feature(__lane_id(), (float)f, (float)sd, (float)cum, (float)p.nq,
+        const float feat = ms_feature(__lane_id(), (float)f, (float)d, (float)c, (float)u, (float)p.nq,
                                       (float)k, (float)p.n, (float)p.out_ptr[p.n]);
         const int b = mlp_argmin(p.mlp, feat, 2);
         v = b < 0 ? 0u : (uint32_t)b;

@@ -244,19 +244,21 @@ MS_WEIGHTS = os.path.join(HERE, "selector_ms_weights.json")
 MS_DIRECTIONS = ("push", "pull")
 
 
-def ms_features(frontier, frontier_edges, listed, sources, level, n, nnz) -> np.ndarray:
+def ms_features(frontier, frontier_edges, listed, unsettled, sources, level, n, nnz) -> np.ndarray:
     """The twelve multi-source level features (the device's definitions), float64
     [rows, 12]: f = |F_k|, d = out-degree sum over F_k, c = summed union-frontier
-    sizes of levels 0..k, q = number of sources, k, n, nnz."""
+    sizes of levels 0..k, u = (vertex, source) pairs not reached through level k,
+    q = number of sources, k, n, nnz."""
     f = np.asarray(frontier, np.float64)
     d = np.asarray(frontier_edges, np.float64)
     c = np.asarray(listed, np.float64)
+    u = np.asarray(unsettled, np.float64)
     q = np.asarray(sources, np.float64)
     k = np.asarray(level, np.float64)
     n = np.full(f.shape, float(n)) if np.ndim(n) == 0 else np.asarray(n, np.float64)
     nnz = np.full(f.shape, float(nnz)) if np.ndim(nnz) == 0 else np.asarray(nnz, np.float64)
     return np.stack([np.log1p(f), np.log1p(d), np.log1p(c), np.log1p(q), np.log1p(k), nnz / n,
-                     np.log((f + 1) / n), np.log((d + 1) / (nnz + 1)), np.log((c + 1) / n),
+                     np.log((f + 1) / n), np.log((d + 1) / (nnz + 1)), np.log((u + 1) / (n * q)),
                      np.log((d + 1) / (f + 1)), np.log((f + 1) * q / n),
                      np.log((d + 1) / (nnz - d + 1))], axis=-1)
 
@@ -291,7 +293,7 @@ def ms_profile(G, sources: Sequence[int], reps: int = 2, out=None) -> List[Dict]
     for i in range(cnt.value):
         r = recs[i]
         d = res.setdefault(r.level, dict(level=r.level, frontier=r.frontier, frontier_edges=r.frontier_edges,
-                                         listed=r.unvisited, sources=r.unvisited_edges,
+                                         listed=r.unvisited, unsettled=r.unvisited_edges, sources=nq,
                                          times=[math.nan] * N_OUT))
         d["times"][r.variant] = r.time_us
     return [res[k] for k in sorted(res)]
@@ -303,8 +305,8 @@ def ms_dataset(levels: Sequence[Dict], n: int, nnz: int) -> Tuple[np.ndarray, np
     if not levels:
         return np.zeros((0, N_IN)), np.zeros((0, N_OUT)), np.zeros((0, N_OUT))
     X = ms_features([d["frontier"] for d in levels], [d["frontier_edges"] for d in levels],
-                    [d["listed"] for d in levels], [d["sources"] for d in levels],
-                    [d["level"] for d in levels], n, nnz)
+                    [d["listed"] for d in levels], [d["unsettled"] for d in levels],
+                    [d["sources"] for d in levels], [d["level"] for d in levels], n, nnz)
     T = np.array([d["times"] for d in levels], dtype=np.float64)
     T[:, 2] = np.nan
     M = np.isfinite(T) & (T > 0)

@@ -12,7 +12,8 @@ so the searches of different workers overlap on the device:
     query and every other waiting query on the same graph (up to max_batch), so
     queries that arrived while others ran join the next batch;
   * a batch of several queries on one graph runs as one multi-source search
-    (64 sources per mask word) when the graph is small enough for that to pay,
+    (64 sources per mask word, push or pull per level from the learned
+    direction network) when the graph is shallow enough for that to pay,
     otherwise as consecutive single searches with the learned per-level selector.
 
 Every query's result is the search's own (level, parent): the same bits alone
@@ -106,8 +107,13 @@ def poisson_arrivals(rate_qps: float, count: int, seed: int) -> np.ndarray:
 
 
 def latency_stats(queries: Sequence[Query]) -> Dict[str, float]:
+    """Latency percentiles over the completed queries (NaN when none completed;
+    failed queries are counted, never timed)."""
     ok = [q for q in queries if q.error is None and q.done >= 0]
-    lat = np.array([q.done - q.arrival for q in ok]) if ok else np.zeros(1)
+    if not ok:
+        nan = float("nan")
+        return dict(completed=0, failed=len(queries), p50_ms=nan, p99_ms=nan, mean_ms=nan)
+    lat = np.array([q.done - q.arrival for q in ok])
     return dict(completed=len(ok), failed=len(queries) - len(ok),
                 p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
                 mean_ms=float(lat.mean() * 1e3))
@@ -156,14 +162,16 @@ class GpuExecutor:
 
     def __init__(self, graphs: Dict[str, object], mode: str = "batched", selector=None,
                  multi_source_max_n: int = 1 << 23, keep_results: bool = False,
-                 params: Optional[Dict[str, Dict]] = None, shallow: Optional[Dict[str, bool]] = None):
+                 params: Optional[Dict[str, Dict]] = None, shallow: Optional[Dict[str, bool]] = None,
+                 ms_selector=None):
         import torch
         import paper_1906_03113_amd as P
         self.P = P
         self.torch = torch
         self.graphs = graphs
         self.mode = mode                       # "plain": push only, one query at a time
-        self.selector = selector
+        self.selector = selector               # single-source per-level variant network
+        self.ms_selector = ms_selector         # multi-source per-level direction network
         self.ms_max_n = multi_source_max_n
         self.keep = keep_results
         self.params = params or {}             # per-graph launch parameters (autotuned)
@@ -196,7 +204,9 @@ class GpuExecutor:
             if self.mode == "plain":
                 outs = [P.bfs(G, src, variant="push", stream=s) for src in srcs]
             elif self.multi_source(b.graph, len(srcs)):
-                lv, pa = P.bfs_batch(G, srcs, stream=s, variant="heuristic")
+                kw = dict(variant="learned", selector=self.ms_selector) if self.ms_selector is not None \
+                    else dict(variant="heuristic")
+                lv, pa = P.bfs_batch(G, srcs, stream=s, **kw)
                 outs = list(zip(lv, pa))
             else:
                 kw = dict(variant="learned", selector=self.selector) if self.selector is not None \
@@ -295,7 +305,7 @@ def run_load(executor: GpuExecutor, graph_names: Sequence[str], sources: Dict[st
     finally:
         srv.close()
     st = latency_stats(qs)
-    st.update(rate_qps=rate_qps, queries=count, wall_s=wall, achieved_qps=count / wall,
+    st.update(rate_qps=rate_qps, queries=count, wall_s=wall, achieved_qps=st["completed"] / wall,
               peak_inflight_mb=srv.sched.peak_bytes / 1e6)
     fams = sorted({family(q.graph) for q in qs})
     st["by_family"] = {f: latency_stats([q for q in qs if family(q.graph) == f]) for f in fams}
@@ -371,27 +381,35 @@ def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector):
 
 
 def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers=4, seed=5,
-               log=None, budget_bytes=64 << 30):
+               log=None, budget_bytes=64 << 30, seconds=None):
     """Plain (push only, one query at a time) vs batched + learned at fixed
-    fractions of the plain path's saturation rate; returns a dict of results."""
+    fractions of the plain path's saturation rate; returns a dict of results.
+    Each rate and path serves `queries` Poisson arrivals, or with `seconds`
+    set, those arriving within that many seconds (at most `queries`, at least 40)."""
+    from concurrent.futures import ThreadPoolExecutor
     import torch
-    import graphgen
     import paper_1906_03113_amd as P
     from . import selector as S
     torch.cuda.init()
     Gs, srcs = {}, {}
-    for name, build in resident_set(which).items():
-        g = build()
-        Gs[name] = P.Graph.from_graphgen(g)
-        srcs[name] = np.nonzero(g.out_degree() > 0)[0]
-        if log:
-            log(f"[serve] resident {name}: n={g.n} nnz={g.nnz}")
-        del g
+    builders = resident_set(which)
+    # the graphs are generated on host threads (the generator's array work
+    # releases the interpreter lock) and uploaded one at a time
+    with ThreadPoolExecutor(8) as ex:
+        futs = {name: ex.submit(build) for name, build in builders.items()}
+        for name in builders:
+            g = futs.pop(name).result()
+            Gs[name] = P.Graph.from_graphgen(g)
+            srcs[name] = np.nonzero(g.out_degree() > 0)[0]
+            if log:
+                log(f"[serve] resident {name}: n={g.n} nnz={g.nnz}")
+            del g
     names = sorted(Gs)
     sel = S.load_weights()
+    ms_sel = S.load_weights(S.MS_WEIGHTS)
     params, shallow = launch_params(Gs, srcs, sel)
     plain = GpuExecutor(Gs, mode="plain")
-    fast = GpuExecutor(Gs, mode="batched", selector=sel, params=params, shallow=shallow)
+    fast = GpuExecutor(Gs, mode="batched", selector=sel, params=params, shallow=shallow, ms_selector=ms_sel)
     # saturation of the plain path: back-to-back queries, one worker
     rng = np.random.default_rng(seed)
     warm = [Query(i, names[int(rng.integers(len(names)))], 0, 0.0) for i in range(len(names))]
@@ -411,9 +429,10 @@ def experiment(which="small", queries=400, rates=(0.25, 0.5, 0.8, 0.95), workers
     res = {"saturation_qps_plain": sat_qps, "graphs": names, "rates": {}}
     for frac in rates:
         rate = frac * sat_qps
-        r_plain = run_load(plain, names, srcs, rate, queries, seed, budget_bytes, workers=1, max_batch=1,
+        count = queries if seconds is None else max(40, min(queries, int(rate * seconds)))
+        r_plain = run_load(plain, names, srcs, rate, count, seed, budget_bytes, workers=1, max_batch=1,
                            progress=log)
-        r_fast = run_load(fast, names, srcs, rate, queries, seed, budget_bytes, workers=workers,
+        r_fast = run_load(fast, names, srcs, rate, count, seed, budget_bytes, workers=workers,
                           progress=log)
         res["rates"][str(frac)] = {"plain": r_plain, "batched_learned": r_fast}
         if log:
@@ -437,10 +456,12 @@ def main(argv=None):
     ap.add_argument("--set", default="small", choices=["small", "full"])
     ap.add_argument("--queries", type=int, default=2000)
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--seconds", type=float, default=None,
+                    help="serve the arrivals of this many seconds per rate (at most --queries)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
-    res = experiment(a.set, a.queries, workers=a.workers, log=log)
+    res = experiment(a.set, a.queries, workers=a.workers, log=log, seconds=a.seconds)
     txt = json.dumps(res)
     if a.out:
         with open(a.out, "w") as f:

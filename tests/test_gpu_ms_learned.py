@@ -155,11 +155,13 @@ def test_ms_profile_levels(P, graphs, name, nq):
     deg = np.diff(g.ptr.astype(np.int64))
     listed = 0
     for d in levels:
-        F = np.any(W == d["level"], axis=0)
+        k = d["level"]
+        F = np.any(W == k, axis=0)
         listed += int(F.sum())
         assert d["frontier"] == int(F.sum())
         assert d["frontier_edges"] == int(deg[F].sum())
         assert d["listed"] == listed
+        assert d["unsettled"] == g.n * nq - int(((W >= 0) & (W <= k)).sum())
         assert d["sources"] == nq
         assert all(np.isfinite(t) and t > 0 for t in d["times"][:2])
     X, T, M = S.ms_dataset(levels, g.n, g.nnz)

@@ -60,6 +60,18 @@ def test_failing_batches_fail_only_their_queries():
     assert latency_stats(qs)["failed"] == 10
 
 
+def test_latency_stats_without_completions_are_nan():
+    """No completed query: the percentiles are undefined (NaN), never 0 ms."""
+    qs = [Query(i, "g", i, 0.0) for i in range(4)]
+    for q in qs:
+        q.error = "device error"
+        q.done = 1.0
+    st = latency_stats(qs)
+    assert st["completed"] == 0 and st["failed"] == 4
+    assert all(np.isnan(st[k]) for k in ("p50_ms", "p99_ms", "mean_ms"))
+    assert np.isnan(latency_stats([])["p99_ms"])
+
+
 def test_poisson_arrivals():
     a = poisson_arrivals(200.0, 20000, seed=5)
     assert np.all(np.diff(a) > 0)
