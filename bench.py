@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--sources", type=int, default=0,
+                    help="use only the first N of the workload's sources (0 = all; profiling runs)")
     ap.add_argument("--variant", default="push")
     ap.add_argument("--loop", default="host")
     ap.add_argument("--levels-per-sync", type=int, default=0)
@@ -187,6 +189,8 @@ def main():
     g = graphgen.workload(key)
     log(f"[bench] graph n={g.n} nnz={g.nnz} directed={g.directed} ({time.time() - t0:.1f}s)")
     sources = np.array([0], np.int32) if sseed is None else graphgen.pick_sources(g, nsrc, sseed)
+    if args.sources > 0:
+        sources = sources[:args.sources]
     torch.cuda.set_device(0)
     G = P.Graph.from_graphgen(g)
     log(f"[bench] resident on GPU: {G.device_bytes() / 1e6:.1f} MB")
