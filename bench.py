@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--sources", type=int, default=0,
                     help="use only the first N of the workload's sources (0 = all; profiling runs)")
     ap.add_argument("--variant", default="push")
+    ap.add_argument("--push-impl", default="auto", choices=["auto", "list", "sliced", "claim"])
     ap.add_argument("--loop", default="host")
     ap.add_argument("--levels-per-sync", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
@@ -199,7 +200,7 @@ def main():
     parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
     kw = dict(variant=args.variant, loop=args.loop, levels_per_sync=args.levels_per_sync,
               grid_blocks=args.grid_blocks, heavy_degree=args.heavy_degree,
-              chunk_edges=args.chunk_edges)
+              chunk_edges=args.chunk_edges, push_impl=args.push_impl)
     timek = (args.loop == "host") and not args.no_time_kernels
 
     # edge counts of each search (from the search's own output), and the level
@@ -283,13 +284,16 @@ def main():
         bytes_total = float(sum(b_search))
         kern_us = level_us + init_us
         ach = bytes_total / (kern_us * 1e-6) / 1e9
-        sliced = args.variant == "push" and g.n <= 4 * 32768 * 32 and args.loop in ("host", "graph")
-        kname = "k_sl_level" if sliced else "k_level"
+        sliced = (args.variant == "push" and g.n <= 4 * 32768 * 32 and args.loop in ("host", "graph")
+                  and args.push_impl in ("auto", "sliced"))
+        kname = ("k_sl_level" if sliced else
+                 "k_cw_narrow / k_cw_wide" if args.push_impl == "claim" else "k_level")
         traffic = measured_traffic() if (args.workload == "rmat22" and sliced) else None
         per_search = [i["kernel_us"] + i["init_us"] for i in infos]
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": kname, "init_kernel": "k_sl_init" if sliced else "k_init",
+                    "kernel": kname,
+                    "init_kernel": "k_sl_init" if sliced else "k_cw_fill" if args.push_impl == "claim" else "k_init",
                     "algorithmic_bytes_per_search": round(bytes_total / nsearch),
                     "kernel_us_per_search": round(kern_us / nsearch, 2),
                     "level_kernel_us_per_search": round(level_us / nsearch, 2),

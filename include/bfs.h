@@ -132,12 +132,27 @@ typedef struct bfs_run_options {
  *                    frontier) when the next level expands it.  Needs
  *                    n <= 4 * 2^20 and the host or graph loop (BFS_EINVAL
  *                    otherwise).
+ *   BFS_PUSH_CLAIM   one 64-bit word per vertex, (level << 32) | parent, its
+ *                    top bit set while unreached: a frontier column offers
+ *                    ((k + 1) << 32) | u to each of its rows by atomicMin, so
+ *                    one atomic masks the visited rows (smaller words) and
+ *                    keeps the smallest frontier in-neighbour (Lemma 1's
+ *                    min-select), and the offer that finds the top bit set
+ *                    lists the row (Theorem 2's single claim).  Levels whose frontier
+ *                    holds at most 8192 columns and 2^16 entries run in one
+ *                    workgroup, many levels per launch, the frontier in LDS;
+ *                    wider levels one launch each over the whole grid.  For
+ *                    deep, thin searches (grids, road-like graphs), where the
+ *                    other forms pay a grid-wide launch per level.  Needs
+ *                    variant PUSH and the host loop (BFS_EINVAL otherwise);
+ *                    fills no trace.
  *   BFS_PUSH_AUTO    sliced when it applies, the list form otherwise.
  */
 enum {
     BFS_PUSH_AUTO = 0,
     BFS_PUSH_LIST = 1,
-    BFS_PUSH_SLICED = 2
+    BFS_PUSH_SLICED = 2,
+    BFS_PUSH_CLAIM = 3
 };
 
 /*
@@ -204,11 +219,17 @@ bfs_status bfs_run(bfs_graph *g, int32_t source,
  * push when an output is not finite and on every level when opt->selector is
  * NULL; from level 16 on, a push decision covers the next 8 levels.  With
  * opt->trace set, record k holds level k's direction (variant 0 push, 1 pull)
- * and, where the host read it, the union frontier's size.  Queries on
- * different graphs are run one after another on the stream.
+ * and, where the host read it, the union frontier's size.
+ * Queries on different graphs (any mix, repeats allowed) run together, as one
+ * search over the block-diagonal matrix of their graphs with one root per
+ * block, without copying a graph: the library gives query q the vertex ids
+ * [base_q, base_q + n_q) of a virtual vertex space and runs the claim-word
+ * push (BFS_PUSH_CLAIM) over all of them, one launch per level for every
+ * query (or one narrow launch for many levels while the joint frontier is
+ * small); they need variant PUSH and the host loop.  One query is bfs_run.
  * The result for query q is bit-identical to bfs_run(graphs[q], sources[q]).
- * workspace: bfs_workspace_size(graphs[0], num_queries, 0) bytes when all
- * graphs are equal; otherwise the largest bfs_workspace_size(graphs[q], 1, 0).
+ * workspace: bfs_batch_workspace_size(num_queries, graphs) bytes, 256-byte
+ * aligned.
  * Errors: BFS_EINVAL, BFS_ERANGE, BFS_EHIP.
  */
 bfs_status bfs_run_batch(int32_t num_queries,
@@ -216,6 +237,9 @@ bfs_status bfs_run_batch(int32_t num_queries,
                          int32_t *const *level, int32_t *const *parent,
                          bfs_run_options *opt,
                          void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Workspace bytes of bfs_run_batch for these queries' graphs (0 on a bad argument). */
+size_t bfs_batch_workspace_size(int32_t num_queries, bfs_graph *const *graphs);
 
 /*
  * A search started from several roots at once (x_1 = sum of e_r): the level

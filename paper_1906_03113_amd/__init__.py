@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import BfsError, LOOPS, VARIANTS, VARIANT_NAMES, LevelRecord, RunOptions
 
-__all__ = ["Graph", "bfs", "bfs_static", "bfs_batch", "bfs_batch_vm", "batch_vm_workspace_size", "bfs_roots",
+__all__ = ["Graph", "bfs", "bfs_static", "bfs_batch", "bfs_batch_vm", "batch_vm_workspace_size",
+           "batch_workspace_size", "bfs_roots",
            "bfs_compare", "compare_workspace_size", "masked_spmspv",
            "spmspv_workspace_size", "BfsError", "VARIANTS", "LOOPS",
            "Workspace", "make_options"]
@@ -235,6 +236,12 @@ def bfs_roots(g: Graph, roots: Sequence[int], variant="push", loop="host", level
     return level, parent
 
 
+def batch_workspace_size(graphs) -> int:
+    """Workspace bytes bfs_batch needs for queries on these graphs (one per query)."""
+    H = (ctypes.c_void_p * len(graphs))(*[gr.handle for gr in graphs])
+    return int(_lib.lib().bfs_batch_workspace_size(len(graphs), H))
+
+
 def _ms_trace(o: RunOptions, recs) -> list:
     """The multi-source trace: level k's direction and, where the host read it,
     the union frontier's size (0 elsewhere)."""
@@ -257,11 +264,10 @@ def bfs_batch(graphs, sources: Sequence[int], variant="push", loop="host", level
         levels = [t.empty(gr.n, dtype=t.int32, device="cuda") for gr in graphs]
     if parents is None:
         parents = [t.empty(gr.n, dtype=t.int32, device="cuda") for gr in graphs]
-    same = all(gr is graphs[0] for gr in graphs)
-    need = graphs[0].workspace_size(nq) if same else max(gr.workspace_size(1) for gr in graphs)
+    H = (ctypes.c_void_p * nq)(*[gr.handle for gr in graphs])
+    need = batch_workspace_size(graphs)
     if workspace is None or not workspace.fits(need):
         workspace = Workspace(need)
-    H = (ctypes.c_void_p * nq)(*[gr.handle for gr in graphs])
     S = (ctypes.c_int32 * nq)(*[int(s) for s in sources])
     Lp = (ctypes.c_void_p * nq)(*[x.data_ptr() for x in levels])
     Pp = (ctypes.c_void_p * nq)(*[x.data_ptr() for x in parents])

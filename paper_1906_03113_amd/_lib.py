@@ -13,7 +13,7 @@ BFS_DIRECTED, BFS_INPUT_ON_DEVICE, BFS_VALIDATE_TRANSPOSE = 1, 2, 4
 VARIANTS = {"push": 0, "pull": 1, "bitmap": 2, "learned": 3, "heuristic": 4, "short_circuit": 5}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 LOOPS = {"host": 0, "graph": 1, "persistent": 2}
-PUSH_IMPLS = {"auto": 0, "list": 1, "sliced": 2}
+PUSH_IMPLS = {"auto": 0, "list": 1, "sliced": 2, "claim": 3}
 COMPARE = {"spmv": 0, "spmspv": 1, "spmmspv": 2}
 SEMIRINGS = {"boolean": 0, "arithmetic": 1, "min_plus": 2, "min_select": 3}
 
@@ -68,6 +68,8 @@ def lib():
     L.bfs_run_roots.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(RunOptions), vp, sz, vp]
     L.bfs_roots_workspace_size.argtypes = [vp, i32]
     L.bfs_roots_workspace_size.restype = sz
+    L.bfs_batch_workspace_size.argtypes = [i32, vp]
+    L.bfs_batch_workspace_size.restype = sz
     L.bfs_status_string.argtypes = [i32]
     L.bfs_status_string.restype = ctypes.c_char_p
     L.bfs_last_error_detail.argtypes = []

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbfs.so")
-SOURCES = ["bfs_kernels.hip", "bfs_slice.hip", "bfs_msbfs.hip", "bfs_mlp.hip", "bfs_compare.hip", "bfs_spmspv.hip", "bfs_static.hip", "bfs_host.cpp"]
+SOURCES = ["bfs_kernels.hip", "bfs_slice.hip", "bfs_msbfs.hip", "bfs_mlp.hip", "bfs_compare.hip", "bfs_spmspv.hip", "bfs_static.hip", "bfs_claim.hip", "bfs_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions are disabled for every HIP translation unit.

@@ -290,6 +290,30 @@ MsLayout ms_layout(int32_t n, int32_t nq, bool staged) {
     L.total = off;
     return L;
 }
+
+CwLayout cw_layout(uint64_t V, uint64_t nnz, uint32_t nq) {
+    CwLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    // chunks of one level: every long column (at least kCwLong entries) has
+    // ceil(deg / kCwChunk) <= deg / kCwChunk + 1 of them
+    const size_t chunks = (size_t)(nnz / kCwChunk + nnz / kCwLong + 1);
+    L.q = take((size_t)nq * sizeof(CwQuery));
+    L.bases = take(((size_t)nq + 1) * 4);
+    L.st = take(sizeof(CwState));
+    L.cw = take((size_t)V * 8);
+    L.s0 = take((size_t)V * 4);
+    L.l0 = take((size_t)V * 4);
+    L.b0 = take((size_t)V * 4);
+    L.c0 = take(chunks * 4);
+    L.s1 = take((size_t)V * 4);
+    L.l1 = take((size_t)V * 4);
+    L.b1 = take((size_t)V * 4);
+    L.c1 = take(chunks * 4);
+    L.spill = take((size_t)V * 4);
+    L.total = off;
+    return L;
+}
 }  // namespace bfsi
 
 namespace {
@@ -578,7 +602,194 @@ bfs_status run_levels(bfs_graph *g, LevelParams &P, const RunCfg &c, hipStream_t
 size_t ws_single(const bfs_graph *g) {
     const size_t list = ws_layout(g->n, g->nnz, kHeavyFloor).total;
     const size_t sliced = g->sl_S ? sl_layout(g->sl_S * g->sl_sw).total : 0;
-    return std::max(list, sliced);
+    const size_t claim = cw_layout((uint64_t)g->n, g->nnz, 1).total;
+    return std::max(std::max(list, sliced), claim);
+}
+
+// ---------------------------------------------------------------------------
+// The claim-word push (bfs_claim.hip): one query, or many on any graphs
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kCwLevelsPerLaunch = 4096;    // narrow: levels per launch at most
+// The narrow kernel runs from a frontier of at most kCwNarrowEnter columns
+// until the next one holds more than kCwNarrowExit columns or a level more than
+// kCwNarrowEdgesMax entries: one workgroup issues about one memory request per
+// cycle, so beyond a few thousand requests per level the grid-wide launch
+// (about 14 us of dependent memory round trips per level) is faster.
+constexpr uint32_t kCwNarrowEnter = 128;
+constexpr uint32_t kCwNarrowExit = 512;
+constexpr uint32_t kCwNarrowEdgesMax = 4096;
+constexpr uint32_t kCwWidePerSync = 32;          // wide levels between two reads of the counts, at most
+constexpr uint32_t kCwWideMinGrid = 64;          // workgroups of a wide launch at least
+
+struct ClaimQuery {
+    const bfs_graph *g;
+    int32_t source;
+    int32_t *level, *parent;
+};
+
+uint64_t claim_vertices(const ClaimQuery *qs, int32_t nq, uint64_t *nnz) {
+    uint64_t V = 0, E = 0;
+    for (int32_t q = 0; q < nq; ++q) {
+        V += (uint64_t)qs[q].g->n;
+        E += qs[q].g->nnz;
+    }
+    if (nnz) *nnz = E;
+    return V;
+}
+
+size_t claim_workspace(const ClaimQuery *qs, int32_t nq) {
+    uint64_t E = 0;
+    const uint64_t V = claim_vertices(qs, nq, &E);
+    return cw_layout(V, E, (uint32_t)nq).total;
+}
+
+// The searches of qs together: the narrow kernel while a level fits one
+// workgroup, the wide one otherwise (a level it hands back unexpanded runs
+// wide), the frontier counts read back after every launch.
+bfs_status run_claim(const ClaimQuery *qs, int32_t nq, void *workspace, size_t ws_bytes, hipStream_t s,
+                     int cus, bfs_run_options *opt) {
+    uint64_t E = 0;
+    const uint64_t V = claim_vertices(qs, nq, &E);
+    if (V >= 0xFFFFFFFFull) return fail(BFS_EINVAL, "the queries hold %llu vertices (at most 2^32 - 2)",
+                                        (unsigned long long)V);
+    if ((uint32_t)nq > kCwMaxQueries) return fail(BFS_EINVAL, "%d queries (at most %u)", nq, kCwMaxQueries);
+    const CwLayout L = cw_layout(V, E, (uint32_t)nq);
+    if (ws_bytes < L.total) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    char *b = (char *)workspace;
+    std::vector<CwQuery> hq((size_t)nq);
+    std::vector<uint32_t> hb((size_t)nq + 1);
+    uint32_t base = 0, max_n = 0;
+    for (int32_t q = 0; q < nq; ++q) {
+        CwQuery &d = hq[(size_t)q];
+        d.out_ptr = qs[q].g->out_ptr;
+        d.out_idx = qs[q].g->out_idx;
+        d.level = qs[q].level;
+        d.parent = qs[q].parent;
+        d.base = base;
+        d.n = (uint32_t)qs[q].g->n;
+        d.source = qs[q].source;
+        d.pad = 0;
+        hb[(size_t)q] = base;
+        base += d.n;
+        max_n = std::max(max_n, d.n);
+    }
+    hb[(size_t)nq] = base;
+    CwParams P{};
+    P.q = (const CwQuery *)(b + L.q);
+    P.bases = (const uint32_t *)(b + L.bases);
+    P.nq = (uint32_t)nq;
+    P.V = (uint32_t)V;
+    P.max_n = max_n;
+    P.cw = (unsigned long long *)(b + L.cw);
+    P.lists[0] = CwLists{(uint32_t *)(b + L.s0), (uint32_t *)(b + L.l0), (uint32_t *)(b + L.b0),
+                         (uint32_t *)(b + L.c0)};
+    P.lists[1] = CwLists{(uint32_t *)(b + L.s1), (uint32_t *)(b + L.l1), (uint32_t *)(b + L.b1),
+                         (uint32_t *)(b + L.c1)};
+    P.spill = (uint32_t *)(b + L.spill);
+    P.st = (CwState *)(b + L.st);
+    HIP_TRY(hipMemcpyAsync(b + L.q, hq.data(), hq.size() * sizeof(CwQuery), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b + L.bases, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, s));
+    const bool tk = opt && opt->time_kernels;
+    std::vector<hipEvent_t> evs;
+    auto free_events = [&]() {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    };
+    // every launch, bracketed by two events when timing
+    auto launch = [&](auto &&fn) -> hipError_t {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tk) {
+            hipError_t e = hipEventCreate(&e0);
+            if (e != hipSuccess) return e;
+            evs.push_back(e0);
+            if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+            evs.push_back(e1);
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+        }
+        hipError_t e = fn();
+        if (e == hipSuccess && tk) e = hipEventRecord(e1, s);
+        return e;
+    };
+    auto run = [&](uint32_t &levels, uint32_t &launches) -> bfs_status {
+        HIP_TRY(launch_cw_init(P, s));
+        CwState hst;
+        auto read_state = [&]() -> hipError_t {
+            hipError_t e = hipMemcpyAsync(&hst, P.st, sizeof hst, hipMemcpyDeviceToHost, s);
+            return e == hipSuccess ? hipStreamSynchronize(s) : e;
+        };
+        HIP_TRY(read_state());
+        uint32_t k = 0;
+        bool narrow_refused = false;          // the narrow kernel handed level k back
+        const uint32_t wide_max = 8u * (uint32_t)(cus > 0 ? cus : 256);
+        // wide levels between two reads of the counts: as given, else 2, 4,
+        // ... up to kCwWidePerSync as the search goes on (a shallow search
+        // launches few levels past its end, a deep one syncs rarely)
+        const uint32_t fixed_sync = opt ? opt->levels_per_sync : 0u;
+        uint32_t per_sync = fixed_sync ? fixed_sync : 2u;
+        for (uint64_t guard = 0;; ++guard) {
+            if (guard > V + 4) return fail(BFS_EHIP, "claim-word loop did not terminate");
+            const uint32_t *c = hst.cnt[k % 3];
+            const uint32_t nf = c[0] + c[1];
+            if (nf == 0) break;
+            if (nf <= kCwNarrowEnter && !narrow_refused) {
+                HIP_TRY(launch([&]() {
+                    return launch_cw_narrow(P, k, kCwLevelsPerLaunch, kCwNarrowExit, kCwNarrowEdgesMax, s);
+                }));
+                ++launches;
+                HIP_TRY(read_state());
+                if (hst.level == k) {
+                    narrow_refused = true;
+                    continue;
+                }
+                k = hst.level;
+                if (hst.done) break;
+                continue;
+            }
+            // per_sync wide levels back to back, sized for twice this level's
+            // frontier; levels launched past the end of the search find no
+            // frontier and change nothing
+            const uint32_t waves = (c[0] + 63) / 64 + c[2];
+            const uint32_t grid = std::min(wide_max, std::max(kCwWideMinGrid, (2 * waves + 3) / 4));
+            for (uint32_t i = 0; i < per_sync; ++i) {
+                HIP_TRY(launch([&]() { return launch_cw_wide(P, k + i, grid, s); }));
+                ++launches;
+            }
+            HIP_TRY(read_state());
+            const uint32_t *cn = hst.cnt[(k + per_sync) % 3];
+            if (cn[0] + cn[1] == 0) {
+                k = hst.last + 1;              // the level after the deepest frontier
+                break;
+            }
+            k += per_sync;
+            if (!fixed_sync) per_sync = std::min(2 * per_sync, kCwWidePerSync);
+            narrow_refused = false;
+        }
+        levels = k;
+        HIP_TRY(launch_cw_out(P, s));
+        return BFS_OK;
+    };
+    uint32_t levels = 0, launches = 0;
+    bfs_status st = run(levels, launches);
+    if (st == BFS_OK && tk) {
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(BFS_EHIP, "stream synchronise failed");
+        float total = 0.f;
+        for (size_t i = 0; st == BFS_OK && i + 1 < evs.size(); i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) != hipSuccess) st = fail(BFS_EHIP, "event time failed");
+            total += ms * 1000.f;
+        }
+        if (st == BFS_OK) {
+            opt->kernel_us = total;
+            opt->launches = launches;
+        }
+    }
+    free_events();
+    if (st != BFS_OK) return st;
+    if (opt) {
+        opt->levels = levels;
+        opt->trace_count = 0;
+    }
+    return BFS_OK;
 }
 
 // The sliced push's launch size: 8 * S * R workgroups, R = compute units per
@@ -592,12 +803,15 @@ uint32_t sl_grid(const bfs_graph *g) {
 
 bool sliced_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
     const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
-    return c.policy == kPush && impl != BFS_PUSH_LIST && g->sl_S != 0 && c.loop != BFS_LOOP_PERSISTENT;
+    return c.policy == kPush && (impl == BFS_PUSH_AUTO || impl == BFS_PUSH_SLICED) && g->sl_S != 0 &&
+           c.loop != BFS_LOOP_PERSISTENT;
 }
 
 bfs_status check_push_impl(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
     const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
-    if (impl > BFS_PUSH_SLICED) return fail(BFS_EINVAL, "unknown push_impl %u", impl);
+    if (impl > BFS_PUSH_CLAIM) return fail(BFS_EINVAL, "unknown push_impl %u", impl);
+    if (impl == BFS_PUSH_CLAIM && (c.policy != kPush || c.loop != BFS_LOOP_HOST))
+        return fail(BFS_EINVAL, "the claim-word push needs variant PUSH and the host loop");
     if (impl == BFS_PUSH_SLICED && !sliced_applies(g, c, opt))
         return fail(BFS_EINVAL, "the sliced push needs variant PUSH, the host or graph loop and "
                                 "n <= %u (n = %d)", bfsi::kSlMaxSlices * bfsi::kSlMaxSliceWords * 32u, g->n);
@@ -827,6 +1041,10 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
     st = check_push_impl(g, c, opt);
     if (st != BFS_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (opt && opt->push_impl == BFS_PUSH_CLAIM) {
+        const ClaimQuery q{g, source, level, parent};
+        return run_claim(&q, 1, workspace, ws_bytes, s, g->cus, opt);
+    }
     if (sliced_applies(g, c, opt))
         return run_sliced(g, source, 1, nullptr, level, parent, c, workspace, s, opt);
     LevelParams P;
@@ -1078,15 +1296,33 @@ extern "C" bfs_status bfs_run_batch(int32_t num_queries, bfs_graph *const *graph
         return run_multi_source(graphs[0], num_queries, sources, level, parent, opt, workspace,
                                 (hipStream_t)hip_stream);
     }
+    if (num_queries == 1)
+        return bfs_run(graphs[0], sources[0], level[0], parent[0], opt, workspace, ws_bytes, hip_stream);
+    // queries on different graphs: every search at once
+    // through the claim-word push, one launch per level (or one narrow
+    // launch for many levels) for all of them
+    if (opt && opt->variant != kPush) return fail(BFS_EINVAL, "queries on different graphs run the push only");
+    if (opt && opt->loop_mode != BFS_LOOP_HOST) return fail(BFS_EINVAL, "queries on different graphs run the host loop");
+    std::vector<ClaimQuery> qs((size_t)num_queries);
+    int cus = 0;
     for (int32_t q = 0; q < num_queries; ++q) {
-        const size_t need = bfs_workspace_size(graphs[q], 1, 0);
-        if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, query %d needs %zu", ws_bytes, q, need);
+        qs[(size_t)q] = ClaimQuery{graphs[q], sources[q], level[q], parent[q]};
+        cus = std::max(cus, graphs[q]->cus);
     }
+    return run_claim(qs.data(), num_queries, workspace, ws_bytes, (hipStream_t)hip_stream, cus, opt);
+}
+
+extern "C" size_t bfs_batch_workspace_size(int32_t num_queries, bfs_graph *const *graphs) {
+    if (num_queries <= 0 || !graphs) return 0;
+    bool same = true;
     for (int32_t q = 0; q < num_queries; ++q) {
-        bfs_status st = bfs_run(graphs[q], sources[q], level[q], parent[q], opt, workspace, ws_bytes, hip_stream);
-        if (st != BFS_OK) return st;
+        if (!graphs[q]) return 0;
+        same = same && graphs[q] == graphs[0];
     }
-    return BFS_OK;
+    if (same && num_queries > 1) return bfs_workspace_size(graphs[0], num_queries, 0);
+    std::vector<ClaimQuery> qs((size_t)num_queries);
+    for (int32_t q = 0; q < num_queries; ++q) qs[(size_t)q] = ClaimQuery{graphs[q], 0, nullptr, nullptr};
+    return claim_workspace(qs.data(), num_queries);
 }
 
 // ---------------------------------------------------------------------------

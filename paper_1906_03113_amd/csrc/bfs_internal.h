@@ -250,6 +250,72 @@ uint32_t persistent_max_grid(int device);
 
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// The claim-word push (bfs_claim.hip).  Every vertex of every query holds one
+// 64-bit word, (level << 32) | parent, ~0 while unreached; frontier vertex u of
+// level k offers ((k + 1) << 32) | u to each out-neighbour by atomicMin, so
+// one atomic both masks the visited rows (their words are smaller) and
+// selects the smallest frontier in-neighbour; the atomic that finds ~0 lists
+// the vertex for the next level.  Several queries (on different graphs) run
+// together in one virtual vertex space: query q owns ids [base_q, base_q + n_q).
+// ---------------------------------------------------------------------------
+constexpr int kCwBlock = 256;                 // threads per workgroup of the wide level
+constexpr int kCwNarrowThreads = 1024;        // the narrow kernel's one workgroup
+constexpr uint32_t kCwCap = 8192;             // narrow: frontier entries held in LDS
+constexpr uint32_t kCwPer = kCwCap / kCwNarrowThreads;
+constexpr uint32_t kCwLongCap = 2048;         // narrow: entries with more than 4 out-edges
+constexpr uint32_t kCwNarrowEdges = 1u << 16; // narrow: out-edges of a level at most
+constexpr uint32_t kCwLong = 256;             // wide: a column this long is split into chunks
+constexpr uint32_t kCwChunk = 1024;           // wide: entries per chunk
+constexpr uint32_t kCwPrecheck = 1u << 16;    // wide: frontier entries from which a word is read first
+constexpr uint32_t kCwMaxQueries = 4096;
+
+struct CwQuery {
+    const int32_t *out_ptr, *out_idx;
+    int32_t *level, *parent;                  // the query's outputs (n each)
+    uint32_t base, n;                         // virtual ids [base, base + n)
+    int32_t source;
+    uint32_t pad;
+};
+
+struct CwLists {                              // one level's frontier
+    uint32_t *s;                              // short columns (virtual ids)
+    uint32_t *l;                              // long columns (virtual ids)
+    uint32_t *lbase;                          // long column i's first chunk
+    uint32_t *cmap;                           // chunk -> long column
+};
+
+struct alignas(256) CwState {
+    uint32_t level;                           // the level whose frontier is listed
+    uint32_t done;                            // the last search level ended (narrow)
+    uint32_t last;                            // wide: the deepest level launched with a frontier
+    uint32_t pad;
+    uint32_t cnt[3][4];                       // level k: cnt[k % 3] = short, long, chunks
+};
+
+struct CwParams {
+    const CwQuery *q;                         // device, nq
+    const uint32_t *bases;                    // device, nq + 1: base_q, then V
+    uint32_t nq;
+    uint32_t V;                               // virtual vertices (sum of n)
+    uint32_t max_n;                           // largest n_q
+    unsigned long long *cw;                   // [V]
+    CwLists lists[2];                         // level k lists in lists[k & 1]
+    uint32_t *spill;                          // narrow: next-frontier entries beyond the LDS
+    CwState *st;
+};
+
+struct CwLayout {
+    size_t q, bases, st, cw, s0, l0, b0, c0, s1, l1, b1, c1, spill, total;
+};
+CwLayout cw_layout(uint64_t V, uint64_t nnz, uint32_t nq);
+
+hipError_t launch_cw_init(const CwParams &p, hipStream_t s);
+hipError_t launch_cw_wide(const CwParams &p, uint32_t k, uint32_t grid, hipStream_t s);
+hipError_t launch_cw_narrow(const CwParams &p, uint32_t k, uint32_t max_levels, uint32_t max_next,
+                            uint32_t max_edges, hipStream_t s);
+hipError_t launch_cw_out(const CwParams &p, hipStream_t s);
+
 // The comparison searches of the Experiments section (bfs_compare.hip).
 enum CmpMethod : uint32_t { kCmpSpmv = 0, kCmpSpmspv = 1, kCmpSpmmspv = 2 };
 
