@@ -146,7 +146,10 @@ typedef struct bfs_run_options {
  *                    other forms pay a grid-wide launch per level.  Needs
  *                    variant PUSH and the host loop (BFS_EINVAL otherwise);
  *                    fills no trace.
- *   BFS_PUSH_AUTO    sliced when it applies, the list form otherwise.
+ *   BFS_PUSH_AUTO    sliced when it applies and n >= 2^17; else, with the host
+ *                    loop, claim-word when the sliced form does not apply
+ *                    (n > 4 * 2^20) and the average degree is at most 8; the
+ *                    list form otherwise.
  */
 enum {
     BFS_PUSH_AUTO = 0,

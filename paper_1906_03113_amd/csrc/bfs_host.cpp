@@ -801,10 +801,28 @@ uint32_t sl_grid(const bfs_graph *g) {
     return per * r;
 }
 
+// The automatic choice of the push's form (measured, one search from each of
+// 64 sources on R-MAT s22, 16 on directed R-MAT s20, one on Erdos-Renyi 16K,
+// two on the 4096^2 grid): the sliced form where it applies, except on
+// graphs below kSlMinAuto vertices (its per-level set-up, ~38 us, exceeds the
+// list form's ~19 us there); beyond the sliced form's size limit, the
+// claim-word form on graphs of average degree at most kClaimMaxAvgDeg (thin
+// frontiers, few masked entries per level: 2x the list form on the grid) and
+// the list form otherwise (hub columns make one atomic per entry costly).
+constexpr int32_t kSlMinAuto = 1 << 17;
+constexpr uint64_t kClaimMaxAvgDeg = 8;
+
 bool sliced_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
     const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
-    return c.policy == kPush && (impl == BFS_PUSH_AUTO || impl == BFS_PUSH_SLICED) && g->sl_S != 0 &&
-           c.loop != BFS_LOOP_PERSISTENT;
+    if (c.policy != kPush || g->sl_S == 0 || c.loop == BFS_LOOP_PERSISTENT) return false;
+    return impl == BFS_PUSH_SLICED || (impl == BFS_PUSH_AUTO && g->n >= kSlMinAuto);
+}
+
+bool claim_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
+    const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
+    if (impl == BFS_PUSH_CLAIM) return true;
+    return impl == BFS_PUSH_AUTO && c.policy == kPush && c.loop == BFS_LOOP_HOST && g->sl_S == 0 &&
+           (uint64_t)g->nnz <= kClaimMaxAvgDeg * (uint64_t)g->n;
 }
 
 bfs_status check_push_impl(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
@@ -1041,7 +1059,7 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
     st = check_push_impl(g, c, opt);
     if (st != BFS_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (opt && opt->push_impl == BFS_PUSH_CLAIM) {
+    if (claim_applies(g, c, opt)) {
         const ClaimQuery q{g, source, level, parent};
         return run_claim(&q, 1, workspace, ws_bytes, s, g->cus, opt);
     }
@@ -1084,6 +1102,8 @@ extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t 
     if (st != BFS_OK) return st;
     st = check_push_impl(g, c, opt);
     if (st != BFS_OK) return st;
+    if (opt && opt->push_impl == BFS_PUSH_CLAIM)
+        return fail(BFS_EINVAL, "the claim-word push runs single searches and bfs_run_batch, not several roots");
     hipStream_t s = (hipStream_t)hip_stream;
     int32_t *roots_dev = (int32_t *)((char *)workspace + base);
     HIP_TRY(hipMemcpyAsync(roots_dev, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, s));
@@ -1319,7 +1339,7 @@ extern "C" size_t bfs_batch_workspace_size(int32_t num_queries, bfs_graph *const
         if (!graphs[q]) return 0;
         same = same && graphs[q] == graphs[0];
     }
-    if (same && num_queries > 1) return bfs_workspace_size(graphs[0], num_queries, 0);
+    if (same) return bfs_workspace_size(graphs[0], num_queries, 0);   // one query: bfs_run's
     std::vector<ClaimQuery> qs((size_t)num_queries);
     for (int32_t q = 0; q < num_queries; ++q) qs[(size_t)q] = ClaimQuery{graphs[q], 0, nullptr, nullptr};
     return claim_workspace(qs.data(), num_queries);

@@ -346,8 +346,9 @@ def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector):
     each graph: the autotuner's cached choice for the graph's shape if there is
     one, else by diameter class (deep graphs read the frontier size back every
     64 levels instead of every 4); then the faster, on the probe source, of the
-    learned per-level form and plain push (on graphs thousands of levels deep
-    the per-level decision costs more than it saves).  Also whether the graph is
+    learned per-level form, plain push and the claim-word push (on graphs
+    thousands of levels deep the per-level decision costs more than it saves,
+    and the claim-word form's lighter levels win).  Also whether the graph is
     shallow (at most 64 levels), which lets its batches run as one
     multi-source search."""
     import torch
@@ -364,7 +365,8 @@ def launch_params(Gs: Dict[str, object], srcs: Dict[str, np.ndarray], selector):
         if levels > 64:
             kw.setdefault("levels_per_sync", 64)
         best, best_t = None, float("inf")
-        for form in (dict(variant="learned", selector=selector), dict(variant="push")):
+        for form in (dict(variant="learned", selector=selector), dict(variant="push"),
+                     dict(variant="push", push_impl="claim")):
             run = dict(kw, **form)
             P.bfs(G, s, **run)
             torch.cuda.synchronize()
