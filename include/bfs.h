@@ -159,6 +159,10 @@ enum {
 };
 
 /*
+ * The adjacency matrix A as the paper's Notation section fixes it (A(i,j) = 1
+ * for an edge i -> j, rows egress) in the CSR format the paper describes for
+ * its Algorithms 2 and 3 (a row pointer array of n+1 offsets and a column
+ * index array).
  * Create a graph from the CSR of A (out-neighbours: row i lists j with A(i,j)=1;
  * out_ptr has n+1 entries, out_idx has out_ptr[n]) and, for directed graphs,
  * the CSC of A (in-neighbours: in_ptr n+1 entries, in_idx in_ptr[n]).  For an
@@ -183,13 +187,19 @@ bfs_status bfs_graph_info(const bfs_graph *g, int32_t *n, int64_t *nnz,
 
 /*
  * Device workspace bytes that bfs_run (num_queries = 1) or bfs_run_batch
- * (num_queries sources on this graph) needs.  0 on a bad argument.
- * run_flags is reserved (pass 0).
+ * (num_queries sources on this graph) needs: the state Algorithm 1 carries
+ * between steps (the visited set V_k as bitmaps, the frontier supp(x_k) as
+ * lists or bitmaps, the per-level counters) for every form of the push, the
+ * pull and the claim-word push; for num_queries > 1 also the multi-source
+ * masks.  0 on a bad argument.  run_flags is reserved (pass 0).
  */
 size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_flags);
 
 /*
- * One search from `source`.  level and parent are device arrays of n int32
+ * One search from `source`: Algorithm 1 / Theorem 1, x_1 = e_source and
+ * x_{k+1} = A^T[V_{k+1}, V_k] x_k until the frontier is empty, with the
+ * parent of Algorithm 3 (its min-parent reading, see the header).
+ * level and parent are device arrays of n int32
  * (caller-owned); workspace is a device buffer of at least
  * bfs_workspace_size(g, 1, 0) bytes, 256-byte aligned.  Nothing is allocated
  * per call (a host thread's first search allocates a 256-byte pinned host
@@ -208,7 +218,9 @@ bfs_status bfs_run(bfs_graph *g, int32_t source,
                    void *workspace, size_t ws_bytes, void *hip_stream);
 
 /*
- * Many searches in one call.  Query q is (graphs[q], sources[q]) with outputs
+ * Many searches in one call: Algorithm 3's parallel search (its `for all`
+ * loops over frontier columns and their entries) run for every query at once.
+ * Query q is (graphs[q], sources[q]) with outputs
  * level[q], parent[q] (device, n of that graph each).  When every query names
  * the same graph, the searches advance together, 64 sources per 64-bit mask
  * per vertex (one pass over a column serves every source whose frontier holds
