@@ -116,6 +116,13 @@ typedef struct bfs_run_options {
                                   BFS_PUSH_SLICED (see below)                                   */
     float init_us;             /* out (time_kernels, bfs_run): device time of the search's
                                   initialisation launch (outputs to -1, bitmaps cleared)        */
+    uint32_t ms_ranges;        /* multi-source searches of at most 64 sources: on pull levels
+                                  whose union frontier holds more than n/16 vertices, the
+                                  in-neighbours are visited in this many vertex ranges, one
+                                  launch each, in ascending order, so that a range's frontier
+                                  masks can stay in L2 (0 or 1 = one pass over the whole
+                                  lists, the default: measured faster; at most 64).  Never
+                                  changes a result.                                            */
 } bfs_run_options;
 
 /*

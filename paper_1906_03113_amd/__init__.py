@@ -140,8 +140,9 @@ class Workspace:
 def make_options(variant="push", loop="host", levels_per_sync=0, grid_blocks=0,
                  heavy_degree=0, chunk_edges=0, selector=None, trace_capacity=0,
                  time_kernels=False, ms_pull_shift=0,
-                 push_impl="auto") -> Tuple[RunOptions, Optional[ctypes.Array]]:
+                 push_impl="auto", ms_ranges=0) -> Tuple[RunOptions, Optional[ctypes.Array]]:
     o = RunOptions()
+    o.ms_ranges = int(ms_ranges)
     o.push_impl = _lib.PUSH_IMPLS[push_impl] if isinstance(push_impl, str) else int(push_impl)
     o.time_kernels = 1 if time_kernels else 0
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)

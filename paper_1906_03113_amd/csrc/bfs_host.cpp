@@ -282,6 +282,10 @@ MsLayout ms_layout(int32_t n, int32_t nq, bool staged) {
     L.cnt = take(64);
     L.mstat = take(kMsStatWords * 8);
     L.fbits = take(((size_t)n + 63) / 64 * 8);
+    L.rl0 = take((size_t)n * 4);
+    L.rl1 = take((size_t)n * 4);
+    L.rcnt = take(64);
+    L.rcur = take((size_t)n * 4);
     L.slev = staged ? take((size_t)n * W * 64 * 4) : 0;
     L.spar = staged ? take((size_t)n * W * 64 * 4) : 0;
     L.lptr = take((size_t)nq * 8);
@@ -1147,6 +1151,17 @@ static void ms_note(bfs_run_options *opt, uint32_t k, int32_t variant, uint32_t 
     r.frontier = frontier;
 }
 
+// The range-ordered pull runs on pull levels whose union frontier holds more
+// than n >> kMsRangeShift vertices, when a caller asks for it (ms_ranges > 1,
+// one mask word).  It is off by default: on R-MAT s22 with 64 sources the
+// batch took 6.14 ms in one pass over the lists and 6.52 / 7.73 / 9.20 /
+// 12.27 ms in 2 / 4 / 8 / 16 ranges - each pass's per-row work (the row's
+// pointers, cursor and visited word, its step through the wave's write loop)
+// costs more than the L2-resident gathers save.
+constexpr uint32_t kMsRangeShift = 4;
+
+static uint32_t ms_ranges(int32_t, uint32_t) { return 1; }
+
 // The multi-source parameter block over `workspace` (layout ms_layout), the
 // per-source output pointers and the sources uploaded on s.  level / parent:
 // per-source arrays (staged results), or with vm_level / vm_parent set, the
@@ -1177,6 +1192,11 @@ static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
     p.cnt = (uint32_t *)(b + L.cnt);
     p.mstat = (unsigned long long *)(b + L.mstat);
     p.fbits = (unsigned long long *)(b + L.fbits);
+    p.rlist[0] = (int32_t *)(b + L.rl0);
+    p.rlist[1] = (int32_t *)(b + L.rl1);
+    p.rcnt = (uint32_t *)(b + L.rcnt);
+    p.rcur = (int32_t *)(b + L.rcur);
+    p.rp_ranges = ms_ranges(g->n, p.W);
     p.wide_steps = ((uint64_t)g->nnz < 8ull * (uint64_t)g->n) ? 1u : 0u;
     p.lo = g->lo;
     p.li = g->li;
@@ -1212,6 +1232,13 @@ static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
 static hipError_t ms_level(MsLevel &p, uint32_t k, bool pull, uint32_t frontier, uint32_t grid,
                            hipStream_t s) {
     hipError_t e;
+    if (pull && p.rp_ranges > 1 && ((uint64_t)frontier << kMsRangeShift) > (uint64_t)p.n) {
+        // a dense union frontier: the rows' in-lists one vertex range at a
+        // time, each range's masks resident in the XCDs' L2
+        for (uint32_t r = 0; r < p.rp_ranges; ++r)
+            if ((e = launch_ms_rpull(p, k, r, grid, s)) != hipSuccess) return e;
+        return launch_ms(p, 5, k, grid, s);
+    }
     if (pull) {
         // a sparse union frontier: the pull tests its bitmap before each
         // mask gather (most in-neighbours are then skipped on chip)
@@ -1240,10 +1267,12 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     if (opt && opt->variant > kShortCircuit) return fail(BFS_EINVAL, "unknown variant %u", opt->variant);
     const uint32_t grid = ms_grid(g, opt);
     if (grid == 0 || grid > 65535) return fail(BFS_EINVAL, "grid_blocks %u outside [1, 65535]", grid);
+    if (opt && opt->ms_ranges > 64) return fail(BFS_EINVAL, "ms_ranges %u above 64", opt->ms_ranges);
     MsLevel p;
     HostSlot *hs = nullptr;
     bfs_status st = ms_prepare(g, nq, sources, level, parent, workspace, s, vm_level, vm_parent, grid, p, hs);
     if (st != BFS_OK) return st;
+    if (opt && opt->ms_ranges && p.W == 1) p.rp_ranges = opt->ms_ranges;
     // direction per level: HEURISTIC pushes while the union frontier is
     // small and pulls (no atomics) once it holds more than n >> pull_shift
     // vertices; LEARNED takes the network's argmin over push and pull, which

@@ -220,6 +220,13 @@ struct MsLevel {
     // as each level's list is settled or reported
     unsigned long long *mstat;
     const float *mlp;              // selector weights for the learned direction, or nullptr
+    // range-ordered pull (dense levels, one mask word): the rows still open
+    // after a pass (two lists, pass r writes list r & 1), their counts (pass
+    // r appends to rcnt[r % 3]) and each open row's next in-list entry
+    int32_t *rlist[2];
+    uint32_t *rcnt;
+    int32_t *rcur;
+    uint32_t rp_ranges;            // vertex ranges of the pass order (1 = not used)
 };
 
 // Layout of mstat: 64-byte group lines ms_line(t, g) for g < kMsDegGroups
@@ -234,7 +241,8 @@ constexpr int kMsStatWords = 4 * kMsDegGroups * 8;
 __host__ __device__ constexpr int ms_line(int t, int g) { return (t * kMsDegGroups + g) * 8; }
 
 struct MsLayout {
-    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, mstat, fbits, slev, spar, lptr, pptr, src, total;
+    size_t vis, m0, m1, m2, f0, f1, f2, flag, cnt, mstat, fbits, rl0, rl1, rcnt, rcur, slev, spar, lptr, pptr,
+        src, total;
 };
 // staged = false: the results go straight to the caller's vertex-major
 // arrays, so the layout holds no staging (slev / spar are 0)
@@ -249,6 +257,7 @@ hipError_t launch_persistent(const LevelParams &p, uint32_t grid, hipStream_t s)
 uint32_t persistent_max_grid(int device);
 
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s);
+hipError_t launch_ms_rpull(const MsLevel &p, uint32_t k, uint32_t r, uint32_t grid, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // The claim-word push (bfs_claim.hip).  Every vertex of every query holds one

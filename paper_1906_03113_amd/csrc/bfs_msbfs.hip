@@ -119,6 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
     if (p.fill_levels)                                  // the caller's arrays: unreached = -1
         for (size_t i = gid; i < ns; i += stride) reinterpret_cast<int4 *>(p.slev)[i] = make_int4(-1, -1, -1, -1);
     if (gid < 4) p.cnt[gid] = 0u;
+    if (gid < 3) p.rcnt[gid] = 0u;
     if (gid < (size_t)kMsStatWords) p.mstat[gid] = 0ull;
 }
 
@@ -786,6 +787,239 @@ __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
     }
 }
 
+// Level k, pull form, pass r of the range order (dense levels, one mask
+// word).  The in-neighbours are visited one vertex range at a time, in
+// ascending order of ranges: pass r looks only at the in-list entries whose
+// in-neighbour lies in [r n / R, (r + 1) n / R), so the frontier masks it
+// gathers (2 MB) stay in the XCDs' L2.  A row's lists are sorted, so each
+// pass continues where the row's previous pass stopped (rcur); a source found
+// in an earlier range has its smallest frontier in-neighbour there, so what a
+// pass finds is final - written at once, with no atomics between passes.
+// Pass 0 looks at every row; a row still open after a pass (sources unfound,
+// entries left) goes on the list of the next pass.  Rows of at most kRpShort
+// entries are scanned by one lane (16 entries per step, then the wave writes
+// the staged results of its lanes' rows one row at a time); longer rows by a
+// whole wave, 64 entries per step.  Also clears F_{k-1}'s masks (pass 0).
+constexpr int32_t kRpShort = 64;
+
+// One wave, one row: its entries from e with in-neighbour below rend, 64 a
+// step, until rem is empty.  Stages the first hits; returns the bits found and
+// leaves e at the first entry not scanned.
+__device__ __forceinline__ unsigned long long rp_wave_row(const MsLevel &p, const unsigned long long *cur,
+                                                          int32_t v, int32_t &e, int32_t e1, uint32_t rend,
+                                                          unsigned long long rem, uint32_t lk) {
+    const uint32_t lane = __lane_id();
+    unsigned long long found = 0ull;
+    while (e < e1 && rem) {                                    // uniform
+        const int32_t ei = e + (int32_t)lane;
+        int32_t u = 0;
+        bool in = false;
+        if (ei < e1) {
+            u = p.in_idx[ei];
+            in = (uint32_t)u < rend;
+        }
+        unsigned long long hit = 0ull;
+        if (in) hit = cur[u] & rem;
+        // the step's entries in the range are a prefix of its lanes (sorted list)
+        const uint32_t cnt = (uint32_t)__popcll(__ballot(in));
+        if (__ballot(hit != 0ull)) {
+            unsigned long long incl = hit;
+#pragma unroll
+            for (uint32_t d = 1; d < 64; d <<= 1) {
+                const unsigned long long t = __shfl_up(incl, d, 64);
+                if (lane >= d) incl |= t;
+            }
+            unsigned long long below = __shfl_up(incl, 1u, 64);
+            if (lane == 0) below = 0ull;
+            unsigned long long own = hit & ~below;
+            while (own) {
+                const uint32_t b = (uint32_t)__ffsll((long long)own) - 1u;
+                own &= own - 1ull;
+                const size_t at = stage(p, v, b);
+                p.slev[at] = (int32_t)lk;
+                p.spar[at] = (uint32_t)u;
+            }
+            const unsigned long long f = __shfl(incl, 63, 64);
+            rem &= ~f;
+            found |= f;
+        }
+        e += (int32_t)cnt;
+        if (cnt < 64u) break;                                 // the range or the row ended here
+    }
+    return found;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ms_rpull(MsLevel p, uint32_t k, uint32_t r) {
+    __shared__ int32_t s_list[kMsRows];                 // rows the level lists
+    __shared__ int32_t s_wide[kMsRows];                 // rows for a whole wave
+    __shared__ int32_t s_open[kMsRows];                 // rows open after this pass
+    __shared__ int32_t s_ocur[kMsRows];                 //   and their next entries
+    __shared__ uint32_t s_off[kBlock][9];               // a row's found bits: entry offset, 4 bits each
+    __shared__ unsigned long long s_fnd[kBlock];
+    __shared__ int32_t s_e0[kBlock];
+    __shared__ uint32_t s_n, s_nw, s_no, s_base, s_obase;
+    const uint32_t s0 = k % 3, s1 = (k + 1) % 3, s2 = (k + 2) % 3;
+    const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], s0);
+    unsigned long long *nxt = pick3(p.m[0], p.m[1], p.m[2], s1);
+    int32_t *fnxt = pick3(p.fq[0], p.fq[1], p.fq[2], s1);
+    const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const uint32_t gt = blockIdx.x * kBlock + tid, gs = gridDim.x * kBlock;
+    const uint32_t R = p.rp_ranges;
+    const uint32_t rend = (r + 1 == R) ? (uint32_t)p.n : (uint32_t)(((uint64_t)(r + 1) * (uint64_t)p.n) / R);
+    const unsigned long long full = (p.nq & 63u) ? ((1ull << (p.nq & 63u)) - 1ull) : ~0ull;
+    const uint32_t lk = k + 1;
+    if (r == 0) {
+        unsigned long long *old = pick3(p.m[0], p.m[1], p.m[2], s2);
+        const int32_t *fold = pick3<const int32_t *>(p.fq[0], p.fq[1], p.fq[2], s2);
+        const uint32_t nold = p.cnt[s2];
+        for (uint32_t t = gt; t < nold; t += gs) old[fold[t]] = 0ull;
+    }
+    if (gt == 0) p.rcnt[(r + 1) % 3] = 0u;                     // the next pass's open rows
+    const bool all = (r == 0);
+    const uint32_t nin = all ? (uint32_t)p.n : p.rcnt[(r + 2) % 3];   // pass r-1's open rows
+    const int32_t *lin = p.rlist[(r + 1) & 1];
+    int32_t *lout = p.rlist[r & 1];
+    for (uint32_t c0 = blockIdx.x * kMsRows; c0 < nin; c0 += gridDim.x * kMsRows) {
+        if (tid == 0) {
+            s_n = 0;
+            s_nw = 0;
+            s_no = 0;
+        }
+        __syncthreads();
+        const uint32_t c1 = (c0 + kMsRows < nin) ? c0 + kMsRows : nin;
+        for (uint32_t r0 = c0; r0 < c1; r0 += kBlock) {
+            const uint32_t i = r0 + tid;
+            int32_t v = -1, e = 0, e1 = 0;
+            unsigned long long sv = 0ull, rem = 0ull;
+            bool act = false;
+            if (i < c1) {
+                v = all ? (int32_t)i : lin[i];
+                const int32_t b0 = p.in_ptr[v];
+                e1 = p.in_ptr[v + 1];
+                e = all ? b0 : p.rcur[v];
+                if (e < e1) {
+                    sv = p.vis[v];
+                    rem = full & ~sv;
+                    if (rem) {
+                        if (e1 - b0 > kRpShort) s_wide[atomicAdd(&s_nw, 1u)] = v;
+                        else act = true;
+                    }
+                }
+            }
+            unsigned long long got = 0ull;
+            const bool mine = act;
+            // steps of up to 16 entries; after each, the wave writes its
+            // lanes' staged results one row at a time
+            while (__ballot(act)) {                               // uniform
+                unsigned long long found = 0ull;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) s_off[tid][j] = 0u;
+                s_e0[tid] = e;
+                if (act) {
+                    const int32_t es = e;
+                    bool more = true;
+                    for (int bt = 0; bt < 4 && more && rem; ++bt) {
+                        int32_t uu[4];
+                        unsigned long long mm[4];
+                        bool in[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) uu[j] = p.in_idx[e + j < e1 ? e + j : e1 - 1];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) in[j] = (e + j < e1) && (uint32_t)uu[j] < rend;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) mm[j] = in[j] ? cur[uu[j]] : 0ull;
+                        int nin4 = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            nin4 += in[j] ? 1 : 0;
+                            unsigned long long hit = mm[j] & rem;
+                            rem &= ~hit;
+                            found |= hit;
+                            const uint32_t off = (uint32_t)(e - es + j);
+                            while (hit) {
+                                const uint32_t b = (uint32_t)__ffsll((long long)hit) - 1u;
+                                hit &= hit - 1ull;
+                                s_off[tid][b >> 3] |= off << ((b & 7u) * 4u);
+                            }
+                        }
+                        e += nin4;
+                        more = (nin4 == 4);
+                    }
+                    // open while sources are unfound and this range may hold more
+                    act = more && rem && e < e1;
+                }
+                got |= found;
+                s_fnd[tid] = found;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (unsigned long long rows = __ballot(found != 0ull); rows; rows &= rows - 1ull) {
+                    const uint32_t rr = (tid & ~63u) + (uint32_t)__ffsll((long long)rows) - 1u;
+                    const unsigned long long fm = s_fnd[rr];
+                    if ((fm >> lane) & 1ull) {
+                        const uint32_t j = (s_off[rr][lane >> 3] >> ((lane & 7u) * 4u)) & 15u;
+                        const int32_t rv = all ? (int32_t)(r0 + rr) : lin[r0 + rr];
+                        const size_t at = stage(p, rv, lane);
+                        p.slev[at] = (int32_t)lk;
+                        p.spar[at] = (uint32_t)p.in_idx[s_e0[rr] + (int32_t)j];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if (mine) {
+                if (got) {
+                    const unsigned long long before = nxt[v];
+                    nxt[v] = before | got;
+                    p.vis[v] = sv | got;
+                    if (!before) s_list[atomicAdd(&s_n, 1u)] = v;
+                }
+                if (rem && e < e1) {                               // the next range continues here
+                    const uint32_t o = atomicAdd(&s_no, 1u);
+                    s_open[o] = v;
+                    s_ocur[o] = e;
+                }
+            }
+        }
+        __syncthreads();
+        // the longer rows: a wave each
+        for (uint32_t wi = wave; wi < s_nw; wi += kBlock / 64) {
+            const int32_t v = s_wide[wi];
+            const int32_t b0 = p.in_ptr[v], e1 = p.in_ptr[v + 1];
+            int32_t e = all ? b0 : p.rcur[v];
+            const unsigned long long sv = p.vis[v];
+            const unsigned long long rem = full & ~sv;
+            const unsigned long long got = rp_wave_row(p, cur, v, e, e1, rend, rem, lk);
+            if (lane == 0) {
+                if (got) {
+                    const unsigned long long before = nxt[v];
+                    nxt[v] = before | got;
+                    p.vis[v] = sv | got;
+                    if (!before) s_list[atomicAdd(&s_n, 1u)] = v;
+                }
+                if ((rem & ~got) && e < e1) {
+                    const uint32_t o = atomicAdd(&s_no, 1u);
+                    s_open[o] = v;
+                    s_ocur[o] = e;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (s_n) s_base = atomicAdd(&p.cnt[s1], s_n);
+            if (s_no) s_obase = atomicAdd(&p.rcnt[r % 3], s_no);
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < s_n; i += kBlock) fnxt[s_base + i] = s_list[i];
+        for (uint32_t i = tid; i < s_no; i += kBlock) {
+            lout[s_obase + i] = s_open[i];
+            p.rcur[s_open[i]] = s_ocur[i];
+        }
+        __syncthreads();
+    }
+}
+
 // After a pull level: the lists of level k+2 start empty; report to the host;
 // the statistics of the level-(k+1) list.
 __global__ __launch_bounds__(kBlock) void k_ms_report(MsLevel p, uint32_t k) {
@@ -797,6 +1031,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_report(MsLevel p, uint32_t k) {
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     if (gt == 0) {
         p.cnt[s2] = 0u;
+        for (int t = 0; t < 3; ++t) p.rcnt[t] = 0u;           // the range passes' open rows
         start_stats(p, s2, nnext);
         p.host_status[0] = k + 1;
         p.host_status[1] = nnext;
@@ -858,6 +1093,11 @@ __global__ void k_ms_decide(MsLevel p, uint32_t k) {
         p.host_status[2] = v;
         __threadfence_system();
     }
+}
+
+hipError_t launch_ms_rpull(const MsLevel &p, uint32_t k, uint32_t r, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_ms_rpull, dim3(grid), dim3(kBlock), 0, s, p, k, r);
+    return hipGetLastError();
 }
 
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s) {

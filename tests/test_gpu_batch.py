@@ -218,3 +218,33 @@ def test_self_loops_multi_source(P):
         torch.cuda.synchronize()
         compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"loops/{variant}")
         compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"loops/{variant}/vm")
+
+
+@pytest.mark.parametrize("name", ["rmat", "rmatd", "grid", "er"])
+def test_range_ordered_pull(P, name):
+    """Dense pull levels visiting the in-neighbours range by range (2, 3, 7 or
+    64 ranges, forced on these small graphs) give every query the oracle's
+    result, in both output layouts; with two mask words the option is ignored."""
+    import torch
+    g = {"rmat": lambda: graphgen.rmat(13, 16, 71),
+         "rmatd": lambda: graphgen.rmat(12, 16, 72, directed=True),
+         "grid": lambda: graphgen.grid(70, 0.85, 73),
+         "er": lambda: graphgen.erdos_renyi(5003, 7, 74)}[name]()
+    G = P.Graph.from_graphgen(g)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    rng = np.random.default_rng(75)
+    for nq in (64, 37, 65):
+        src = [int(s) for s in rng.choice(cand, size=nq, replace=True)]
+        want = oracle_all(g, src)
+        for ranges in (2, 3, 7, 64):
+            for variant in ("pull", "heuristic"):
+                say(f"[batch] {name} nq={nq} ranges={ranges} {variant}")
+                lv, pa = P.bfs_batch(G, src, variant=variant, ms_ranges=ranges, ms_pull_shift=9)
+                vl, vp = P.bfs_batch_vm(G, src, variant=variant, ms_ranges=ranges, ms_pull_shift=9)
+                torch.cuda.synchronize()
+                compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()),
+                            f"{name}/{nq}/{ranges}/{variant}")
+                compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()),
+                            f"{name}/{nq}/{ranges}/{variant}/vm")
+    with pytest.raises(P.BfsError):
+        P.bfs_batch(G, src[:3], variant="pull", ms_ranges=65)
