@@ -79,10 +79,13 @@ def test_rmat22_batch_of_64():
     vp = torch.empty((g.n, 64), dtype=torch.int32, device="cuda")
     say("[full] rmat22 oracle from the 64 sources (host threads)")
     want = oracle_all(g, src)
-    for kw in (dict(variant="heuristic", ms_pull_shift=5), dict(variant="heuristic", ms_pull_shift=9),
+    from paper_1906_03113_amd import selector as S
+    msw = S.load_weights(S.MS_WEIGHTS)
+    for kw in (dict(variant="learned", selector=msw),            # the bench's headline call
+               dict(variant="heuristic", ms_pull_shift=5), dict(variant="heuristic", ms_pull_shift=9),
                dict(variant="heuristic", ms_pull_shift=11), dict(variant="heuristic", ms_pull_shift=13),
                dict(variant="push")):
-        say(f"[full] rmat22 multi-source x64 {kw}")
+        say(f"[full] rmat22 multi-source x64 {kw.get('variant')} {kw.get('ms_pull_shift', '')}")
         P.bfs_batch(G, src, levels=lv, parents=pa, **kw)
         P.bfs_batch_vm(G, src, level=vl, parent=vp, **kw)
         torch.cuda.synchronize()
@@ -101,6 +104,35 @@ def test_grid4096():
                dict(variant="push", loop="persistent")):
         say(f"[full] grid4096 s={s} {kw}")
         _check(g, s, run_gpu(P, G, s, **{k: v for k, v in kw.items()}), f"grid4096/{kw}")
+
+
+def test_grid4096_claim_every_source():
+    """The 4096^2 grid as bench.py times it: the automatic push form (the
+    claim-word push here) from all 16 sources, and the 16 sources in one
+    batched + learned call; every query against the oracle."""
+    P = need_gpu()
+    import torch
+    from paper_1906_03113_amd import selector as S
+    g = graphgen.workload("grid4096")
+    G = P.Graph.from_graphgen(g)
+    src = [int(s) for s in graphgen.pick_sources(g, 16, 31)]
+    say("[full] grid4096 oracle from the 16 sources (host threads)")
+    want = oracle_all(g, src)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ws = P.Workspace(G.workspace_size(1))
+
+    def run(q):
+        P.bfs(G, src[q], level=lv, parent=pa, workspace=ws)
+        torch.cuda.synchronize()
+        return lv.cpu().numpy(), pa.cpu().numpy()
+    say("[full] grid4096 automatic push x16")
+    compare_all(want, src, run, "grid4096 auto push")
+    del ws
+    say("[full] grid4096 batched + learned x16")
+    bl, bp = P.bfs_batch(G, src, variant="learned", selector=S.load_weights(S.MS_WEIGHTS))
+    torch.cuda.synchronize()
+    compare_all(want, src, lambda q: (bl[q].cpu().numpy(), bp[q].cpu().numpy()), "grid4096 batch")
 
 
 def test_rmat20_directed():
@@ -195,6 +227,14 @@ def test_er_pack_of_64_graphs():
         nz = np.nonzero(g.out_degree() > 0)[0]
         roots.append(int(offs[b] + (nz[0] if len(nz) else 0)))
     want = [oracle.bfs_graph(g, roots[b] - int(offs[b])) for b, g in enumerate(gs)]
+    say("[full] ER x64 as one call over different graphs")
+    Gs = [P.Graph.from_graphgen(g) for g in gs]
+    ml, mp = P.bfs_batch(Gs, [roots[b] - int(offs[b]) for b in range(len(gs))])
+    torch.cuda.synchronize()
+    for b in range(len(gs)):
+        wl, wp = want[b]
+        assert np.array_equal(ml[b].cpu().numpy(), wl), ("mixed", b)
+        assert np.array_equal(mp[b].cpu().numpy(), wp), ("mixed", b)
     for loop in ("persistent", "graph"):
         say(f"[full] ER pack x64 loop={loop}")
         lv, pa = P.bfs_roots(G, roots, loop=loop)
