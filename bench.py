@@ -522,7 +522,17 @@ def other_workload(wname, args, msw):
         dtb = time_calls(lambda: P.bfs_batch(G, src, **bk), steps)
         res["batched_learned"] = {"gteps": round(tm / dtb / 1e9, 3), "ms_per_step": round(dtb * 1e3, 3),
                                   "us_per_level": round(dtb * 1e6 / max(levels), 2)}
-        del bl, bp, wsb
+        # the same sources in one call with the push on every level: the
+        # library's own choice of form for the batch (claim-word searches in
+        # lockstep on thin graphs)
+        del wsb
+        torch.cuda.empty_cache()
+        pk = dict(variant="push", levels=bl, parents=bp)
+        P.bfs_batch(G, src, **pk)
+        dtp = time_calls(lambda: P.bfs_batch(G, src, **pk), steps)
+        res["batched_push"] = {"gteps": round(tm / dtp / 1e9, 3), "ms_per_step": round(dtp * 1e3, 3),
+                               "us_per_level": round(dtp * 1e6 / max(levels), 2)}
+        del bl, bp
     if not args.no_cpu_baseline:
         cg, count, t_cpu, _, _ = cpu_oracle_gteps(g, sources, m_c, seconds=30.0, max_sources=8)
         res["cpu_baseline"] = {"value": round(cg, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",

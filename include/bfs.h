@@ -192,13 +192,21 @@ bfs_status bfs_graph_destroy(bfs_graph *g);
 bfs_status bfs_graph_info(const bfs_graph *g, int32_t *n, int64_t *nnz,
                           int32_t *directed, size_t *device_bytes);
 
+/* run_flags of bfs_workspace_size */
+enum {
+    BFS_WS_CLAIM = 1u << 0    /* also room for a batch in the claim-word form (push_impl CLAIM) */
+};
+
 /*
  * Device workspace bytes that bfs_run (num_queries = 1) or bfs_run_batch
  * (num_queries sources on this graph) needs: the state Algorithm 1 carries
  * between steps (the visited set V_k as bitmaps, the frontier supp(x_k) as
  * lists or bitmaps, the per-level counters) for every form of the push, the
  * pull and the claim-word push; for num_queries > 1 also the multi-source
- * masks.  0 on a bad argument.  run_flags is reserved (pass 0).
+ * masks and, on a graph where bfs_run_batch picks the claim-word form by
+ * itself (see bfs_run_batch) or with run_flags BFS_WS_CLAIM, the claim-word
+ * batch (about 36 bytes per vertex per query).  0 on a bad argument (unknown
+ * run_flags bits included).
  */
 size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_flags);
 
@@ -231,7 +239,9 @@ bfs_status bfs_run(bfs_graph *g, int32_t source,
  * level[q], parent[q] (device, n of that graph each).  When every query names
  * the same graph, the searches advance together, 64 sources per 64-bit mask
  * per vertex (one pass over a column serves every source whose frontier holds
- * it).  opt->variant picks the direction per level: PUSH (default) scatters
+ * it) - except with opt->push_impl BFS_PUSH_CLAIM, or with the automatic
+ * choice for variant PUSH (host loop) on a graph beyond 2^22 vertices of
+ * average degree at most 8, where they run as claim-word searches (below).  opt->variant picks the direction per level: PUSH (default) scatters
  * the frontier masks along out-edges; PULL lets every unsettled vertex gather
  * its in-neighbours' masks in ascending order; HEURISTIC pushes while the
  * union frontier holds at most n >> ms_pull_shift vertices and pulls after;

@@ -97,8 +97,10 @@ class Graph:
         _lib.check(_lib.lib().bfs_graph_info(self.handle, None, None, None, ctypes.byref(b)))
         return int(b.value)
 
-    def workspace_size(self, num_queries: int = 1) -> int:
-        return int(_lib.lib().bfs_workspace_size(self.handle, int(num_queries), 0))
+    def workspace_size(self, num_queries: int = 1, claim: bool = False) -> int:
+        """Workspace bytes for bfs / bfs_batch on this graph; claim=True also
+        covers a batch in the claim-word form (push_impl="claim")."""
+        return int(_lib.lib().bfs_workspace_size(self.handle, int(num_queries), 1 if claim else 0))
 
     def roots_workspace_size(self, nroots: int) -> int:
         return int(_lib.lib().bfs_roots_workspace_size(self.handle, int(nroots)))
@@ -267,6 +269,8 @@ def bfs_batch(graphs, sources: Sequence[int], variant="push", loop="host", level
         parents = [t.empty(gr.n, dtype=t.int32, device="cuda") for gr in graphs]
     H = (ctypes.c_void_p * nq)(*[gr.handle for gr in graphs])
     need = batch_workspace_size(graphs)
+    if kw.get("push_impl") in ("claim", _lib.PUSH_IMPLS["claim"]) and all(gr is graphs[0] for gr in graphs):
+        need = max(need, graphs[0].workspace_size(nq, claim=True))
     if workspace is None or not workspace.fits(need):
         workspace = Workspace(need)
     S = (ctypes.c_int32 * nq)(*[int(s) for s in sources])

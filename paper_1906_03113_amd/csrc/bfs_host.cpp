@@ -822,11 +822,28 @@ bool sliced_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *
     return impl == BFS_PUSH_SLICED || (impl == BFS_PUSH_AUTO && g->n >= kSlMinAuto);
 }
 
+// Thin: beyond the sliced form's size limit, average degree at most kClaimMaxAvgDeg.
+bool thin_graph(const bfs_graph *g) {
+    return g->sl_S == 0 && (uint64_t)g->nnz <= kClaimMaxAvgDeg * (uint64_t)g->n;
+}
+
 bool claim_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
     const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
     if (impl == BFS_PUSH_CLAIM) return true;
-    return impl == BFS_PUSH_AUTO && c.policy == kPush && c.loop == BFS_LOOP_HOST && g->sl_S == 0 &&
-           (uint64_t)g->nnz <= kClaimMaxAvgDeg * (uint64_t)g->n;
+    return impl == BFS_PUSH_AUTO && c.policy == kPush && c.loop == BFS_LOOP_HOST && thin_graph(g);
+}
+
+// Many sources on one graph as claim-word searches (each source its own
+// words, all in lockstep) instead of the 64-per-word multi-source kernels:
+// asked for (push_impl CLAIM), or the automatic choice for the push on a thin
+// graph - its levels are too small for the multi-source kernels' two grid-wide
+// launches per level (4096^2 grid, 16 sources: 33 us per level there).
+bool claim_batch_applies(const bfs_graph *g, const bfs_run_options *opt) {
+    const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
+    const uint32_t pol = opt ? opt->variant : kPush;
+    const uint32_t loop = opt ? opt->loop_mode : BFS_LOOP_HOST;
+    if (impl == BFS_PUSH_CLAIM) return true;
+    return impl == BFS_PUSH_AUTO && pol == kPush && loop == BFS_LOOP_HOST && thin_graph(g);
 }
 
 bfs_status check_push_impl(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
@@ -1040,10 +1057,16 @@ bfs_status bfs_graph_info(const bfs_graph *g, int32_t *n, int64_t *nnz, int32_t 
 }
 
 size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_flags) {
-    if (!g || num_queries <= 0 || run_flags != 0) return 0;
+    if (!g || num_queries <= 0 || (run_flags & ~(uint32_t)BFS_WS_CLAIM) != 0) return 0;
     const size_t single = ws_single(g);
     if (num_queries == 1) return single;
-    return std::max(single, ms_layout(g->n, num_queries).total);
+    size_t need = std::max(single, ms_layout(g->n, num_queries).total);
+    // thin graphs (or when asked): room for the claim-word batch too (see
+    // claim_batch_applies)
+    if (thin_graph(g) || (run_flags & BFS_WS_CLAIM))
+        need = std::max(need, cw_layout((uint64_t)g->n * (uint64_t)num_queries,
+                                        (uint64_t)g->nnz * (uint64_t)num_queries, (uint32_t)num_queries).total);
+    return need;
 }
 
 bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent,
@@ -1339,7 +1362,7 @@ extern "C" bfs_status bfs_run_batch(int32_t num_queries, bfs_graph *const *graph
             return fail(BFS_ERANGE, "query %d: source %d outside [0, %d)", q, sources[q], graphs[q]->n);
         same = same && graphs[q] == graphs[0];
     }
-    if (same && num_queries > 1) {
+    if (same && num_queries > 1 && !claim_batch_applies(graphs[0], opt)) {
         const size_t need = bfs_workspace_size(graphs[0], num_queries, 0);
         if (ws_bytes < need) return fail(BFS_EINVAL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
         return run_multi_source(graphs[0], num_queries, sources, level, parent, opt, workspace,
@@ -1347,9 +1370,9 @@ extern "C" bfs_status bfs_run_batch(int32_t num_queries, bfs_graph *const *graph
     }
     if (num_queries == 1)
         return bfs_run(graphs[0], sources[0], level[0], parent[0], opt, workspace, ws_bytes, hip_stream);
-    // queries on different graphs: every search at once
-    // through the claim-word push, one launch per level (or one narrow
-    // launch for many levels) for all of them
+    // queries on different graphs, or (claim_batch_applies) many on one thin
+    // graph: every search at once through the claim-word push, one launch per
+    // level (or one narrow launch for many levels) for all of them
     if (opt && opt->variant != kPush) return fail(BFS_EINVAL, "queries on different graphs run the push only");
     if (opt && opt->loop_mode != BFS_LOOP_HOST) return fail(BFS_EINVAL, "queries on different graphs run the host loop");
     std::vector<ClaimQuery> qs((size_t)num_queries);

@@ -14,7 +14,8 @@ so the searches of different workers overlap on the device:
   * a batch of several queries on one graph runs as one multi-source search
     (64 sources per mask word, push or pull per level from the learned
     direction network) when the graph is shallow enough for that to pay,
-    otherwise as consecutive single searches with the learned per-level selector.
+    otherwise as claim-word searches in lockstep (one launch per level for
+    the whole batch); a single query runs alone with its graph's fastest form.
 
 Every query's result is the search's own (level, parent): the same bits alone
 or in any mix (tested).  Latency = completion time - arrival time.
@@ -185,9 +186,17 @@ class GpuExecutor:
         return (self.mode != "plain" and nq > 1 and G.n <= self.ms_max_n
                 and self.shallow.get(gname, False))
 
+    def claim_batch(self, gname: str, nq: int) -> bool:
+        """A batch on a deep graph (more than 64 levels): its searches as
+        claim-word searches in lockstep, one launch per level for all."""
+        return self.mode != "plain" and nq > 1 and not self.shallow.get(gname, False)
+
     def footprint(self, gname: str, nq: int) -> int:
         G = self.graphs[gname]
-        ws = G.workspace_size(nq if self.multi_source(gname, nq) else 1)
+        if self.claim_batch(gname, nq):
+            ws = G.workspace_size(nq, claim=True)
+        else:
+            ws = G.workspace_size(nq if self.multi_source(gname, nq) else 1)
         return int(ws) + 8 * G.n * nq
 
     def _stream(self):
@@ -207,6 +216,9 @@ class GpuExecutor:
                 kw = dict(variant="learned", selector=self.ms_selector) if self.ms_selector is not None \
                     else dict(variant="heuristic")
                 lv, pa = P.bfs_batch(G, srcs, stream=s, **kw)
+                outs = list(zip(lv, pa))
+            elif self.claim_batch(b.graph, len(srcs)):
+                lv, pa = P.bfs_batch(G, srcs, stream=s, variant="push", push_impl="claim")
                 outs = list(zip(lv, pa))
             else:
                 kw = dict(variant="learned", selector=self.selector) if self.selector is not None \

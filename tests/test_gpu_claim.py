@@ -169,3 +169,24 @@ def test_mixed_batch_rejects_other_variants(P):
     Gs = [P.Graph.from_graphgen(g) for g in fam]
     with pytest.raises(P.BfsError):
         P.bfs_batch(Gs, [0, 0], variant="pull")
+
+
+@pytest.mark.parametrize("name", ["grid", "path", "rmat", "broom"])
+def test_claim_batch_on_one_graph(P, cases, name):
+    """Many sources on one graph as claim-word searches in lockstep (the form
+    the library takes by itself for thin graphs beyond 2^22 vertices, asked
+    for here): every query equals the oracle's, duplicates included."""
+    import torch
+    g, s0 = {"grid": (graphgen.grid(150, 0.9, 81), None), "path": (graphgen.path_graph(3000), None),
+             "rmat": (graphgen.rmat(12, 16, 82), None), "broom": cases["broom"]}[name]
+    G = P.Graph.from_graphgen(g)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = [int(s) for s in np.random.default_rng(83).choice(cand, size=20, replace=True)]
+    src[1] = src[0]
+    if s0 is not None:
+        src[2] = s0
+    want = oracle_all(g, src)
+    say(f"[claim] batch of {len(src)} on {name}")
+    lv, pa = P.bfs_batch(G, src, push_impl="claim")
+    torch.cuda.synchronize()
+    compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"claim batch {name}")
