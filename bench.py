@@ -284,16 +284,17 @@ def main():
         bytes_total = float(sum(b_search))
         kern_us = level_us + init_us
         ach = bytes_total / (kern_us * 1e-6) / 1e9
-        sliced = (args.variant == "push" and g.n <= 4 * 32768 * 32 and args.loop in ("host", "graph")
-                  and args.push_impl in ("auto", "sliced"))
-        kname = ("k_sl_level" if sliced else
-                 "k_cw_narrow / k_cw_wide" if args.push_impl == "claim" else "k_level")
+        used = {i.get("push_used", "list") for i in infos}
+        form = used.pop() if len(used) == 1 else "list"
+        sliced = form == "sliced"
+        kname = ("k_sl_level" if sliced else "k_cw_narrow / k_cw_wide" if form == "claim" else "k_level")
         traffic = measured_traffic() if (args.workload == "rmat22" and sliced) else None
         per_search = [i["kernel_us"] + i["init_us"] for i in infos]
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": kname,
-                    "init_kernel": "k_sl_init" if sliced else "k_cw_fill" if args.push_impl == "claim" else "k_init",
+                    "push_form": form,
+                    "init_kernel": "k_sl_init" if sliced else "k_cw_fill" if form == "claim" else "k_init",
                     "algorithmic_bytes_per_search": round(bytes_total / nsearch),
                     "kernel_us_per_search": round(kern_us / nsearch, 2),
                     "level_kernel_us_per_search": round(level_us / nsearch, 2),
@@ -505,12 +506,13 @@ def other_workload(wname, args, msw):
         nz = int(deg[lv >= 0].sum())
         m_c.append(nz if g.directed else nz // 2)
         levels.append(int(info["levels"]))
+        form = info.get("push_used", "list")
     tm = float(sum(m_c))
     steps = max(1, min(args.steps, 3))
     dt = time_calls(lambda: [P.bfs(G, s, level=level, parent=parent, workspace=ws) for s in src], steps)
     res = {"graph": desc, "n": g.n, "nnz": g.nnz, "sources": len(src), "mean_levels": float(np.mean(levels)),
            "plain_push": {"gteps": round(tm / dt / 1e9, 3), "ms_per_step": round(dt * 1e3, 3),
-                          "us_per_level": round(dt * 1e6 / sum(levels), 2)}}
+                          "us_per_level": round(dt * 1e6 / sum(levels), 2), "form": form}}
     if len(src) > 1:
         del ws, level, parent
         torch.cuda.empty_cache()

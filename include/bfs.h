@@ -112,8 +112,8 @@ typedef struct bfs_run_options {
     uint32_t launches;         /* out (time_kernels): level-kernel launches issued, including
                                   launches after the last level, which return at once          */
     float kernel_us;           /* out (time_kernels): summed device time of those launches      */
-    uint32_t push_impl;        /* BFS_VARIANT_PUSH only: BFS_PUSH_AUTO (0), BFS_PUSH_LIST or
-                                  BFS_PUSH_SLICED (see below)                                   */
+    uint32_t push_impl;        /* BFS_VARIANT_PUSH only: BFS_PUSH_AUTO (0), BFS_PUSH_LIST,
+                                  BFS_PUSH_SLICED or BFS_PUSH_CLAIM (see below)                 */
     float init_us;             /* out (time_kernels, bfs_run): device time of the search's
                                   initialisation launch (outputs to -1, bitmaps cleared)        */
     uint32_t ms_ranges;        /* multi-source searches of at most 64 sources: on pull levels
@@ -123,6 +123,9 @@ typedef struct bfs_run_options {
                                   masks can stay in L2 (0 or 1 = one pass over the whole
                                   lists, the default: measured faster; at most 64).  Never
                                   changes a result.                                            */
+    uint32_t push_used;        /* out (bfs_run, bfs_run_roots): the form of the push that ran,
+                                  BFS_PUSH_LIST / _SLICED / _CLAIM (the list form's kernels
+                                  also run the other variants)                                 */
 } bfs_run_options;
 
 /*
@@ -153,9 +156,11 @@ typedef struct bfs_run_options {
  *                    other forms pay a grid-wide launch per level.  Needs
  *                    variant PUSH and the host loop (BFS_EINVAL otherwise);
  *                    fills no trace.
- *   BFS_PUSH_AUTO    sliced when it applies and n >= 2^17; else, with the host
- *                    loop, claim-word when the sliced form does not apply
- *                    (n > 4 * 2^20) and the average degree is at most 8; the
+ *   BFS_PUSH_AUTO    from the out-degrees (after duplicates and self-loops are
+ *                    removed): claim-word, with the host loop, when every
+ *                    out-degree is at most 8 (grids, road-like graphs);
+ *                    sliced when it applies, n >= 2^17 and the largest
+ *                    out-degree is at least 16 times the average (hubs); the
  *                    list form otherwise.
  */
 enum {
@@ -240,8 +245,9 @@ bfs_status bfs_run(bfs_graph *g, int32_t source,
  * the same graph, the searches advance together, 64 sources per 64-bit mask
  * per vertex (one pass over a column serves every source whose frontier holds
  * it) - except with opt->push_impl BFS_PUSH_CLAIM, or with the automatic
- * choice for variant PUSH (host loop) on a graph beyond 2^22 vertices of
- * average degree at most 8, where they run as claim-word searches (below).  opt->variant picks the direction per level: PUSH (default) scatters
+ * choice for variant PUSH (host loop) on a graph beyond 2^22 vertices whose
+ * out-degrees are all at most 8, where they run as claim-word searches
+ * (below).  opt->variant picks the direction per level: PUSH (default) scatters
  * the frontier masks along out-edges; PULL lets every unsettled vertex gather
  * its in-neighbours' masks in ascending order; HEURISTIC pushes while the
  * union frontier holds at most n >> ms_pull_shift vertices and pulls after;

@@ -18,6 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import BfsError, LOOPS, VARIANTS, VARIANT_NAMES, LevelRecord, RunOptions
 
+PUSH_IMPL_NAMES = {v: k for k, v in _lib.PUSH_IMPLS.items()}
+
 __all__ = ["Graph", "bfs", "bfs_static", "bfs_batch", "bfs_batch_vm", "batch_vm_workspace_size",
            "batch_workspace_size", "bfs_roots",
            "bfs_compare", "compare_workspace_size", "masked_spmspv",
@@ -196,6 +198,7 @@ def bfs(g: Graph, source: int, variant="push", loop="host", level=None, parent=N
         info["launches"] = o.launches
         info["kernel_us"] = o.kernel_us
         info["init_us"] = o.init_us
+        info["push_used"] = PUSH_IMPL_NAMES.get(int(o.push_used), "list")
         if trace:
             info["trace"] = trace_dicts(o, recs)
     return level, parent
@@ -236,6 +239,7 @@ def bfs_roots(g: Graph, roots: Sequence[int], variant="push", loop="host", level
                                         workspace.ptr, workspace.nbytes, _stream_handle(stream)))
     if info is not None:
         info["levels"] = o.levels
+        info["push_used"] = PUSH_IMPL_NAMES.get(int(o.push_used), "list")
     return level, parent
 
 

@@ -34,7 +34,8 @@ class RunOptions(ctypes.Structure):
                 ("time_kernels", ctypes.c_uint32), ("trace_count", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32), ("launches", ctypes.c_uint32),
                 ("kernel_us", ctypes.c_float), ("push_impl", ctypes.c_uint32),
-                ("init_us", ctypes.c_float), ("ms_ranges", ctypes.c_uint32)]
+                ("init_us", ctypes.c_float), ("ms_ranges", ctypes.c_uint32),
+                ("push_used", ctypes.c_uint32)]
 
 
 class BfsError(RuntimeError):

@@ -41,6 +41,7 @@ struct GraphExecCache {
 struct bfs_graph {
     int32_t n = 0;
     uint32_t nnz = 0;
+    uint32_t max_deg = 0;             // largest out-degree (after duplicates and self-loops are removed)
     bool directed = false;
     int device = 0;
     int cus = 0;
@@ -805,26 +806,33 @@ uint32_t sl_grid(const bfs_graph *g) {
     return per * r;
 }
 
-// The automatic choice of the push's form (measured, one search from each of
-// 64 sources on R-MAT s22, 16 on directed R-MAT s20, one on Erdos-Renyi 16K,
-// two on the 4096^2 grid): the sliced form where it applies, except on
-// graphs below kSlMinAuto vertices (its per-level set-up, ~38 us, exceeds the
-// list form's ~19 us there); beyond the sliced form's size limit, the
-// claim-word form on graphs of average degree at most kClaimMaxAvgDeg (thin
-// frontiers, few masked entries per level: 2x the list form on the grid) and
-// the list form otherwise (hub columns make one atomic per entry costly).
+// The automatic choice of the push's form, from the degree distribution
+// (measured, one search each: R-MAT s18 / s20 / s22, Erdos-Renyi 2^18 x 16 and
+// 2^20 x 8, 1024^2 / 2048^2 / 4096^2 grids, a pack of 64 ER graphs):
+//   - bounded small degree (every out-degree <= kClaimMaxDeg: grids,
+//     road-like graphs, thousands of thin levels): the claim-word form (grid
+//     2048^2: 25.9 ms, list 57.4, sliced 122.9);
+//   - skewed degrees (the largest out-degree at least kSlSkew x the average:
+//     hubs) on 2^17 <= n <= 2^22: the sliced form (R-MAT s20: 0.42 ms, list
+//     0.72);
+//   - otherwise the list form (ER 2^18 x 16: 0.29 ms, sliced 0.57; the ER
+//     pack: 1.00 ms, sliced 2.74).
 constexpr int32_t kSlMinAuto = 1 << 17;
-constexpr uint64_t kClaimMaxAvgDeg = 8;
+constexpr uint32_t kClaimMaxDeg = 8;
+constexpr uint64_t kSlSkew = 16;
+
+// Thin: every out-degree at most kClaimMaxDeg.
+bool thin_graph(const bfs_graph *g) { return g->max_deg <= kClaimMaxDeg; }
+
+bool skewed_graph(const bfs_graph *g) {
+    return (uint64_t)g->max_deg * (uint64_t)g->n >= kSlSkew * (uint64_t)g->nnz;
+}
 
 bool sliced_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
     const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
     if (c.policy != kPush || g->sl_S == 0 || c.loop == BFS_LOOP_PERSISTENT) return false;
-    return impl == BFS_PUSH_SLICED || (impl == BFS_PUSH_AUTO && g->n >= kSlMinAuto);
-}
-
-// Thin: beyond the sliced form's size limit, average degree at most kClaimMaxAvgDeg.
-bool thin_graph(const bfs_graph *g) {
-    return g->sl_S == 0 && (uint64_t)g->nnz <= kClaimMaxAvgDeg * (uint64_t)g->n;
+    return impl == BFS_PUSH_SLICED ||
+           (impl == BFS_PUSH_AUTO && g->n >= kSlMinAuto && skewed_graph(g) && !thin_graph(g));
 }
 
 bool claim_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
@@ -836,14 +844,15 @@ bool claim_applies(const bfs_graph *g, const RunCfg &c, const bfs_run_options *o
 // Many sources on one graph as claim-word searches (each source its own
 // words, all in lockstep) instead of the 64-per-word multi-source kernels:
 // asked for (push_impl CLAIM), or the automatic choice for the push on a thin
-// graph - its levels are too small for the multi-source kernels' two grid-wide
-// launches per level (4096^2 grid, 16 sources: 33 us per level there).
+// graph beyond the sliced form's size limit - its levels are too small for
+// the multi-source kernels' two grid-wide launches per level (4096^2 grid, 16
+// sources: 33 us per level there).
 bool claim_batch_applies(const bfs_graph *g, const bfs_run_options *opt) {
     const uint32_t impl = opt ? opt->push_impl : BFS_PUSH_AUTO;
     const uint32_t pol = opt ? opt->variant : kPush;
     const uint32_t loop = opt ? opt->loop_mode : BFS_LOOP_HOST;
     if (impl == BFS_PUSH_CLAIM) return true;
-    return impl == BFS_PUSH_AUTO && pol == kPush && loop == BFS_LOOP_HOST && thin_graph(g);
+    return impl == BFS_PUSH_AUTO && pol == kPush && loop == BFS_LOOP_HOST && thin_graph(g) && g->sl_S == 0;
 }
 
 bfs_status check_push_impl(const bfs_graph *g, const RunCfg &c, const bfs_run_options *opt) {
@@ -1004,6 +1013,7 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
     if (!g) return fail(BFS_ENOMEM, "host allocation failed");
     g->n = n;
     g->nnz = (uint32_t)ptr[n];
+    for (int32_t v = 0; v < n; ++v) g->max_deg = std::max<uint32_t>(g->max_deg, (uint32_t)(ptr[v + 1] - ptr[v]));
     g->directed = directed;
     if (hipGetDevice(&g->device) != hipSuccess) { delete g; return fail(BFS_EHIP, "hipGetDevice failed"); }
     if (hipDeviceGetAttribute(&g->cus, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess)
@@ -1063,7 +1073,7 @@ size_t bfs_workspace_size(const bfs_graph *g, int32_t num_queries, uint32_t run_
     size_t need = std::max(single, ms_layout(g->n, num_queries).total);
     // thin graphs (or when asked): room for the claim-word batch too (see
     // claim_batch_applies)
-    if (thin_graph(g) || (run_flags & BFS_WS_CLAIM))
+    if ((thin_graph(g) && g->sl_S == 0) || (run_flags & BFS_WS_CLAIM))
         need = std::max(need, cw_layout((uint64_t)g->n * (uint64_t)num_queries,
                                         (uint64_t)g->nnz * (uint64_t)num_queries, (uint32_t)num_queries).total);
     return need;
@@ -1087,10 +1097,13 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
     if (st != BFS_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
     if (claim_applies(g, c, opt)) {
+        if (opt) opt->push_used = BFS_PUSH_CLAIM;
         const ClaimQuery q{g, source, level, parent};
         return run_claim(&q, 1, workspace, ws_bytes, s, g->cus, opt);
     }
-    if (sliced_applies(g, c, opt))
+    const bool sliced = sliced_applies(g, c, opt);
+    if (opt) opt->push_used = sliced ? BFS_PUSH_SLICED : BFS_PUSH_LIST;
+    if (sliced)
         return run_sliced(g, source, 1, nullptr, level, parent, c, workspace, s, opt);
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
@@ -1134,7 +1147,9 @@ extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t 
     hipStream_t s = (hipStream_t)hip_stream;
     int32_t *roots_dev = (int32_t *)((char *)workspace + base);
     HIP_TRY(hipMemcpyAsync(roots_dev, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, s));
-    if (sliced_applies(g, c, opt))
+    const bool sliced = sliced_applies(g, c, opt);
+    if (opt) opt->push_used = sliced ? BFS_PUSH_SLICED : BFS_PUSH_LIST;
+    if (sliced)
         return run_sliced(g, -1, nroots, roots_dev, level, parent, c, workspace, s, opt);
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);

@@ -190,3 +190,32 @@ def test_claim_batch_on_one_graph(P, cases, name):
     lv, pa = P.bfs_batch(G, src, push_impl="claim")
     torch.cuda.synchronize()
     compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"claim batch {name}")
+
+
+def test_auto_form_from_degrees(P):
+    """The automatic push picks its form from the out-degrees: claim-word when
+    every out-degree is at most 8 (a grid, a path), sliced on a graph with hubs
+    of at least 2^17 vertices (R-MAT), the list form on flat degrees (ER) and
+    on small graphs; the searches equal the oracle's and report the form."""
+    cases = [("grid", graphgen.grid(200, 0.9, 91), "claim"),
+             ("path", graphgen.path_graph(3000), "claim"),
+             ("rmat17", graphgen.rmat(17, 16, 92), "sliced"),
+             ("er17", graphgen.erdos_renyi(1 << 17, 16, 93), "list"),
+             ("rmat12", graphgen.rmat(12, 16, 94), "list")]
+    for name, g, want in cases:
+        G = P.Graph.from_graphgen(g)
+        s = int(graphgen.pick_sources(g, 1, 95)[0])
+        say(f"[auto] {name} s={s}")
+        info = {}
+        got = run_gpu(P, G, s, info=info)
+        assert info["push_used"] == want, (name, info["push_used"])
+        assert_same(g, s, got, f"auto/{name}")
+    # several roots over a block-diagonal pack of ER graphs: the list form
+    fam = graphgen.er_family(count=8, lo=12, hi=15)
+    pack, offs = graphgen.block_diagonal(fam)
+    G = P.Graph.from_graphgen(pack)
+    roots = [int(o) for o in offs[:-1]]
+    info = {}
+    say("[auto] ER pack roots")
+    P.bfs_roots(G, roots, info=info)
+    assert info["push_used"] == "list"
