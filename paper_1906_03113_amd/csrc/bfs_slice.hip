@@ -280,20 +280,67 @@ __device__ __forceinline__ uint32_t expand(const SlParams &P, SlLds &L, uint32_t
 // first kSettleFirst entries of every pending vertex are loaded in
 // settle_issue (before the batch's expansion, so that their latency overlaps
 // it; positions past a list's end repeat its last entry, which cannot change
-// the first hit) and tested in settle_finish; a vertex with more entries and
-// no hit among those is finished by the whole wave, 256 entries per step.
-constexpr int kSettleFirst = 8;
+// the first hit) and tested in settle_finish; vertices with no hit go on in
+// steps of kSettleNext entries, every pending vertex of the wave at once,
+// for up to kSettleRounds steps in all; a vertex still pending after those
+// is finished by the whole wave, 256 entries per step.  The first step is
+// short because the first entry is the hit for almost every vertex of a big
+// level (on R-MAT the smallest in-neighbour of a vertex reached from the hub
+// level lies in it): each entry tested is a random read of the C_{k-1}
+// bitmap, the settle's whole cost.
+constexpr int kSettleFirst = 2;
+constexpr int kSettleNext = 8;
+constexpr int kSettleRounds = 4;
 
+template <int N>
 __device__ __forceinline__ void settle_issue(const SlParams &P, const bool (&pending)[kCols],
                                              const int32_t (&pos)[kCols], const int32_t (&end)[kCols],
-                                             int32_t (&u)[kCols * kSettleFirst]) {
+                                             int32_t (&u)[kCols * N]) {
 #pragma unroll
     for (int p = 0; p < (int)kCols; ++p) {
         const int32_t last = pending[p] ? end[p] - 1 : 0;
 #pragma unroll
-        for (int t = 0; t < kSettleFirst; ++t) {
+        for (int t = 0; t < N; ++t) {
             const int32_t e = pending[p] ? pos[p] + t : 0;
-            u[kSettleFirst * p + t] = P.in_idx[e < last ? e : last];
+            u[N * p + t] = P.in_idx[e < last ? e : last];
+        }
+    }
+}
+
+// The C_{k-1} words of the N entries u of each pending vertex.
+template <int N>
+__device__ __forceinline__ void settle_probe(const uint32_t *prev, const bool (&pending)[kCols],
+                                             const int32_t (&u)[kCols * N], uint32_t (&wv)[kCols * N]) {
+#pragma unroll
+    for (int x = 0; x < (int)kCols * N; ++x) {
+        wv[x] = 0u;
+        if (pending[x / N]) wv[x] = prev[(uint32_t)u[x] >> 5];
+    }
+}
+
+// One step: the N entries u (loaded from positions from[p] ..) with their
+// C_{k-1} words wv; a hit settles the vertex, otherwise it stays pending
+// while entries remain.
+template <int N>
+__device__ __forceinline__ void settle_test(const SlParams &P, uint32_t k, const int32_t (&v)[kCols],
+                                            bool (&pending)[kCols], int32_t (&from)[kCols],
+                                            const int32_t (&end)[kCols], const int32_t (&u)[kCols * N],
+                                            const uint32_t (&wv)[kCols * N]) {
+#pragma unroll
+    for (int p = 0; p < (int)kCols; ++p) {
+        int32_t hit = -1;
+#pragma unroll
+        for (int t = N - 1; t >= 0; --t)
+            if ((wv[N * p + t] >> (u[N * p + t] & 31)) & 1u) hit = u[N * p + t];
+        from[p] += N;
+        if (pending[p]) {
+            if (hit >= 0) {
+                P.level[v[p]] = (int32_t)k;
+                P.parent[v[p]] = hit;
+                pending[p] = false;
+            } else {
+                pending[p] = from[p] < end[p];
+            }
         }
     }
 }
@@ -301,7 +348,8 @@ __device__ __forceinline__ void settle_issue(const SlParams &P, const bool (&pen
 __device__ __forceinline__ void settle_finish(const SlParams &P, const uint32_t *prev, uint32_t k,
                                               const int32_t (&v)[kCols], bool (&pending)[kCols],
                                               const int32_t (&pos)[kCols], const int32_t (&end)[kCols],
-                                              const int32_t (&u)[kCols * kSettleFirst]) {
+                                              const int32_t (&u)[kCols * kSettleFirst],
+                                              const uint32_t (&wv)[kCols * kSettleFirst]) {
     const uint32_t lane = lane_id();
     if (k == 0) {
 #pragma unroll
@@ -313,28 +361,21 @@ __device__ __forceinline__ void settle_finish(const SlParams &P, const uint32_t 
             }
         return;
     }
-    uint32_t wv[kCols * kSettleFirst];
-#pragma unroll
-    for (int x = 0; x < (int)kCols * kSettleFirst; ++x) wv[x] = prev[(uint32_t)u[x] >> 5];
     int32_t from[kCols];
 #pragma unroll
-    for (int p = 0; p < (int)kCols; ++p) {
-        int32_t hit = -1;
+    for (int p = 0; p < (int)kCols; ++p) from[p] = pos[p];
+    settle_test<kSettleFirst>(P, k, v, pending, from, end, u, wv);
+    for (int r = 1; r < kSettleRounds; ++r) {
+        bool any = false;
 #pragma unroll
-        for (int t = kSettleFirst - 1; t >= 0; --t)
-            if ((wv[kSettleFirst * p + t] >> (u[kSettleFirst * p + t] & 31)) & 1u) hit = u[kSettleFirst * p + t];
-        from[p] = pos[p] + kSettleFirst;
-        if (pending[p]) {
-            if (hit >= 0) {
-                P.level[v[p]] = (int32_t)k;
-                P.parent[v[p]] = hit;
-                pending[p] = false;
-            } else {
-                pending[p] = from[p] < end[p];
-            }
-        }
+        for (int p = 0; p < (int)kCols; ++p) any = any || pending[p];
+        if (!__ballot(any)) break;                     // uniform
+        int32_t u2[kCols * kSettleNext];
+        uint32_t w2[kCols * kSettleNext];
+        settle_issue<kSettleNext>(P, pending, from, end, u2);
+        settle_probe<kSettleNext>(prev, pending, u2, w2);
+        settle_test<kSettleNext>(P, k, v, pending, from, end, u2, w2);
     }
-#pragma unroll
     for (int p = 0; p < (int)kCols; ++p) {
         unsigned long long hm = __ballot(pending[p]);
         while (hm) {
@@ -672,12 +713,15 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_level(SlParams P) {
                 }
 #pragma unroll
                 for (int p = 0; p < (int)kCols; ++p) pend[p] = pend[p] && (k == 0 || pos[p] < end[p]);
-                {
-                    int32_t su[kCols * kSettleFirst];
-                    if (k != 0) settle_issue(P, pend, pos, end, su);
-                    settle_finish(P, prev, k, v, pend, pos, end, su);
+                // the first settle step's loads are in flight during the expansion
+                int32_t su[kCols * kSettleFirst];
+                uint32_t sw[kCols * kSettleFirst];
+                if (k != 0) {
+                    settle_issue<kSettleFirst>(P, pend, pos, end, su);
+                    settle_probe<kSettleFirst>(prev, pend, su, sw);
                 }
                 claims += expand(P, L, wave, sbase, sv, ep, ra, re, v);
+                settle_finish(P, prev, k, v, pend, pos, end, su, sw);
             }
         }
     }
