@@ -144,10 +144,10 @@ __device__ __forceinline__ void mark_lazy4(SlLds &L, uint32_t sbase, uint32_t sv
 // Eager: the pairs (j, i) of a lane's quads.  For a row i not visited
 // through level k (B_k read from L2, all the lane's words loaded together),
 // j competes for parent[i] by atomicMin (Lemma 1's form: every such pair
-// contributes, so the result is the smallest), i joins C_{k+1} and takes
-// level k + 1.  None of these waits for an answer: the atomics return nothing
-// and the stores of one row all write the same value.  A quad's four mask
-// words are loaded together.  Returns the pairs
+// contributes, so the result is the smallest) and i joins C_{k+1} (its level
+// is written when level k + 1 scans C_{k+1}).  None of these waits for an
+// answer: the atomics return nothing.  A quad's four mask words are loaded
+// together.  Returns the pairs
 // (an upper bound of the rows claimed, 0 iff none).
 __device__ __forceinline__ uint32_t mark_eager4(const SlParams &P, const Eager &E,
                                                 const int4 (&d)[kQuadsPerLane],
@@ -175,7 +175,6 @@ __device__ __forceinline__ uint32_t mark_eager4(const SlParams &P, const Eager &
             if (on[x] && !((mw[x] >> (r[x] & 31)) & 1u)) {
                 atomicMin(&par[r[x]], (uint32_t)cj[i]);
                 atomicOr(&E.nxt[(uint32_t)r[x] >> 5], 1u << (r[x] & 31));
-                P.level[r[x]] = (int32_t)(E.k + 1);
                 ++pairs;
             }
         }
@@ -274,8 +273,9 @@ __device__ __forceinline__ uint32_t expand(const SlParams &P, SlLds &L, uint32_t
     return claims;
 }
 
-// Level and parent of the frontier vertices of F_k a lane settles (up to
-// kCols; pending[p] set for each).  At level 0 they are roots.  Otherwise the
+// Parent of the frontier vertices of F_k a lane settles (up to kCols;
+// pending[p] set for each; their level is written by the scan of C_k).  At
+// level 0 they are roots.  Otherwise the
 // parent is the first in-neighbour, in ascending order, in C_{k-1}.  The
 // first kSettleFirst entries of every pending vertex are loaded in
 // settle_issue (before the batch's expansion, so that their latency overlaps
@@ -335,7 +335,6 @@ __device__ __forceinline__ void settle_test(const SlParams &P, uint32_t k, const
         from[p] += N;
         if (pending[p]) {
             if (hit >= 0) {
-                P.level[v[p]] = (int32_t)k;
                 P.parent[v[p]] = hit;
                 pending[p] = false;
             } else {
@@ -355,7 +354,6 @@ __device__ __forceinline__ void settle_finish(const SlParams &P, const uint32_t 
 #pragma unroll
         for (int p = 0; p < (int)kCols; ++p)
             if (pending[p]) {
-                P.level[v[p]] = 0;
                 P.parent[v[p]] = v[p];
                 pending[p] = false;
             }
@@ -403,10 +401,7 @@ __device__ __forceinline__ void settle_finish(const SlParams &P, const uint32_t 
                     if (found < 0 && m) found = __shfl(w[t], __ffsll((long long)m) - 1, 64);
                 }
             }
-            if (lane == 0 && found >= 0) {
-                P.level[hv] = (int32_t)k;
-                P.parent[hv] = found;
-            }
+            if (lane == 0 && found >= 0) P.parent[hv] = found;
         }
     }
 }
@@ -635,11 +630,15 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_level(SlParams P) {
     unsigned long long n_settled = 0, deg_settled = 0, claims = 0;
 
     // long parts of frontier columns in slice s, as chunks: wave gw of the
-    // slice takes records c0 + gw, c0 + gw + nw, ... (64 per step, one per lane)
+    // slice takes records c0 + gw, c0 + gw + nw, ... (64 per step, one per
+    // lane).  Consecutive gw lie in different workgroups (a column's chunks
+    // are consecutive records: a hub's chunks spread over the compute units
+    // instead of filling one workgroup's waves, whose random memory
+    // operations would queue on one unit)
     {
         const uint32_t c0 = pick4(P.chunk_off[0], P.chunk_off[1], P.chunk_off[2], P.chunk_off[3], s);
         const uint32_t c1 = pick4(P.chunk_off[1], P.chunk_off[2], P.chunk_off[3], P.chunk_off[4], s);
-        const uint64_t gw = (uint64_t)q * kSlWaves + wave, nw = (uint64_t)P.streams * kSlWaves;
+        const uint64_t gw = (uint64_t)wave * P.streams + q, nw = (uint64_t)P.streams * kSlWaves;
         for (uint64_t jb = 0; c0 + gw + jb * nw < c1; jb += 64) {
             const uint64_t r = c0 + gw + (jb + lane) * nw;
             const SlChunk ch = P.chunks[r < c1 ? r : c1 - 1];     // c1 > c0 here
@@ -667,6 +666,21 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_level(SlParams P) {
         for (uint32_t sw0 = ws0 + wave * 64u; sw0 < ws1; sw0 += kSlWaves * 64u) {
             const uint32_t wi = sw0 + lane;
             uint32_t fw = (wi < ws1) ? cur[wi] : 0u;
+            // level k for every vertex of the segment in C_k, by one of the
+            // stream's S workgroups: for each pair of words 2j, 2j + 1 with a
+            // bit, lane t writes vertex t of the pair, so each store covers
+            // 64 consecutive vertices (two lines) instead of one line per
+            // vertex
+            const unsigned long long nzw = __ballot(fw != 0u);
+            if ((sw0 >> 6) % S == s) {
+                unsigned long long pairs = (nzw | (nzw >> 1)) & 0x5555555555555555ull;
+                while (pairs) {                                      // uniform
+                    const uint32_t j2 = (uint32_t)__ffsll((long long)pairs) - 1u;
+                    pairs &= pairs - 1ull;
+                    const uint32_t w = (uint32_t)__shfl((int)fw, (int)(j2 + (lane >> 5)), 64);
+                    if ((w >> (lane & 31u)) & 1u) P.level[(sw0 + j2) * 32u + lane] = (int32_t)k;
+                }
+            }
             while (__ballot(fw != 0u)) {
                 int32_t v[kCols], vend[kCols];
                 int4 sg[kCols];
