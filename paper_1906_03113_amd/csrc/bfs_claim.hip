@@ -129,6 +129,9 @@ __device__ __forceinline__ Ref ref_of(const CwParams &P, const Ref &one, uint32_
 __device__ __forceinline__ void settle_after_issue(unsigned long long &x) {
     asm volatile("" : "+v"(x));
 }
+__device__ __forceinline__ void settle_after_issue32(uint32_t &x) {
+    asm volatile("" : "+v"(x));
+}
 
 // A wave's staging of the next level's short columns in LDS: appends are
 // gathered here (a ballot and an LDS write per batch) and go to the global
@@ -269,16 +272,22 @@ __global__ __launch_bounds__(kCwBlock) void k_cw_wide(CwParams P, uint32_t k) {
     __shared__ uint32_t s_stage[kCwBlock / 64][kCwStage];
     CwState *st = P.st;
     const uint32_t t0 = k % 3, t1 = (k + 1) % 3, t2 = (k + 2) % 3;
-    const uint32_t ns = st->cnt[t0][0], nc = st->cnt[t0][2];
     const CwLists C = P.lists[k & 1], N = P.lists[(k + 1) & 1];
+    const uint32_t lane = lane_id();
+    const uint32_t gw = blockIdx.x * (kCwBlock / 64) + (threadIdx.x >> 6);
+    const uint32_t nw = gridDim.x * (kCwBlock / 64);
+    // the lane's entry of the wave's first step, read together with the
+    // counts (before it is known to exist: the list has room for V entries)
+    // instead of one round trip after them
+    const uint32_t i_first = gw * 64u + lane;
+    uint32_t x_first = C.s[i_first < P.V ? i_first : 0u];
+    const uint32_t ns = st->cnt[t0][0], nc = st->cnt[t0][2];
+    settle_after_issue32(x_first);
     if (blockIdx.x == 0 && threadIdx.x < 4) st->cnt[t2][threadIdx.x] = 0u;   // level k+2's lists
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->level = k + 1;
         if (ns + nc != 0) st->last = k;                          // the deepest level with a frontier
     }
-    const uint32_t lane = lane_id();
-    const uint32_t gw = blockIdx.x * (kCwBlock / 64) + (threadIdx.x >> 6);
-    const uint32_t nw = gridDim.x * (kCwBlock / 64);
     const uint32_t sw = (ns + 63) / 64;
     // test the row's word before the atomic on wide levels (most rows are
     // settled there; the test saves their atomics), not on thin ones (where a
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(kCwBlock) void k_cw_wide(CwParams P, uint32_t k) {
         if (it < sw) {
             const uint32_t i = it * 64 + lane;
             Col c{};
-            if (i < ns) c = column(P, C.s[i]);
+            if (i < ns) c = column(P, it == gw ? x_first : C.s[i]);
             const unsigned long long key = offer_key(k + 1, c.u);
             const uint32_t rounds = (uint32_t)wave_max((int32_t)c.deg);
             for (uint32_t r = 0; r < rounds; r += kCwUnroll) {
