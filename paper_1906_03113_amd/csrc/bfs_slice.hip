@@ -526,17 +526,40 @@ __device__ __forceinline__ uint32_t owner(int32_t v, uint32_t S) {
     return o;
 }
 
-// Up to kCols frontier vertices of a lane's word, lowest bit first (v[p] = -1
-// when the word has run out; v[0] < 0 means none).
-__device__ __forceinline__ void pop_batch(uint32_t &fw, uint32_t wi, int32_t (&v)[kCols]) {
+// A batch of the segment's frontier vertices, compacted over the wave: the
+// vertex of rank b0 + 64 p + lane among the segment's set bits (ascending),
+// v[p] = -1 past the last.  Lane j holds word sw0 + j of the segment, with
+// excl_j of the segment's bits before it.  (Popping each lane's own word
+// instead leaves a batch's lanes idle once their words run out: on a dense
+// level the fullest of 64 words sets the number of batches.)
+__device__ __forceinline__ void select_batch(uint32_t fw, uint32_t excl, uint32_t total, uint32_t b0,
+                                             uint32_t sw0, int32_t (&v)[kCols]) {
+    const uint32_t lane = lane_id();
 #pragma unroll
     for (int p = 0; p < (int)kCols; ++p) {
-        v[p] = -1;
-        if (fw) {
-            const uint32_t bit = (uint32_t)__ffs((int)fw) - 1u;
-            fw &= fw - 1u;
-            v[p] = (int32_t)(wi * 32u + bit);
+        const uint32_t r = b0 + (uint32_t)p * 64u + lane;
+        // the last lane j with excl_j <= r (the word holding rank r)
+        uint32_t j = 0;
+#pragma unroll
+        for (uint32_t step = 32; step; step >>= 1) {
+            const uint32_t e = (uint32_t)__shfl((int)excl, (int)(j + step), 64);
+            if (e <= r) j += step;
         }
+        uint32_t w = (uint32_t)__shfl((int)fw, (int)j, 64);
+        uint32_t kk = r - (uint32_t)__shfl((int)excl, (int)j, 64);
+        // the kk-th set bit of w: halve the window, skipping halves whose
+        // bits come before it
+        uint32_t bit = 0;
+#pragma unroll
+        for (uint32_t h = 16; h; h >>= 1) {
+            const uint32_t lo = (uint32_t)__popc(w & ((1u << h) - 1u));
+            if (kk >= lo) {
+                kk -= lo;
+                w >>= h;
+                bit += h;
+            }
+        }
+        v[p] = r < total ? (int32_t)((sw0 + j) * 32u + bit) : -1;
     }
 }
 
@@ -658,7 +681,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_level(SlParams P) {
     // every frontier vertex: settle it (if this slice owns it and level k - 1
     // left it unsettled) and expand its short part in slice s.  The stream's
     // words are cut into 64-word segments (2048 vertices) dealt to the waves; a
-    // batch takes up to kCols frontier vertices per lane, lowest bit first.
+    // batch takes the segment's next 64 kCols frontier vertices, kCols per lane.
     {
         const uint32_t wps = (((P.words + P.streams - 1u) / P.streams) + 63u) & ~63u;
         const uint32_t ws0 = q * wps;
@@ -681,10 +704,14 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_level(SlParams P) {
                     if ((w >> (lane & 31u)) & 1u) P.level[(sw0 + j2) * 32u + lane] = (int32_t)k;
                 }
             }
-            while (__ballot(fw != 0u)) {
+            const uint32_t cnt = (uint32_t)__popc(fw);
+            const uint32_t incl = wave_incl_scan(cnt);
+            const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+            const uint32_t excl = incl - cnt;
+            for (uint32_t b0 = 0; b0 < total; b0 += 64u * kCols) {          // uniform
                 int32_t v[kCols], vend[kCols];
                 int4 sg[kCols];
-                pop_batch(fw, wi, v);
+                select_batch(fw, excl, total, b0, sw0, v);
                 load_starts(P, v, sg, vend);
                 int32_t ra[kCols], re[kCols], pos[kCols], end[kCols];
                 bool pend[kCols];
