@@ -105,10 +105,10 @@ __device__ __forceinline__ int32_t quad_at(const int4 &q, uint32_t x) {
     return x == 0 ? q.x : (x == 1 ? q.y : (x == 2 ? q.z : q.w));
 }
 
-// Lazy: claim every reached row in the slice (rows outside it cannot occur;
-// the bound is a guard only).  All the words are read first, then a row
-// whose bit is clear (not visited, not yet claimed by this workgroup) is set
-// and its 4-word group flagged for the flush.
+// Lazy: claim every reached row in the slice (a part's rows all lie in it).
+// All the words are read first, then a row whose bit is clear (not visited,
+// not yet claimed by this workgroup) is set and its 4-word group flagged for
+// the flush.
 __device__ __forceinline__ void mark_lazy4(SlLds &L, uint32_t sbase, uint32_t sv,
                                            const int4 (&d)[kQuadsPerLane], const int32_t (&eb)[kQuadsPerLane],
                                            const int32_t (&ca)[kQuadsPerLane],
@@ -118,16 +118,20 @@ __device__ __forceinline__ void mark_lazy4(SlLds &L, uint32_t sbase, uint32_t sv
         uint32_t w[4 * kMarkQuads], m[4 * kMarkQuads];
         bool on[4 * kMarkQuads];
 #pragma unroll
-        for (uint32_t i = 0; i < kMarkQuads; ++i)
+        for (uint32_t i = 0; i < kMarkQuads; ++i) {
+            // entry eb + x counts when it lies in [ca, ce): one unsigned compare
+            const uint32_t off = (uint32_t)(eb[h + i] - ca[h + i]), len = (uint32_t)(ce[h + i] - ca[h + i]);
 #pragma unroll
             for (uint32_t x = 0; x < 4; ++x) {
-                const uint32_t e = (uint32_t)(eb[h + i] + (int32_t)x);
+                // a part's rows lie in its slice (the slice starts split each
+                // sorted list at the slice bounds): li < sv needs no test
                 const uint32_t li = (uint32_t)quad_at(d[h + i], x) - sbase;
-                const bool ok = e >= (uint32_t)ca[h + i] && e < (uint32_t)ce[h + i] && li < sv;
+                const bool ok = off + x < len;
                 on[4 * i + x] = ok;
                 w[4 * i + x] = ok ? li >> 5 : 0u;
-                m[4 * i + x] = ok ? 1u << (li & 31) : 0u;
+                m[4 * i + x] = 1u << (li & 31);
             }
+        }
         uint32_t cur[4 * kMarkQuads];
 #pragma unroll
         for (uint32_t u = 0; u < 4 * kMarkQuads; ++u) cur[u] = L.slice[w[u]];
