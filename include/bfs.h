@@ -126,6 +126,15 @@ typedef struct bfs_run_options {
     uint32_t push_used;        /* out (bfs_run, bfs_run_roots): the form of the push that ran,
                                   BFS_PUSH_LIST / _SLICED / _CLAIM (the list form's kernels
                                   also run the other variants)                                 */
+    uint32_t count_atomics;    /* bfs_run with the list form's kernels only (else BFS_EINVAL):
+                                  0 = off; 1 = count the parent atomicMin operations the push
+                                  levels issue into `atomics`; 2 = the same with the parent
+                                  pre-read off, so that every pair (j, i) with level[i] =
+                                  level[j] + 1 issues exactly one: the count of Lemma 1's
+                                  products that reach an unvisited row.  Never changes a
+                                  result.                                                      */
+    uint32_t reserved0;
+    uint64_t atomics;          /* out (count_atomics): the count                                 */
 } bfs_run_options;
 
 /*

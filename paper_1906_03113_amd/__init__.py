@@ -144,9 +144,10 @@ class Workspace:
 def make_options(variant="push", loop="host", levels_per_sync=0, grid_blocks=0,
                  heavy_degree=0, chunk_edges=0, selector=None, trace_capacity=0,
                  time_kernels=False, ms_pull_shift=0,
-                 push_impl="auto", ms_ranges=0) -> Tuple[RunOptions, Optional[ctypes.Array]]:
+                 push_impl="auto", ms_ranges=0, count_atomics=0) -> Tuple[RunOptions, Optional[ctypes.Array]]:
     o = RunOptions()
     o.ms_ranges = int(ms_ranges)
+    o.count_atomics = int(count_atomics)
     o.push_impl = _lib.PUSH_IMPLS[push_impl] if isinstance(push_impl, str) else int(push_impl)
     o.time_kernels = 1 if time_kernels else 0
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
@@ -199,6 +200,8 @@ def bfs(g: Graph, source: int, variant="push", loop="host", level=None, parent=N
         info["kernel_us"] = o.kernel_us
         info["init_us"] = o.init_us
         info["push_used"] = PUSH_IMPL_NAMES.get(int(o.push_used), "list")
+        if o.count_atomics:
+            info["atomics"] = int(o.atomics)
         if trace:
             info["trace"] = trace_dicts(o, recs)
     return level, parent

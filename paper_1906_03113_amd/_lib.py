@@ -35,7 +35,8 @@ class RunOptions(ctypes.Structure):
                 ("levels", ctypes.c_uint32), ("launches", ctypes.c_uint32),
                 ("kernel_us", ctypes.c_float), ("push_impl", ctypes.c_uint32),
                 ("init_us", ctypes.c_float), ("ms_ranges", ctypes.c_uint32),
-                ("push_used", ctypes.c_uint32)]
+                ("push_used", ctypes.c_uint32), ("count_atomics", ctypes.c_uint32),
+                ("reserved0", ctypes.c_uint32), ("atomics", ctypes.c_uint64)]
 
 
 class BfsError(RuntimeError):

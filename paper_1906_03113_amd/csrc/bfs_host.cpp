@@ -1095,6 +1095,10 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
     }
     st = check_push_impl(g, c, opt);
     if (st != BFS_OK) return st;
+    const uint32_t count = opt ? opt->count_atomics : 0u;
+    if (count > 2u) return fail(BFS_EINVAL, "count_atomics = %u (0, 1 or 2)", count);
+    if (count && (claim_applies(g, c, opt) || sliced_applies(g, c, opt)))
+        return fail(BFS_EINVAL, "count_atomics needs the list form of the push (push_impl LIST)");
     hipStream_t s = (hipStream_t)hip_stream;
     if (claim_applies(g, c, opt)) {
         if (opt) opt->push_used = BFS_PUSH_CLAIM;
@@ -1107,12 +1111,22 @@ bfs_status bfs_run(bfs_graph *g, int32_t source, int32_t *level, int32_t *parent
         return run_sliced(g, source, 1, nullptr, level, parent, c, workspace, s, opt);
     LevelParams P;
     make_params(g, level, parent, c, workspace, opt && opt->trace != nullptr, P);
+    if (count) {                                    // zeroed by the init launch
+        P.atomics = &P.st->atomics;
+        P.no_preread = count == 2u ? 1u : 0u;
+    }
     st = timed_init(g, opt, s, [&]() { return launch_init(P, 1, nullptr, source, s); });
     if (st != BFS_OK) return st;
     uint32_t levels = 0;
     st = run_levels(g, P, c, s, levels, opt);
     if (st != BFS_OK) return st;
     if (opt) opt->levels = levels;
+    if (count) {
+        unsigned long long a = 0;
+        HIP_TRY(hipMemcpyAsync(&a, P.atomics, sizeof(a), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        opt->atomics = a;
+    }
     return BFS_OK;
 }
 
@@ -1144,6 +1158,7 @@ extern "C" bfs_status bfs_run_roots(bfs_graph *g, int32_t nroots, const int32_t 
     if (st != BFS_OK) return st;
     if (opt && opt->push_impl == BFS_PUSH_CLAIM)
         return fail(BFS_EINVAL, "the claim-word push runs single searches and bfs_run_batch, not several roots");
+    if (opt && opt->count_atomics) return fail(BFS_EINVAL, "count_atomics is for bfs_run");
     hipStream_t s = (hipStream_t)hip_stream;
     int32_t *roots_dev = (int32_t *)((char *)workspace + base);
     HIP_TRY(hipMemcpyAsync(roots_dev, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, s));

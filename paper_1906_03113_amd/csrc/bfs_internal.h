@@ -41,6 +41,7 @@ struct alignas(256) BfsState {
     // per-group release generations (one line each): the top release is
     // watched by the groups' last arrivals only, everyone else watches its group
     uint32_t bar_gen_group[kBarGroups * 16];
+    unsigned long long atomics;          // parent atomicMin operations issued (when counted)
 };
 // Per-level record kept on the device (a trace ring of kTraceCap entries).
 struct DevLevelRec {
@@ -82,6 +83,8 @@ struct LevelParams {
     uint32_t *host_status;   // pinned host memory: [0] level, [1] its frontier size
     uint32_t maintain_fb;
     uint32_t stats;
+    unsigned long long *atomics;   // count the push's parent atomicMin operations here, or nullptr
+    uint32_t no_preread;           // 1: every unmasked pair issues its atomicMin (no pre-read)
 };
 
 struct WsLayout {

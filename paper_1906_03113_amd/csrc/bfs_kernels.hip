@@ -433,7 +433,7 @@ __device__ __forceinline__ void settle4(const LevelParams &P, const LevelPtrs &L
         // small level the pre-read is skipped: its latency costs more than
         // the few atomics it would save); the atomic that found the slot
         // empty claims the row
-        const bool pre = L.pre;
+        const bool pre = L.pre && !P.no_preread;
         const uint32_t p0 = (u0 && pre) ? ld_agent(&P.parent[i0]) : 0xFFFFFFFFu;
         const uint32_t p1 = (u1 && pre) ? ld_agent(&P.parent[i1]) : 0xFFFFFFFFu;
         const uint32_t p2 = (u2 && pre) ? ld_agent(&P.parent[i2]) : 0xFFFFFFFFu;
@@ -448,6 +448,13 @@ __device__ __forceinline__ void settle4(const LevelParams &P, const LevelPtrs &L
         o1 = t1 && a1 == 0xFFFFFFFFu;
         o2 = t2 && a2 == 0xFFFFFFFFu;
         o3 = t3 && a3 == 0xFFFFFFFFu;
+        if (P.atomics) {                                 // counted: one add per wave
+            const unsigned long long act = __ballot(true);
+            const uint32_t na = (uint32_t)(__popcll(__ballot(t0)) + __popcll(__ballot(t1)) +
+                                           __popcll(__ballot(t2)) + __popcll(__ballot(t3)));
+            if (lane_id() == (uint32_t)__ffsll((long long)act) - 1u && na)
+                atomicAdd(P.atomics, (unsigned long long)na);
+        }
         if (o0) P.level[i0] = nk;
         if (o1) P.level[i1] = nk;
         if (o2) P.level[i2] = nk;
@@ -955,6 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_init(LevelParams P, int32_t single_r
         st->bar_top = 0;
         st->visited_cnt = 0;
         st->visited_deg = 0ull;
+        st->atomics = 0ull;
         for (int r = 0; r < kRing; ++r) {
             st->nf[r] = 0;
             st->heavy[r] = 0ull;
