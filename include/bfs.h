@@ -269,12 +269,17 @@ bfs_status bfs_run(bfs_graph *g, int32_t source,
  * and, where the host read it, the union frontier's size.
  * Queries on different graphs (any mix, repeats allowed) run together, as one
  * search over the block-diagonal matrix of their graphs with one root per
- * block, without copying a graph: the library gives query q the vertex ids
- * [base_q, base_q + n_q) of a virtual vertex space and runs the claim-word
- * push (BFS_PUSH_CLAIM) over all of them, one launch per level for every
- * query (or one narrow launch for many levels while the joint frontier is
- * small); they need variant PUSH and the host loop.  One query is bfs_run.
- * The result for query q is bit-identical to bfs_run(graphs[q], sources[q]).
+ * block: query q gets the vertex ids [base_q, base_q + n_q).  When no graph
+ * is thin (some out-degree above 8), or with opt->push_impl BFS_PUSH_LIST,
+ * the library packs the graphs' out-lists into one CSR in the workspace
+ * (ids offset by base_q) and runs the list form of the push from the
+ * queries' roots; otherwise, or with BFS_PUSH_CLAIM, it runs the claim-word
+ * push over the virtual ids without copying a graph, one launch per level
+ * for every query (or one narrow launch for many levels while the joint
+ * frontier is small).  Either way they need variant PUSH and the host loop
+ * (BFS_PUSH_SLICED: BFS_EINVAL); opt->push_used reports the form.  One query
+ * is bfs_run.  The result for query q is bit-identical to
+ * bfs_run(graphs[q], sources[q]).
  * workspace: bfs_batch_workspace_size(num_queries, graphs) bytes, 256-byte
  * aligned.
  * Errors: BFS_EINVAL, BFS_ERANGE, BFS_EHIP.

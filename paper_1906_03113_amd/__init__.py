@@ -288,6 +288,8 @@ def bfs_batch(graphs, sources: Sequence[int], variant="push", loop="host", level
                                         workspace.nbytes, _stream_handle(stream)))
     if info is not None:
         info["levels"] = int(o.levels)
+        if not all(gr is graphs[0] for gr in graphs):
+            info["push_used"] = PUSH_IMPL_NAMES.get(int(o.push_used), "list")
         if trace:
             info["trace"] = _ms_trace(o, recs)
     return levels, parents

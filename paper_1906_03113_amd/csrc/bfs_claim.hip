@@ -599,6 +599,44 @@ hipError_t launch_cw_narrow(const CwParams &p, uint32_t k, uint32_t max_levels, 
     return hipGetLastError();
 }
 
+// The queries' out-lists into one block-diagonal CSR: row base_q + v holds
+// query q's row v with every entry offset by base_q (a block row of the grid
+// per query; the packed offsets of a query's last row and the next query's
+// first are the same number, written by both).
+__global__ __launch_bounds__(kCwBlock) void k_pack(PackParams P) {
+    const PackQuery &Q = P.q[blockIdx.y];
+    const uint32_t t0 = blockIdx.x * kCwBlock + threadIdx.x, ts = gridDim.x * kCwBlock;
+    for (uint32_t v = t0; v <= Q.n; v += ts) P.ptr[Q.base + v] = Q.ptr[v] + (int32_t)Q.ebase;
+    for (uint32_t e = t0; e < Q.nnz; e += ts) P.idx[Q.ebase + e] = Q.idx[e] + (int32_t)Q.base;
+    if (blockIdx.y == 0)
+        for (uint32_t e = P.E + t0; e < P.pad_end; e += ts) P.idx[e] = 0;
+}
+
+// The packed results into the callers' arrays (parents back to the query's ids).
+__global__ __launch_bounds__(kCwBlock) void k_unpack(PackParams P) {
+    const PackQuery &Q = P.q[blockIdx.y];
+    for (uint32_t v = blockIdx.x * kCwBlock + threadIdx.x; v < Q.n; v += gridDim.x * kCwBlock) {
+        const int32_t l = P.level[Q.base + v], p = P.parent[Q.base + v];
+        Q.level[v] = l;
+        Q.parent[v] = p >= 0 ? p - (int32_t)Q.base : -1;
+    }
+}
+
+hipError_t launch_pack(const PackParams &p, hipStream_t s) {
+    const uint32_t work = p.max_nnz > p.max_n + 1u ? p.max_nnz : p.max_n + 1u;
+    uint32_t gx = (work + kCwBlock - 1) / kCwBlock;
+    gx = gx < 1024u ? (gx ? gx : 1u) : 1024u;
+    hipLaunchKernelGGL(k_pack, dim3(gx, p.nq), dim3(kCwBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const PackParams &p, hipStream_t s) {
+    uint32_t gx = (p.max_n + kCwBlock - 1) / kCwBlock;
+    gx = gx < 1024u ? (gx ? gx : 1u) : 1024u;
+    hipLaunchKernelGGL(k_unpack, dim3(gx, p.nq), dim3(kCwBlock), 0, s, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_cw_out(const CwParams &p, hipStream_t s) {
     uint32_t gx = (p.max_n + kCwBlock - 1) / kCwBlock;
     gx = gx < 1024u ? (gx ? gx : 1u) : 1024u;

@@ -328,6 +328,26 @@ hipError_t launch_cw_narrow(const CwParams &p, uint32_t k, uint32_t max_levels, 
                             uint32_t max_edges, hipStream_t s);
 hipError_t launch_cw_out(const CwParams &p, hipStream_t s);
 
+// Queries on different graphs searched as one block-diagonal graph by the
+// list form: the library packs the graphs' out-lists (vertex ids offset by
+// each query's base) and splits the packed results back (bfs_claim.hip).
+struct PackQuery {
+    const int32_t *ptr, *idx;                 // the query's graph (out-lists)
+    int32_t *level, *parent;                  // the caller's outputs
+    uint32_t base, n;                         // first packed vertex, vertices
+    uint32_t ebase, nnz;                      // first packed entry, entries
+};
+struct PackParams {
+    const PackQuery *q;                       // device, nq
+    uint32_t nq;
+    uint32_t max_n, max_nnz;
+    uint32_t E, pad_end;                      // packed entries; idx is zero-filled in [E, pad_end)
+    int32_t *ptr, *idx;                       // packed CSR: V + 1 offsets, pad_end entries
+    const int32_t *level, *parent;            // packed results [V]
+};
+hipError_t launch_pack(const PackParams &p, hipStream_t s);
+hipError_t launch_unpack(const PackParams &p, hipStream_t s);
+
 // The comparison searches of the Experiments section (bfs_compare.hip).
 enum CmpMethod : uint32_t { kCmpSpmv = 0, kCmpSpmspv = 1, kCmpSpmmspv = 2 };
 

@@ -219,3 +219,32 @@ def test_auto_form_from_degrees(P):
     say("[auto] ER pack roots")
     P.bfs_roots(G, roots, info=info)
     assert info["push_used"] == "list"
+
+
+def test_mixed_batch_both_forms(P):
+    """Queries on different graphs in either form of the library: the list form
+    over the graphs packed into one block-diagonal graph (the automatic choice
+    when no graph is thin) and the claim-word form (the automatic choice with a
+    grid in the mix); each forced on the other's mix too.  Every query against
+    the oracle, repeats of one graph included."""
+    import torch
+    fam = graphgen.er_family(count=12, lo=9, hi=13)
+    flat = fam + [graphgen.rmat(12, 16, 71), graphgen.rmat(11, 16, 72, directed=True)]
+    mixes = {"flat": flat, "with_grid": flat[:6] + [graphgen.grid(100, 0.9, 73)]}
+    for name, gs in mixes.items():
+        Gs = [P.Graph.from_graphgen(g) for g in gs]
+        graphs, srcs, hosts = [], [], []
+        for i, (g, G) in enumerate(zip(gs, Gs)):
+            for s in graphgen.pick_sources(g, 2 if i == 0 else 1, 80 + i):
+                graphs.append(G); srcs.append(int(s)); hosts.append(g)
+        auto = "claim" if name == "with_grid" else "list"
+        for impl in ("auto", "list", "claim"):
+            say(f"[mixed] {name} push_impl={impl}")
+            info = {}
+            lv, pa = P.bfs_batch(graphs, srcs, push_impl=impl, info=info)
+            torch.cuda.synchronize()
+            assert info["push_used"] == (auto if impl == "auto" else impl), (name, impl, info)
+            for q, (g, s) in enumerate(zip(hosts, srcs)):
+                assert_same(g, s, (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/{impl}/q{q}")
+        with pytest.raises(P.BfsError):
+            P.bfs_batch(graphs, srcs, push_impl="sliced")
