@@ -102,6 +102,8 @@ __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const 
 // (k_ms_out reads only entries whose vis bit is set), and k_ms_out writes
 // every output; when the staged arrays are the caller's vertex-major outputs
 // the levels start at -1 too (there is no k_ms_out).
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
     const size_t gid = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kBlock;
@@ -113,11 +115,13 @@ __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
         p.m[2][i] = 0ull;
     }
     for (size_t v = gid; v < (size_t)p.n; v += stride) p.flag[v] = 0u;
-    const size_t ns = (size_t)p.n * p.W * 16u;          // staged parents, 16 bytes at a time
-    for (size_t i = gid; i < ns; i += stride)
-        reinterpret_cast<uint4 *>(p.spar)[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    // staged parents, 16 bytes at a time, streaming stores (not read by
+    // this kernel, and far larger than the caches)
+    const size_t ns = (size_t)p.n * p.W * 16u;
+    const v4i ones = {-1, -1, -1, -1};
+    for (size_t i = gid; i < ns; i += stride) __builtin_nontemporal_store(ones, reinterpret_cast<v4i *>(p.spar) + i);
     if (p.fill_levels)                                  // the caller's arrays: unreached = -1
-        for (size_t i = gid; i < ns; i += stride) reinterpret_cast<int4 *>(p.slev)[i] = make_int4(-1, -1, -1, -1);
+        for (size_t i = gid; i < ns; i += stride) __builtin_nontemporal_store(ones, reinterpret_cast<v4i *>(p.slev) + i);
     if (gid < 4) p.cnt[gid] = 0u;
     if (gid < 3) p.rcnt[gid] = 0u;
     if (gid < (size_t)kMsStatWords) p.mstat[gid] = 0ull;
@@ -734,10 +738,12 @@ __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
                 pa[r] = lv[r];
                 bits[r] = 0;
                 if (v < p.n) bits[r] = (uint32_t)(row(p.vis, v, W)[w] >> g4) & 15u;
-                if (bits[r]) {
+                if (bits[r]) {                          // read once: streaming loads
                     const size_t at = (size_t)v * S + w * 64u + g4;
-                    lv[r] = *reinterpret_cast<const int4 *>(p.slev + at);
-                    pa[r] = *reinterpret_cast<const int4 *>(p.spar + at);
+                    const v4i a = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p.slev + at));
+                    const v4i b = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p.spar + at));
+                    lv[r] = make_int4(a.x, a.y, a.z, a.w);
+                    pa[r] = make_int4(b.x, b.y, b.z, b.w);
                 }
             }
             int4 out_l[4], out_p[4];
@@ -771,8 +777,10 @@ __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
                 const int4 a = out_l[r], b = out_p[r];
                 const bool full = v0 + (int32_t)g4 + 3 < p.n;
                 if (full && ((reinterpret_cast<uintptr_t>(lo) | reinterpret_cast<uintptr_t>(po)) & 15u) == 0) {
-                    *reinterpret_cast<int4 *>(lo) = a;
-                    *reinterpret_cast<int4 *>(po) = b;
+                    // written once and not read here again: streaming stores
+                    const v4i av = {a.x, a.y, a.z, a.w}, bv = {b.x, b.y, b.z, b.w};
+                    __builtin_nontemporal_store(av, reinterpret_cast<v4i *>(lo));
+                    __builtin_nontemporal_store(bv, reinterpret_cast<v4i *>(po));
                 } else {
                     const int32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
