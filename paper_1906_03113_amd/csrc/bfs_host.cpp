@@ -56,6 +56,7 @@ struct bfs_graph {
     // out-lists and the chunks of long slice parts; sl_S = 0 when the graph's
     // bitmap needs more than kSlMaxSlices slices
     int4 *sl_seg = nullptr;
+    uint32_t *sl_occ = nullptr;       // per slice, the vertices whose part there is short and not empty
     bfsi::SlChunk *sl_chunks = nullptr;
     uint32_t sl_S = 0, sl_sw = 0;
     uint32_t sl_chunk_off[bfsi::kSlMaxSlices + 1] = {};
@@ -147,6 +148,7 @@ void free_graph(bfs_graph *g) {
     if (g->out_ptr) (void)hipFree(g->out_ptr);
     if (g->out_idx) (void)hipFree(g->out_idx);
     if (g->sl_seg) (void)hipFree(g->sl_seg);
+    if (g->sl_occ) (void)hipFree(g->sl_occ);
     if (g->sl_chunks) (void)hipFree(g->sl_chunks);
     delete g;
 }
@@ -208,6 +210,18 @@ bfs_status build_slices(bfs_graph *g, const std::vector<int32_t> &ptr, const std
     }
     const int32_t nnz = ptr[n];
     seg[n] = make_int4(nnz, nnz, nnz, nnz);
+    // per slice, a bit for each vertex whose part there the frontier loop
+    // expands (short, not empty); long parts go by chunks
+    const uint64_t allw = (uint64_t)S * sw;
+    std::vector<uint32_t> occ((size_t)(S * allw), 0u);
+    for (int32_t v = 0; v < n; ++v) {
+        const int4 q = seg[v];
+        for (uint32_t s = 0; s < S; ++s) {
+            const int32_t a = s == 0 ? q.x : (s == 1 ? q.y : (s == 2 ? q.z : q.w));
+            const int32_t e = s == 3 ? seg[v + 1].x : (s == 0 ? q.y : (s == 1 ? q.z : q.w));
+            if (e > a && e - a < (int32_t)bfsi::kSlLong) occ[(size_t)(s * allw) + ((uint32_t)v >> 5)] |= 1u << (v & 31);
+        }
+    }
     std::vector<bfsi::SlChunk> ch;
     uint32_t off[bfsi::kSlMaxSlices + 1] = {};
     for (uint32_t s = 0; s < bfsi::kSlMaxSlices; ++s) {
@@ -225,6 +239,7 @@ bfs_status build_slices(bfs_graph *g, const std::vector<int32_t> &ptr, const std
     off[bfsi::kSlMaxSlices] = (uint32_t)ch.size();
     bfs_status st = upload(&g->sl_seg, seg.data(), seg.size(), g->bytes);
     if (st == BFS_OK) st = upload(&g->sl_chunks, ch.data(), ch.size(), g->bytes);
+    if (st == BFS_OK) st = upload(&g->sl_occ, occ.data(), occ.size(), g->bytes);
     if (st != BFS_OK) return st;
     g->sl_S = (uint32_t)S;
     g->sl_sw = sw;
@@ -983,6 +998,7 @@ SlParams make_sl_params(bfs_graph *g, int32_t *level, int32_t *parent, void *ws,
     P.words = g->sl_S * g->sl_sw;
     P.streams = sl_grid(g) / g->sl_S;
     P.seg = g->sl_seg;
+    P.occ = g->sl_occ;
     P.out_idx4 = (const int4 *)g->out_idx;
     P.in_ptr = g->directed ? g->in_ptr : nullptr;
     P.in_idx = g->in_idx;
@@ -1992,12 +2008,14 @@ extern "C" bfs_status bfs_graph_set_slice_words(bfs_graph *g, uint32_t max_words
         return fail(BFS_ENOMEM, "host allocation failed");
     }
     int4 *old_seg = g->sl_seg;
+    uint32_t *old_occ = g->sl_occ;
     SlChunk *old_ch = g->sl_chunks;
     const uint32_t old_S = g->sl_S, old_sw = g->sl_sw;
     uint32_t old_off[kSlMaxSlices + 1];
     for (uint32_t i = 0; i <= kSlMaxSlices; ++i) old_off[i] = g->sl_chunk_off[i];
     const size_t old_bytes = g->bytes;
     g->sl_seg = nullptr;
+    g->sl_occ = nullptr;
     g->sl_chunks = nullptr;
     g->sl_S = 0;
     bfs_status st;
@@ -2008,8 +2026,10 @@ extern "C" bfs_status bfs_graph_set_slice_words(bfs_graph *g, uint32_t max_words
     }
     if (st != BFS_OK) {                       // keep the old cut
         if (g->sl_seg) (void)hipFree(g->sl_seg);
+        if (g->sl_occ) (void)hipFree(g->sl_occ);
         if (g->sl_chunks) (void)hipFree(g->sl_chunks);
         g->sl_seg = old_seg;
+        g->sl_occ = old_occ;
         g->sl_chunks = old_ch;
         g->sl_S = old_S;
         g->sl_sw = old_sw;
@@ -2019,6 +2039,7 @@ extern "C" bfs_status bfs_graph_set_slice_words(bfs_graph *g, uint32_t max_words
     }
     size_t freed = 0;
     if (old_seg) { (void)hipFree(old_seg); freed += ((size_t)g->n + 1) * sizeof(int4); }
+    if (old_occ) { (void)hipFree(old_occ); freed += (size_t)old_S * old_S * old_sw * 4; }
     if (old_ch) {
         (void)hipFree(old_ch);
         const size_t nch = old_off[kSlMaxSlices];

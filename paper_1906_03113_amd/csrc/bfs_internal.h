@@ -145,6 +145,8 @@ struct SlParams {
     uint32_t words;                  // S * sw: words of every bitmap (padded)
     uint32_t streams;                // workgroups per slice
     const int4 *seg;                 // [n + 1]: {out_ptr[v], start of slices 1, 2, 3 in v's out-list}
+    const uint32_t *occ;             // [S][words]: bit v of slice s = v's part in slice s is short and
+                                     // not empty (the frontier loop's work there)
     const int4 *out_idx4;            // out_idx as 16-byte quads (padded to a multiple of 4 entries)
     const int32_t *in_ptr, *in_idx;  // in-lists (undirected: the out-lists)
     const SlChunk *chunks;           // chunk records, slice s at [chunk_off[s], chunk_off[s + 1])

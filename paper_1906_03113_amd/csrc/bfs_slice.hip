@@ -687,6 +687,12 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_level(SlParams P) {
     // words are cut into 64-word segments (2048 vertices) dealt to the waves; a
     // batch takes the segment's next 64 kCols frontier vertices, kCols per lane.
     {
+        // bits j of a word whose vertex 32 w + j this workgroup owns (owner
+        // depends on v mod 4 only, and 32 w is a multiple of 4)
+        uint32_t own_bits = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+            if (owner((int32_t)j, S) == s) own_bits |= 0x11111111u << j;
         const uint32_t wps = (((P.words + P.streams - 1u) / P.streams) + 63u) & ~63u;
         const uint32_t ws0 = q * wps;
         const uint32_t ws1 = (ws0 + wps < P.words) ? ws0 + wps : P.words;
@@ -708,14 +714,18 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_level(SlParams P) {
                     if ((w >> (lane & 31u)) & 1u) P.level[(sw0 + j2) * 32u + lane] = (int32_t)k;
                 }
             }
-            const uint32_t cnt = (uint32_t)__popc(fw);
+            // this workgroup's vertices of the segment: those whose part in
+            // slice s is short and not empty (P.occ), and the ones it settles
+            // and counts (owner s) whatever their part
+            const uint32_t fo = fw & (((wi < ws1) ? P.occ[s * P.words + wi] : 0u) | own_bits);
+            const uint32_t cnt = (uint32_t)__popc(fo);
             const uint32_t incl = wave_incl_scan(cnt);
             const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
             const uint32_t excl = incl - cnt;
             for (uint32_t b0 = 0; b0 < total; b0 += 64u * kCols) {          // uniform
                 int32_t v[kCols], vend[kCols];
                 int4 sg[kCols];
-                select_batch(fw, excl, total, b0, sw0, v);
+                select_batch(fo, excl, total, b0, sw0, v);
                 load_starts(P, v, sg, vend);
                 int32_t ra[kCols], re[kCols], pos[kCols], end[kCols];
                 bool pend[kCols];
