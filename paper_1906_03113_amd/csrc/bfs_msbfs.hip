@@ -83,16 +83,34 @@ __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const 
     unsigned long long below = __shfl_up(incl, 1u, (int)G);
     if (li == 0) below = 0ull;
     unsigned long long own = hit & ~below;
+    const unsigned long long found = __shfl(incl, (int)(G - 1u), (int)G);
+    // each found bit's parent (the u of the lane that owns it) through the
+    // group's row of 64 LDS slots, then written by source: lane li takes
+    // sources li, li + G, ..., so the staged row goes out in 64 / G stores
+    // of consecutive entries instead of one store per bit
+    __shared__ uint32_t s_par[kBlock / 64][(64 / G) * 64];   // a row per group of the wave
+    uint32_t *slot = &s_par[threadIdx.x >> 6][(__lane_id() / G) * 64u];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     while (own) {
         const uint32_t b = (uint32_t)__ffsll((long long)own) - 1u;
         own &= own - 1ull;
-        const uint32_t q = w * 64u + b;
-        const size_t at = stage(p, v, q);
-        p.slev[at] = (int32_t)lk;
-        if (owner_alone) p.spar[at] = (uint32_t)u;
-        else atomicMin(&p.spar[at], (uint32_t)u);
+        slot[b] = (uint32_t)u;
     }
-    return __shfl(incl, (int)(G - 1u), (int)G);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t b = li; b < 64u; b += G) {
+        if ((found >> b) & 1ull) {
+            const size_t at = stage(p, v, w * 64u + b);
+            const uint32_t pu = slot[b];
+            p.slev[at] = (int32_t)lk;
+            if (owner_alone) p.spar[at] = pu;
+            else atomicMin(&p.spar[at], pu);
+        }
+    }
+    return found;
 }
 
 }  // namespace
