@@ -52,6 +52,7 @@ struct bfs_graph {
     bfsi::MsLong *lo = nullptr, *li = nullptr;
     uint32_t *lomap = nullptr, *limap = nullptr;
     uint32_t nlo = 0, nlo_chunks = 0, nli = 0, nli_chunks = 0;
+    uint32_t *lirest = nullptr;       // the long rows' later chunks, by position in the row, then row
     // sliced push (bfs_slice.hip): per-vertex slice starts in the sorted
     // out-lists and the chunks of long slice parts; sl_S = 0 when the graph's
     // bitmap needs more than kSlMaxSlices slices
@@ -143,6 +144,7 @@ void free_graph(bfs_graph *g) {
     if (g->limap && g->limap != g->lomap) (void)hipFree(g->limap);
     if (g->lo) (void)hipFree(g->lo);
     if (g->lomap) (void)hipFree(g->lomap);
+    if (g->lirest) (void)hipFree(g->lirest);
     if (g->in_ptr && g->in_ptr != g->out_ptr) (void)hipFree(g->in_ptr);
     if (g->in_idx && g->in_idx != g->out_idx) (void)hipFree(g->in_idx);
     if (g->out_ptr) (void)hipFree(g->out_ptr);
@@ -171,6 +173,26 @@ bfs_status build_long(int32_t n, const std::vector<int32_t> &ptr, bfsi::MsLong *
     bfs_status st = upload(ents, e.data(), e.size(), bytes);
     if (st == BFS_OK) st = upload(map, m.data(), m.size(), bytes);
     return st;
+}
+
+// The chunk ids of every long row's chunks but its first, ordered by the
+// chunk's position in its row (1, 2, ...) and then by row: the pull's later
+// chunks run in this order, so that a row's earlier chunks have mostly
+// finished (and settled their sources) when its later ones start.
+bfs_status build_rest(int32_t n, const std::vector<int32_t> &ptr, uint32_t **out, size_t &bytes) {
+    std::vector<std::vector<uint32_t>> by_pos;
+    uint32_t base = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const uint32_t deg = (uint32_t)(ptr[v + 1] - ptr[v]);
+        if (deg < bfsi::kMsLong) continue;
+        const uint32_t nch = (deg + bfsi::kMsChunk - 1) / bfsi::kMsChunk;
+        if (by_pos.size() < nch) by_pos.resize(nch);
+        for (uint32_t j = 1; j < nch; ++j) by_pos[j].push_back(base + j);
+        base += nch;
+    }
+    std::vector<uint32_t> order;
+    for (const auto &b : by_pos) order.insert(order.end(), b.begin(), b.end());
+    return upload(out, order.data(), order.size(), bytes);
 }
 
 // The out-lists, padded with zeros to a multiple of four entries plus four, so
@@ -1160,6 +1182,7 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
             g->nli = g->nlo;
             g->nli_chunks = g->nlo_chunks;
         }
+        if (st == BFS_OK) st = build_rest(n, directed ? iptr : ptr, &g->lirest, g->bytes);
     } catch (const std::bad_alloc &) {
         st = fail(BFS_ENOMEM, "host allocation failed");
     }
@@ -1380,6 +1403,7 @@ static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
     p.nlo_chunks = g->nlo_chunks;
     p.nli = g->nli;
     p.nli_chunks = g->nli_chunks;
+    p.lirest = g->lirest;
     p.slev = vm ? vm_level : (int32_t *)(b + L.slev);
     p.spar = vm ? (uint32_t *)vm_parent : (uint32_t *)(b + L.spar);
     p.fill_levels = vm ? 1u : 0u;

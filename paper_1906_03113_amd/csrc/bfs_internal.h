@@ -200,6 +200,7 @@ struct MsLevel {
     const MsLong *lo, *li;
     const uint32_t *lomap, *limap;
     uint32_t nlo_chunks, nli, nli_chunks;
+    const uint32_t *lirest;        // the long rows' chunks but their first, by position in the row, then row
     // results staged vertex-major while the search runs, [n][W * 64]: row v
     // holds every source's level / parent of v (valid where vis has the bit),
     // so the writes of one row share its 256-byte lines; k_ms_out transposes

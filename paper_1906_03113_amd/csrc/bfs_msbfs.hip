@@ -59,7 +59,13 @@ __device__ __forceinline__ bool in_frontier(const MsLevel &p, int32_t u) {
 // within the wave) over in_idx[eb + lane-in-group] (lanes past e1 hold
 // nothing): each bit of rem held by some lane's cur mask goes to the lowest
 // such lane, i.e. to the smallest in-neighbour of the step.  Returns the bits
-// found (the same in every lane of the group).
+// found (the same in every lane of the group).  scan_resolve is the second
+// half, given each lane's entry u and its mask bits already restricted to rem.
+template <uint32_t G>
+__device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int32_t v, uint32_t w,
+                                                           int32_t u, unsigned long long hit,
+                                                           uint32_t lk, bool owner_alone);
+
 template <uint32_t G>
 __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const unsigned long long *cur,
                                                         int32_t v, uint32_t w, int32_t eb, int32_t e1,
@@ -73,6 +79,14 @@ __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const 
         u = p.in_idx[e];
         if (in_frontier(p, u)) hit = row(cur, u, p.W)[w] & rem;
     }
+    return scan_resolve<G>(p, v, w, u, hit, lk, owner_alone);
+}
+
+template <uint32_t G>
+__device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int32_t v, uint32_t w,
+                                                           int32_t u, unsigned long long hit,
+                                                           uint32_t lk, bool owner_alone) {
+    const uint32_t li = __lane_id() & (G - 1u);
     if (__ballot(hit != 0ull) == 0ull) return 0ull;        // (uniform) nothing found in the wave
     unsigned long long incl = hit;
 #pragma unroll
@@ -432,6 +446,61 @@ __global__ __launch_bounds__(kBlock) void k_ms_fbits(MsLevel p, uint32_t k) {
     }
 }
 
+// Entries [e0, e1) of row v scanned by the whole wave for the sources in rem
+// until every one is found; returns the bits found.  The first batch is one
+// step of 64 entries (on a dense frontier most rows end there), every later
+// one four steps: their index loads, then their bitmap tests, then their mask
+// gathers, each four deep in flight.  With prune (a long row's
+// chunk after its first), each batch first drops the sources that an earlier
+// chunk of the row has settled at an in-neighbour below the batch's first
+// entry: staged parents only decrease within the level, so a stale read only
+// keeps a source longer.
+__device__ __forceinline__ unsigned long long scan_wave4(const MsLevel &p, const unsigned long long *cur,
+                                                         int32_t v, uint32_t w, int32_t e0, int32_t e1,
+                                                         unsigned long long rem, uint32_t lk,
+                                                         bool owner_alone, bool prune) {
+    const uint32_t W = p.W;
+    const int32_t lane = (int32_t)__lane_id();
+    unsigned long long found = 0ull;
+    int32_t nst = 1;                                                    // steps in this batch
+    for (int32_t eb = e0; eb < e1 && rem; eb += nst * 64, nst = 4) {
+        int32_t uu[4];
+        bool ok[4];
+        unsigned long long mm[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int32_t e = eb + t * 64 + lane;
+            uu[t] = (t < nst && e < e1) ? p.in_idx[e] : -1;
+        }
+        if (prune) {
+            const uint32_t sp = p.spar[stage(p, v, w * 64u + (uint32_t)lane)];
+            rem &= ~__ballot(sp < (uint32_t)__shfl(uu[0], 0, 64));
+            if (!rem) break;                                            // uniform
+        }
+        if (p.use_fbits) {
+            unsigned long long fb[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) fb[t] = uu[t] >= 0 ? p.fbits[(uint32_t)uu[t] >> 6] : 0ull;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) ok[t] = ((fb[t] >> ((uint32_t)uu[t] & 63u)) & 1ull) != 0ull;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) ok[t] = uu[t] >= 0;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) mm[t] = ok[t] ? row(cur, uu[t], W)[w] : 0ull;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (rem) {                                                  // uniform
+                const unsigned long long f = scan_resolve<64>(p, v, w, uu[t], mm[t] & rem, lk, owner_alone);
+                rem &= ~f;
+                found |= f;
+            }
+        }
+    }
+    return found;
+}
+
 // Level k, pull form (for large frontiers): every vertex v whose sources are
 // not all settled ORs, in ascending in-neighbour order, the frontier masks of
 // its in-neighbours restricted to the sources that have not reached it; each
@@ -458,12 +527,7 @@ __device__ __forceinline__ void long_chunk(const MsLevel &p, const unsigned long
     unsigned long long *vis = row(p.vis, v, W);
     for (uint32_t w = 0; w < W; ++w) {
         const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
-        unsigned long long rem = full & ~vis[w], found = 0ull;
-        for (int32_t eb = e0; eb < e1 && rem; eb += 64) {
-            const unsigned long long f = scan_step<64>(p, cur, v, w, eb, e1, rem, k + 1, false);
-            rem &= ~f;
-            found |= f;
-        }
+        const unsigned long long found = scan_wave4(p, cur, v, w, e0, e1, full & ~vis[w], k + 1, false, j != 0);
         if (found && __lane_id() == 0) {
             atomicOr(&row(nxt, v, W)[w], found);
             if (first) vis[w] |= found;
@@ -637,12 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                 for (uint32_t w = 0; w < W; ++w) {
                     const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
                     const unsigned long long sv = vis[w];
-                    unsigned long long rem = full & ~sv, found = 0ull;
-                    for (int32_t eb = we0; eb < we1 && rem; eb += 64) {
-                        const unsigned long long f = scan_step<64>(p, cur, wv, w, eb, we1, rem, lk, true);
-                        rem &= ~f;
-                        found |= f;
-                    }
+                    const unsigned long long found = scan_wave4(p, cur, wv, w, we0, we1, full & ~sv, lk, true, false);
                     if (found) {
                         if (lane == 0) {
                             row(nxt, wv, W)[w] = found;
@@ -685,14 +744,19 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
 // each looks only for the sources the row's first chunk left unsettled (vis
 // holds those found there), gives its first hits to the staged parents by
 // atomicMin (the smallest over the chunks) and ORs its bits into the next
-// mask; k_ms_fixup then folds those into vis and lists the rows.
+// mask; k_ms_fixup then folds those into vis and lists the rows.  The chunks
+// are taken every row's second chunk first, then the third, ..., so that
+// most chunks find their row's earlier chunks done and skip the sources
+// those settled.
 __global__ __launch_bounds__(kBlock) void k_ms_pull_rest(MsLevel p, uint32_t k) {
     const unsigned long long *cur = pick3<const unsigned long long *>(p.m[0], p.m[1], p.m[2], k % 3);
     unsigned long long *nxt = pick3(p.m[0], p.m[1], p.m[2], (k + 1) % 3);
     const uint32_t gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
-    for (uint32_t c = gt >> 6; c < p.nli_chunks; c += gs >> 6) {        // uniform per wave
+    const uint32_t nrest = p.nli_chunks - p.nli;
+    for (uint32_t i = gt >> 6; i < nrest; i += gs >> 6) {                // uniform per wave
+        const uint32_t c = p.lirest[i];
         const MsLong L = p.li[p.limap[c]];
-        if (c != L.chunk_base) long_chunk(p, cur, nxt, L.v, c - L.chunk_base, k, false);
+        long_chunk(p, cur, nxt, L.v, c - L.chunk_base, k, false);
     }
 }
 
