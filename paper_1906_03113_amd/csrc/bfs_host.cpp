@@ -1452,8 +1452,18 @@ static hipError_t ms_level(MsLevel &p, uint32_t k, bool pull, uint32_t frontier,
     return launch_ms(p, 3, k, grid, s);
 }
 
+// Multi-source launch size: 8 workgroups per compute unit, up to 32 on graphs
+// of more than 4,096 vertices per compute unit (one workgroup per 512
+// vertices: R-MAT s22, 64 sources, 6.25 ms at 8 per compute unit, 5.9-6.05 ms
+// at 12-32), except on thin graphs, whose thousands of small levels pay for
+// every workgroup of every launch (4096^2 grid, 16 sources: 239 ms at 8 per
+// compute unit, 272 ms at 32).
 static uint32_t ms_grid(const bfs_graph *g, const bfs_run_options *opt) {
-    return (opt && opt->grid_blocks) ? opt->grid_blocks : (uint32_t)(8 * (g->cus > 0 ? g->cus : 256));
+    if (opt && opt->grid_blocks) return opt->grid_blocks;
+    const uint32_t cus = (uint32_t)(g->cus > 0 ? g->cus : 256);
+    if (thin_graph(g)) return 8u * cus;
+    const uint32_t want = (uint32_t)std::min<int64_t>((int64_t)g->n / 512, (int64_t)32 * cus);
+    return std::max<uint32_t>(8u * cus, want);
 }
 
 // All queries on one graph: the multi-source kernels (outputs as ms_prepare).
