@@ -1454,8 +1454,9 @@ static hipError_t ms_level(MsLevel &p, uint32_t k, bool pull, uint32_t frontier,
 
 // Multi-source launch size: 8 workgroups per compute unit, up to 32 on graphs
 // of more than 4,096 vertices per compute unit (one workgroup per 512
-// vertices: R-MAT s22, 64 sources, 6.25 ms at 8 per compute unit, 5.9-6.05 ms
-// at 12-32), except on thin graphs, whose thousands of small levels pay for
+// vertices, one pull row chunk each: R-MAT s22, 64 sources, 5.63 ms at 32 per
+// compute unit, 5.90 ms at 16; 6.25 ms at 8 with chunks of 1,024 rows), except
+// on thin graphs, whose thousands of small levels pay for
 // every workgroup of every launch (4096^2 grid, 16 sources: 239 ms at 8 per
 // compute unit, 272 ms at 32).
 static uint32_t ms_grid(const bfs_graph *g, const bfs_run_options *opt) {

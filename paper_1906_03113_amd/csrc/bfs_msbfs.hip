@@ -535,7 +535,7 @@ __device__ __forceinline__ void long_chunk(const MsLevel &p, const unsigned long
     }
 }
 
-constexpr uint32_t kMsRows = 1024;       // rows per block chunk
+constexpr uint32_t kMsRows = 512;        // rows per block chunk
 constexpr int32_t kMsSerial = 16;        // longest row one lane scans alone
 constexpr uint32_t kMsGroupRow = 64;     // longest row a group of 16 lanes scans
 
