@@ -1191,18 +1191,23 @@ hipError_t launch_ms_rpull(const MsLevel &p, uint32_t k, uint32_t r, uint32_t gr
 }
 
 hipError_t launch_ms(const MsLevel &p, int phase, uint32_t k, uint32_t grid, hipStream_t s) {
+    // the list walks after a level (settle, fixup, report) end in one pair of
+    // counter atomics per workgroup on the same two words: at most 2,048
+    // workgroups for them (R-MAT s22: the report 25-31 us at 8,192, 17-22 us
+    // at 1,024-2,048)
+    const uint32_t small = grid < 2048u ? grid : 2048u;
     switch (phase) {
         case 0: hipLaunchKernelGGL(k_ms_clear, dim3(grid), dim3(kBlock), 0, s, p); break;
         case 1: hipLaunchKernelGGL(k_ms_roots, dim3(grid), dim3(kBlock), 0, s, p); break;
         case 2: hipLaunchKernelGGL(k_ms_push, dim3(grid), dim3(kBlock), 0, s, p, k); break;
-        case 3: hipLaunchKernelGGL(k_ms_settle, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        case 3: hipLaunchKernelGGL(k_ms_settle, dim3(small), dim3(kBlock), 0, s, p, k); break;
         case 4: hipLaunchKernelGGL(k_ms_pull, dim3(grid), dim3(kBlock), 0, s, p, k); break;
-        case 6: hipLaunchKernelGGL(k_ms_fixup, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        case 6: hipLaunchKernelGGL(k_ms_fixup, dim3(small), dim3(kBlock), 0, s, p, k); break;
         case 7: hipLaunchKernelGGL(k_ms_out, dim3(grid), dim3(kBlock), 0, s, p); break;
         case 8: hipLaunchKernelGGL(k_ms_fbits, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 9: hipLaunchKernelGGL(k_ms_pull_rest, dim3(grid), dim3(kBlock), 0, s, p, k); break;
         case 10: hipLaunchKernelGGL(k_ms_decide, dim3(1), dim3(64), 0, s, p, k); break;
-        default: hipLaunchKernelGGL(k_ms_report, dim3(grid), dim3(kBlock), 0, s, p, k); break;
+        default: hipLaunchKernelGGL(k_ms_report, dim3(small), dim3(kBlock), 0, s, p, k); break;
     }
     return hipGetLastError();
 }
