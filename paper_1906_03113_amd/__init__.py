@@ -64,7 +64,9 @@ class Graph:
 
     @classmethod
     def from_csr(cls, n: int, ptr, idx, in_ptr=None, in_idx=None, directed: bool = False,
-                 validate_transpose: bool = False) -> "Graph":
+                 validate_transpose: bool = False, ms_degree_order: Optional[bool] = None) -> "Graph":
+        """ms_degree_order: keep (True) or never keep (False) the multi-source
+        search's degree-ordered copy; None lets the library decide."""
         L = _lib.lib()
         _device_ready()
         ptr_h, idx_h = _i32_host(ptr), _i32_host(idx)
@@ -76,6 +78,8 @@ class Graph:
                 ip, ii = _i32_host(in_ptr), _i32_host(in_idx)
         if validate_transpose:
             flags |= _lib.BFS_VALIDATE_TRANSPOSE
+        if ms_degree_order is not None:
+            flags |= _lib.BFS_MS_DEGREE_ORDER if ms_degree_order else _lib.BFS_MS_NO_DEGREE_ORDER
         vp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         h = ctypes.c_void_p()
         _lib.check(L.bfs_graph_create(int(n), vp(ptr_h), vp(idx_h), vp(ip), vp(ii), flags,
@@ -83,10 +87,11 @@ class Graph:
         return cls(h, int(n), int(ptr_h[-1]), bool(directed))
 
     @classmethod
-    def from_graphgen(cls, g) -> "Graph":
+    def from_graphgen(cls, g, ms_degree_order: Optional[bool] = None) -> "Graph":
         if g.directed:
-            return cls.from_csr(g.n, g.ptr, g.idx, g.in_ptr, g.in_idx, directed=True)
-        return cls.from_csr(g.n, g.ptr, g.idx)
+            return cls.from_csr(g.n, g.ptr, g.idx, g.in_ptr, g.in_idx, directed=True,
+                                ms_degree_order=ms_degree_order)
+        return cls.from_csr(g.n, g.ptr, g.idx, ms_degree_order=ms_degree_order)
 
     @property
     def handle(self):

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libbfs.so")
 
 BFS_OK, BFS_EINVAL, BFS_ERANGE, BFS_ECSR, BFS_ENOMEM, BFS_EHIP = range(6)
 BFS_DIRECTED, BFS_INPUT_ON_DEVICE, BFS_VALIDATE_TRANSPOSE = 1, 2, 4
+BFS_MS_DEGREE_ORDER, BFS_MS_NO_DEGREE_ORDER = 8, 16
 VARIANTS = {"push": 0, "pull": 1, "bitmap": 2, "learned": 3, "heuristic": 4, "short_circuit": 5}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 LOOPS = {"host": 0, "graph": 1, "persistent": 2}

@@ -53,6 +53,17 @@ struct bfs_graph {
     uint32_t *lomap = nullptr, *limap = nullptr;
     uint32_t nlo = 0, nlo_chunks = 0, nli = 0, nli_chunks = 0;
     uint32_t *lirest = nullptr;       // the long rows' later chunks, by position in the row, then row
+    // the multi-source search's degree-ordered copy of an undirected graph
+    // (null when not kept): search label x = rank of the vertex by descending
+    // degree; x's list holds its neighbours' labels in the order of their
+    // caller ids, with those ids beside them; its split entries as above
+    int32_t *do_ptr = nullptr, *do_idx = nullptr, *do_ent = nullptr;
+    int32_t *do_orig = nullptr, *do_pos = nullptr;   // label -> caller id, caller id -> label
+    bfsi::MsLong *do_long = nullptr;
+    uint32_t *do_map = nullptr, *do_rest = nullptr;
+    uint32_t do_nlong = 0, do_nchunks = 0;
+    int32_t *do_rows = nullptr;       // the pull's row chunk bounds over the labels
+    uint32_t do_nrows = 0;
     // sliced push (bfs_slice.hip): per-vertex slice starts in the sorted
     // out-lists and the chunks of long slice parts; sl_S = 0 when the graph's
     // bitmap needs more than kSlMaxSlices slices
@@ -145,6 +156,11 @@ void free_graph(bfs_graph *g) {
     if (g->lo) (void)hipFree(g->lo);
     if (g->lomap) (void)hipFree(g->lomap);
     if (g->lirest) (void)hipFree(g->lirest);
+    for (int32_t *a : {g->do_ptr, g->do_idx, g->do_ent, g->do_orig, g->do_pos, g->do_rows})
+        if (a) (void)hipFree(a);
+    if (g->do_long) (void)hipFree(g->do_long);
+    if (g->do_map) (void)hipFree(g->do_map);
+    if (g->do_rest) (void)hipFree(g->do_rest);
     if (g->in_ptr && g->in_ptr != g->out_ptr) (void)hipFree(g->in_ptr);
     if (g->in_idx && g->in_idx != g->out_idx) (void)hipFree(g->in_idx);
     if (g->out_ptr) (void)hipFree(g->out_ptr);
@@ -193,6 +209,70 @@ bfs_status build_rest(int32_t n, const std::vector<int32_t> &ptr, uint32_t **out
     std::vector<uint32_t> order;
     for (const auto &b : by_pos) order.insert(order.end(), b.begin(), b.end());
     return upload(out, order.data(), order.size(), bytes);
+}
+
+// The degree-ordered copy of an undirected graph for the multi-source search.
+// Its frontier masks are gathered once per scanned list entry; with the
+// vertices ranked by descending degree the masks most entries point to share
+// a few megabytes (R-MAT s22: 85% of the entries point to the 262,144 vertices
+// of largest degree, 2 MB of 8-byte masks) instead of one line each across the
+// whole array.  Each list keeps the order of the caller's ids, and the
+// caller's ids sit beside the labels, so that the first frontier neighbour
+// found in list order is still the one of smallest caller id (the parent).
+bfs_status build_degree_order(bfs_graph *g, const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx) {
+    const int32_t n = g->n;
+    std::vector<int32_t> orig((size_t)n), pos((size_t)n);
+    for (int32_t v = 0; v < n; ++v) orig[(size_t)v] = v;
+    std::stable_sort(orig.begin(), orig.end(), [&](int32_t a, int32_t b) {
+        return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b];
+    });
+    for (int32_t x = 0; x < n; ++x) pos[(size_t)orig[(size_t)x]] = x;
+    std::vector<int32_t> dptr((size_t)n + 1), didx(idx.size()), dent(idx.size());
+    dptr[0] = 0;
+    for (int32_t x = 0; x < n; ++x) {
+        const int32_t v = orig[(size_t)x];
+        int32_t o = dptr[(size_t)x];
+        for (int32_t e = ptr[v]; e < ptr[v + 1]; ++e, ++o) {
+            dent[(size_t)o] = idx[(size_t)e];
+            didx[(size_t)o] = pos[(size_t)idx[(size_t)e]];
+        }
+        dptr[(size_t)x + 1] = o;
+    }
+    bfs_status st = upload(&g->do_ptr, dptr.data(), dptr.size(), g->bytes);
+    if (st == BFS_OK) st = upload(&g->do_idx, didx.data(), didx.size(), g->bytes);
+    if (st == BFS_OK) st = upload(&g->do_ent, dent.data(), dent.size(), g->bytes);
+    if (st == BFS_OK) st = upload(&g->do_orig, orig.data(), orig.size(), g->bytes);
+    if (st == BFS_OK) st = upload(&g->do_pos, pos.data(), pos.size(), g->bytes);
+    if (st == BFS_OK) st = build_long(n, dptr, &g->do_long, &g->do_map, g->do_nlong, g->do_nchunks, g->bytes);
+    if (st == BFS_OK) st = build_rest(n, dptr, &g->do_rest, g->bytes);
+    // the pull's row chunks: runs of at most kMsRows labels holding about the
+    // entries kMsRows rows hold on average (rows of kMsLong+ entries count
+    // nothing: their chunks are dealt apart), so that the heaviest rows,
+    // which now lie side by side, spread over many workgroups
+    uint64_t short_entries = 0;
+    for (int32_t x = 0; x < n; ++x) {
+        const uint32_t d = (uint32_t)(dptr[(size_t)x + 1] - dptr[(size_t)x]);
+        if (d < bfsi::kMsLong) short_entries += d;
+    }
+    const uint64_t target = std::max<uint64_t>(1, short_entries * bfsi::kMsRows / (uint64_t)n);
+    std::vector<int32_t> rows{0};
+    uint64_t acc = 0;
+    uint32_t cnt = 0;
+    for (int32_t x = 0; x < n; ++x) {
+        const uint32_t d = (uint32_t)(dptr[(size_t)x + 1] - dptr[(size_t)x]);
+        const uint64_t wgt = d < bfsi::kMsLong ? d : 0;
+        if (cnt > 0 && (cnt == bfsi::kMsRows || acc + wgt > target)) {
+            rows.push_back(x);
+            acc = 0;
+            cnt = 0;
+        }
+        acc += wgt;
+        ++cnt;
+    }
+    rows.push_back(n);
+    g->do_nrows = (uint32_t)(rows.size() - 1);
+    if (st == BFS_OK) st = upload(&g->do_rows, rows.data(), rows.size(), g->bytes);
+    return st;
 }
 
 // The out-lists, padded with zeros to a multiple of four entries plus four, so
@@ -1095,8 +1175,13 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
     if (!out_ptr || !out_idx) return fail(BFS_EINVAL, "out_ptr/out_idx is NULL");
     if ((in_ptr == nullptr) != (in_idx == nullptr))
         return fail(BFS_EINVAL, "in_ptr and in_idx must both be given or both be NULL");
-    if (flags & ~(uint32_t)(BFS_DIRECTED | BFS_INPUT_ON_DEVICE | BFS_VALIDATE_TRANSPOSE))
+    if (flags & ~(uint32_t)(BFS_DIRECTED | BFS_INPUT_ON_DEVICE | BFS_VALIDATE_TRANSPOSE |
+                            BFS_MS_DEGREE_ORDER | BFS_MS_NO_DEGREE_ORDER))
         return fail(BFS_EINVAL, "unknown flags 0x%x", flags);
+    if ((flags & BFS_MS_DEGREE_ORDER) && (flags & BFS_MS_NO_DEGREE_ORDER))
+        return fail(BFS_EINVAL, "BFS_MS_DEGREE_ORDER and BFS_MS_NO_DEGREE_ORDER together");
+    if ((flags & BFS_MS_DEGREE_ORDER) && (flags & BFS_DIRECTED))
+        return fail(BFS_EINVAL, "BFS_MS_DEGREE_ORDER needs an undirected graph");
     const bool directed = (flags & BFS_DIRECTED) != 0;
     const bool on_dev = (flags & BFS_INPUT_ON_DEVICE) != 0;
     if (!directed && in_ptr) return fail(BFS_EINVAL, "a CSC is only accepted with BFS_DIRECTED");
@@ -1183,6 +1268,11 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
             g->nli_chunks = g->nlo_chunks;
         }
         if (st == BFS_OK) st = build_rest(n, directed ? iptr : ptr, &g->lirest, g->bytes);
+        // automatic: undirected graphs whose masks outgrow an XCD's L2 (2^19+
+        // vertices) and whose degrees are skewed (no locality of their own to lose)
+        const bool keep_order = (flags & BFS_MS_DEGREE_ORDER) ||
+                                (!(flags & BFS_MS_NO_DEGREE_ORDER) && !directed && n >= (1 << 19) && skewed_graph(g));
+        if (st == BFS_OK && keep_order) st = build_degree_order(g, ptr, idx);
     } catch (const std::bad_alloc &) {
         st = fail(BFS_ENOMEM, "host allocation failed");
     }
@@ -1404,6 +1494,24 @@ static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
     p.nli = g->nli;
     p.nli_chunks = g->nli_chunks;
     p.lirest = g->lirest;
+    p.orig = p.pos = p.ent = nullptr;
+    if (g->do_ptr) {                  // the degree-ordered copy (undirected: one list serves both ways)
+        p.out_ptr = p.in_ptr = g->do_ptr;
+        p.out_idx = p.in_idx = g->do_idx;
+        p.ent = g->do_ent;
+        p.orig = g->do_orig;
+        p.pos = g->do_pos;
+        p.lo = p.li = g->do_long;
+        p.lomap = p.limap = g->do_map;
+        p.nlo_chunks = p.nli_chunks = g->do_nchunks;
+        p.nli = g->do_nlong;
+        p.lirest = g->do_rest;
+        p.row_chunks = g->do_rows;
+        p.nrow_chunks = g->do_nrows;
+        // the library's staged rows by label (written in label order, k_ms_out
+        // maps them back); the caller's vertex-major arrays by caller id
+        p.stage_labels = vm ? 0u : 1u;
+    }
     p.slev = vm ? vm_level : (int32_t *)(b + L.slev);
     p.spar = vm ? (uint32_t *)vm_parent : (uint32_t *)(b + L.spar);
     p.fill_levels = vm ? 1u : 0u;
@@ -1459,6 +1567,27 @@ static hipError_t ms_level(MsLevel &p, uint32_t k, bool pull, uint32_t frontier,
 // on thin graphs, whose thousands of small levels pay for
 // every workgroup of every launch (4096^2 grid, 16 sources: 239 ms at 8 per
 // compute unit, 272 ms at 32).
+// The multi-source parameters over the caller's vertex order instead of the
+// degree-ordered copy.
+static void ms_caller_order(const bfs_graph *g, MsLevel &p) {
+    p.out_ptr = g->out_ptr;
+    p.out_idx = g->out_idx;
+    p.in_ptr = g->in_ptr;
+    p.in_idx = g->in_idx;
+    p.orig = p.pos = p.ent = nullptr;
+    p.row_chunks = nullptr;
+    p.nrow_chunks = 0;
+    p.stage_labels = 0;
+    p.lo = g->lo;
+    p.li = g->li;
+    p.lomap = g->lomap;
+    p.limap = g->limap;
+    p.nlo_chunks = g->nlo_chunks;
+    p.nli = g->nli;
+    p.nli_chunks = g->nli_chunks;
+    p.lirest = g->lirest;
+}
+
 static uint32_t ms_grid(const bfs_graph *g, const bfs_run_options *opt) {
     if (opt && opt->grid_blocks) return opt->grid_blocks;
     const uint32_t cus = (uint32_t)(g->cus > 0 ? g->cus : 256);
@@ -1483,6 +1612,7 @@ static bfs_status run_multi_source(bfs_graph *g, int32_t nq, const int32_t *sour
     bfs_status st = ms_prepare(g, nq, sources, level, parent, workspace, s, vm_level, vm_parent, grid, p, hs);
     if (st != BFS_OK) return st;
     if (opt && opt->ms_ranges && p.W == 1) p.rp_ranges = opt->ms_ranges;
+    if (p.rp_ranges > 1) ms_caller_order(g, p);       // its passes walk lists sorted by label
     // direction per level: HEURISTIC pushes while the union frontier is
     // small and pulls (no atomics) once it holds more than n >> pull_shift
     // vertices; LEARNED takes the network's argmin over push and pull, which

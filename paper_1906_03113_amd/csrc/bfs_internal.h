@@ -176,6 +176,7 @@ hipError_t launch_sl_level(const SlParams &p, uint32_t grid, hipStream_t s);
 // Multi-source search (64 sources per 64-bit word per vertex).
 constexpr uint32_t kMsLong = 512;      // degree from which a multi-source list entry is split
 constexpr uint32_t kMsChunk = 512;     // entries per chunk of a split entry
+constexpr uint32_t kMsRows = 512;      // most rows per chunk of the multi-source pull's row phase
 
 // A split entry of a multi-source work list: the vertex and the id of its
 // first chunk (chunks of one list are numbered consecutively in entry order).
@@ -201,6 +202,17 @@ struct MsLevel {
     const uint32_t *lomap, *limap;
     uint32_t nlo_chunks, nli, nli_chunks;
     const uint32_t *lirest;        // the long rows' chunks but their first, by position in the row, then row
+    // the graph's degree-ordered copy (all null: the caller's order): the lists
+    // above then hold search labels, orig maps a label to the caller's id, pos
+    // the caller's id to its label, ent[e] is the caller's id of entry e; the
+    // masks, vis, flags and lists use labels, the staged results and every
+    // parent value the caller's ids
+    const int32_t *orig, *pos, *ent;
+    // the pull's row chunks: row_chunks[c] .. row_chunks[c + 1] - 1, at most
+    // kMsRows rows each (null: chunks of kMsRows consecutive rows)
+    const int32_t *row_chunks;
+    uint32_t nrow_chunks;
+    uint32_t stage_labels;         // staged rows by label (the library's own staging with a degree order)
     // results staged vertex-major while the search runs, [n][W * 64]: row v
     // holds every source's level / parent of v (valid where vis has the bit),
     // so the writes of one row share its 256-byte lines; k_ms_out transposes

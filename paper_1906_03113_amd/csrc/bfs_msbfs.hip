@@ -55,36 +55,57 @@ __device__ __forceinline__ bool in_frontier(const MsLevel &p, int32_t u) {
     return !p.use_fbits || ((p.fbits[(uint32_t)u >> 6] >> ((uint32_t)u & 63u)) & 1ull) != 0ull;
 }
 
+// With the graph's degree-ordered copy the kernels walk search labels: the
+// caller's id of label x, the label of the caller's vertex v, and the caller's
+// id of list entry e (label x).  All identities in the caller's order.
+__device__ __forceinline__ int32_t caller_id(const MsLevel &p, int32_t x) {
+    return p.orig ? p.orig[x] : x;
+}
+__device__ __forceinline__ int32_t label_of(const MsLevel &p, int32_t v) {
+    return p.pos ? p.pos[v] : v;
+}
+__device__ __forceinline__ int32_t entry_caller(const MsLevel &p, int32_t e, int32_t x) {
+    return p.ent ? p.ent[e] : x;
+}
+// The staged row of label x: the label itself when the staged results are
+// the library's own (k_ms_out maps them back), else the caller's id.
+__device__ __forceinline__ int32_t srow(const MsLevel &p, int32_t x) {
+    return p.stage_labels ? x : caller_id(p, x);
+}
+
 // One step of the settle scan by a group of G lanes (G = 16 or 64, aligned
 // within the wave) over in_idx[eb + lane-in-group] (lanes past e1 hold
 // nothing): each bit of rem held by some lane's cur mask goes to the lowest
 // such lane, i.e. to the smallest in-neighbour of the step.  Returns the bits
-// found (the same in every lane of the group).  scan_resolve is the second
-// half, given each lane's entry u and its mask bits already restricted to rem.
+// found (the same in every lane of the group).  vo is the row's caller id
+// (its staged results), parents are written as the entries' caller ids.
+// scan_resolve is the second half, given each lane's entry (its caller id uc)
+// and its mask bits already restricted to rem.
 template <uint32_t G>
-__device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int32_t v, uint32_t w,
-                                                           int32_t u, unsigned long long hit,
+__device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int32_t vo, uint32_t w,
+                                                           int32_t uc, unsigned long long hit,
                                                            uint32_t lk, bool owner_alone);
 
 template <uint32_t G>
 __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const unsigned long long *cur,
-                                                        int32_t v, uint32_t w, int32_t eb, int32_t e1,
+                                                        int32_t vo, uint32_t w, int32_t eb, int32_t e1,
                                                         unsigned long long rem, uint32_t lk,
                                                         bool owner_alone) {
     const uint32_t li = __lane_id() & (G - 1u);
     const int32_t e = eb + (int32_t)li;
-    int32_t u = -1;
+    int32_t uc = -1;
     unsigned long long hit = 0ull;
     if (e < e1) {
-        u = p.in_idx[e];
+        const int32_t u = p.in_idx[e];
+        uc = entry_caller(p, e, u);
         if (in_frontier(p, u)) hit = row(cur, u, p.W)[w] & rem;
     }
-    return scan_resolve<G>(p, v, w, u, hit, lk, owner_alone);
+    return scan_resolve<G>(p, vo, w, uc, hit, lk, owner_alone);
 }
 
 template <uint32_t G>
-__device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int32_t v, uint32_t w,
-                                                           int32_t u, unsigned long long hit,
+__device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int32_t vo, uint32_t w,
+                                                           int32_t uc, unsigned long long hit,
                                                            uint32_t lk, bool owner_alone) {
     const uint32_t li = __lane_id() & (G - 1u);
     if (__ballot(hit != 0ull) == 0ull) return 0ull;        // (uniform) nothing found in the wave
@@ -98,7 +119,7 @@ __device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int
     if (li == 0) below = 0ull;
     unsigned long long own = hit & ~below;
     const unsigned long long found = __shfl(incl, (int)(G - 1u), (int)G);
-    // each found bit's parent (the u of the lane that owns it) through the
+    // each found bit's parent (the entry of the lane that owns it) through the
     // group's row of 64 LDS slots, then written by source: lane li takes
     // sources li, li + G, ..., so the staged row goes out in 64 / G stores
     // of consecutive entries instead of one store per bit
@@ -110,14 +131,14 @@ __device__ __forceinline__ unsigned long long scan_resolve(const MsLevel &p, int
     while (own) {
         const uint32_t b = (uint32_t)__ffsll((long long)own) - 1u;
         own &= own - 1ull;
-        slot[b] = (uint32_t)u;
+        slot[b] = (uint32_t)uc;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (uint32_t b = li; b < 64u; b += G) {
         if ((found >> b) & 1ull) {
-            const size_t at = stage(p, v, w * 64u + b);
+            const size_t at = stage(p, vo, w * 64u + b);
             const uint32_t pu = slot[b];
             p.slev[at] = (int32_t)lk;
             if (owner_alone) p.spar[at] = pu;
@@ -164,18 +185,19 @@ __global__ __launch_bounds__(kBlock) void k_ms_clear(MsLevel p) {
 __global__ __launch_bounds__(kBlock) void k_ms_roots(MsLevel p) {
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
     for (uint32_t q = gid; q < p.nq; q += gs) {
-        const int32_t s = p.sources[q];
+        const int32_t s = p.sources[q];                       // the caller's id
+        const int32_t x = label_of(p, s);
         const unsigned long long bit = 1ull << (q & 63);
-        atomicOr(&row(p.m[0], s, p.W)[q >> 6], bit);
-        atomicOr(&row(p.vis, s, p.W)[q >> 6], bit);
-        p.slev[stage(p, s, q)] = 0;
-        p.spar[stage(p, s, q)] = (uint32_t)s;
+        atomicOr(&row(p.m[0], x, p.W)[q >> 6], bit);
+        atomicOr(&row(p.vis, x, p.W)[q >> 6], bit);
+        p.slev[stage(p, srow(p, x), q)] = 0;
+        p.spar[stage(p, srow(p, x), q)] = (uint32_t)s;
         const int g = (int)(q % kMsDegGroups);
         atomicAdd(&p.mstat[ms_line(0, g) + 1], 1ull);              // one pair per source
         atomicAdd(&p.mstat[ms_line(kMsCumSlot, g) + 1], 1ull);
-        if (atomicMax(&p.flag[s], 1u) < 1u) {
-            p.fq[0][atomicAdd(&p.cnt[0], 1u)] = s;
-            atomicAdd(&p.mstat[ms_line(0, g)], (unsigned long long)(p.out_ptr[s + 1] - p.out_ptr[s]));
+        if (atomicMax(&p.flag[x], 1u) < 1u) {
+            p.fq[0][atomicAdd(&p.cnt[0], 1u)] = x;
+            atomicAdd(&p.mstat[ms_line(0, g)], (unsigned long long)(p.out_ptr[x + 1] - p.out_ptr[x]));
             atomicAdd(&p.mstat[ms_line(kMsCumSlot, g)], 1ull);
         }
     }
@@ -240,10 +262,13 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
             const unsigned long long nb = cu[w] & ~vv[w];
             if (!nb) continue;
             // parents only decrease, so a stale pre-read can only let
-            // an atomic through that was not needed
+            // an atomic through that was not needed (staged rows and parent
+            // values in the caller's ids)
+            const int32_t vo = p.stage_labels ? v : entry_caller(p, e, v);
+            const uint32_t uo = (uint32_t)caller_id(p, u);
             for (unsigned long long b = nb; b; b &= b - 1ull) {
-                uint32_t *at = &p.spar[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)];
-                if (*at > (uint32_t)u) atomicMin(at, (uint32_t)u);
+                uint32_t *at = &p.spar[stage(p, vo, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)];
+                if (*at > uo) atomicMin(at, uo);
             }
             if (W == 1) {
                 // the lane whose OR turns nxt[v] nonzero lists v; a
@@ -420,8 +445,9 @@ __global__ __launch_bounds__(kBlock) void k_ms_settle(MsLevel p, uint32_t k) {
             if (!nb) continue;
             pairs += (unsigned long long)__popcll(nb);
             row(p.vis, v, W)[w] |= nb;
+            const int32_t vo = srow(p, v);
             for (unsigned long long b = nb; b; b &= b - 1ull)
-                p.slev[stage(p, v, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)] = (int32_t)(k + 1);
+                p.slev[stage(p, vo, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)] = (int32_t)(k + 1);
         }
     }
     add_stats(p, s1, deg, pairs);
@@ -456,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_fbits(MsLevel p, uint32_t k) {
 // entry: staged parents only decrease within the level, so a stale read only
 // keeps a source longer.
 __device__ __forceinline__ unsigned long long scan_wave4(const MsLevel &p, const unsigned long long *cur,
-                                                         int32_t v, uint32_t w, int32_t e0, int32_t e1,
+                                                         int32_t vo, uint32_t w, int32_t e0, int32_t e1,
                                                          unsigned long long rem, uint32_t lk,
                                                          bool owner_alone, bool prune) {
     const uint32_t W = p.W;
@@ -464,17 +490,19 @@ __device__ __forceinline__ unsigned long long scan_wave4(const MsLevel &p, const
     unsigned long long found = 0ull;
     int32_t nst = 1;                                                    // steps in this batch
     for (int32_t eb = e0; eb < e1 && rem; eb += nst * 64, nst = 4) {
-        int32_t uu[4];
+        int32_t uu[4], oo[4];                                           // labels, caller ids
         bool ok[4];
         unsigned long long mm[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int32_t e = eb + t * 64 + lane;
-            uu[t] = (t < nst && e < e1) ? p.in_idx[e] : -1;
+            const bool in = t < nst && e < e1;
+            uu[t] = in ? p.in_idx[e] : -1;
+            oo[t] = in ? entry_caller(p, e, uu[t]) : -1;
         }
         if (prune) {
-            const uint32_t sp = p.spar[stage(p, v, w * 64u + (uint32_t)lane)];
-            rem &= ~__ballot(sp < (uint32_t)__shfl(uu[0], 0, 64));
+            const uint32_t sp = p.spar[stage(p, vo, w * 64u + (uint32_t)lane)];
+            rem &= ~__ballot(sp < (uint32_t)__shfl(oo[0], 0, 64));
             if (!rem) break;                                            // uniform
         }
         if (p.use_fbits) {
@@ -492,7 +520,7 @@ __device__ __forceinline__ unsigned long long scan_wave4(const MsLevel &p, const
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (rem) {                                                  // uniform
-                const unsigned long long f = scan_resolve<64>(p, v, w, uu[t], mm[t] & rem, lk, owner_alone);
+                const unsigned long long f = scan_resolve<64>(p, vo, w, oo[t], mm[t] & rem, lk, owner_alone);
                 rem &= ~f;
                 found |= f;
             }
@@ -527,7 +555,8 @@ __device__ __forceinline__ void long_chunk(const MsLevel &p, const unsigned long
     unsigned long long *vis = row(p.vis, v, W);
     for (uint32_t w = 0; w < W; ++w) {
         const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
-        const unsigned long long found = scan_wave4(p, cur, v, w, e0, e1, full & ~vis[w], k + 1, false, j != 0);
+        const unsigned long long found = scan_wave4(p, cur, srow(p, v), w, e0, e1, full & ~vis[w], k + 1,
+                                                    false, j != 0);
         if (found && __lane_id() == 0) {
             atomicOr(&row(nxt, v, W)[w], found);
             if (first) vis[w] |= found;
@@ -535,7 +564,6 @@ __device__ __forceinline__ void long_chunk(const MsLevel &p, const unsigned long
     }
 }
 
-constexpr uint32_t kMsRows = 512;        // rows per block chunk
 constexpr int32_t kMsSerial = 16;        // longest row one lane scans alone
 constexpr uint32_t kMsGroupRow = 64;     // longest row a group of 16 lanes scans
 
@@ -562,13 +590,19 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
     }
     const uint32_t tail = p.nq & 63u;
     const uint32_t lk = k + 1;
-    for (uint32_t c0 = blockIdx.x * kMsRows; c0 < (uint32_t)p.n; c0 += gridDim.x * kMsRows) {
+    // row chunks of kMsRows rows, or the graph's own chunk bounds (at most
+    // kMsRows rows and about the same number of list entries each: the
+    // degree-ordered copy puts its heaviest rows side by side)
+    const uint32_t nrc = p.row_chunks ? p.nrow_chunks : (uint32_t)(((size_t)p.n + kMsRows - 1) / kMsRows);
+    for (uint32_t c = blockIdx.x; c < nrc; c += gridDim.x) {
         if (tid == 0) {
             s_n = 0;
             s_nl = 0;
         }
         __syncthreads();
-        const uint32_t c1 = (c0 + kMsRows < (uint32_t)p.n) ? c0 + kMsRows : (uint32_t)p.n;
+        const uint32_t c0 = p.row_chunks ? (uint32_t)p.row_chunks[c] : c * kMsRows;
+        const uint32_t c1 = p.row_chunks ? (uint32_t)p.row_chunks[c + 1]
+                                         : ((c0 + kMsRows < (uint32_t)p.n) ? c0 + kMsRows : (uint32_t)p.n);
         // Rows of up to kMsSerial entries, one lane each, 256 at a time.  A
         // lane records, per found bit, the offset of the entry that gave it
         // (LDS); then each wave writes its lanes' rows, one row at a time
@@ -645,9 +679,10 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                     const unsigned long long fm = s_fnd[rr];
                     if ((fm >> lane) & 1ull) {
                         const uint32_t j = (s_off[rr][lane >> 3] >> ((lane & 7u) * 4u)) & 15u;
-                        const size_t at = stage(p, (int32_t)(r0 + rr), w * 64u + lane);
+                        const size_t at = stage(p, srow(p, (int32_t)(r0 + rr)), w * 64u + lane);
+                        const int32_t e = s_e0[rr] + (int32_t)j;
                         p.slev[at] = (int32_t)lk;
-                        p.spar[at] = (uint32_t)p.in_idx[s_e0[rr] + (int32_t)j];
+                        p.spar[at] = (uint32_t)(p.ent ? p.ent[e] : p.in_idx[e]);
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -678,7 +713,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                         const unsigned long long sv = vis[w];
                         unsigned long long rem = full & ~sv, found = 0ull;
                         for (int32_t eb = e0; eb < e1 && rem; eb += 16) {
-                            const unsigned long long f = scan_step<16>(p, cur, v, w, eb, e1, rem, lk, true);
+                            const unsigned long long f = scan_step<16>(p, cur, srow(p, v), w, eb, e1, rem,
+                                                                       lk, true);
                             rem &= ~f;
                             found |= f;
                         }
@@ -701,7 +737,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull(MsLevel p, uint32_t k) {
                 for (uint32_t w = 0; w < W; ++w) {
                     const unsigned long long full = (w == W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
                     const unsigned long long sv = vis[w];
-                    const unsigned long long found = scan_wave4(p, cur, wv, w, we0, we1, full & ~sv, lk, true, false);
+                    const unsigned long long found = scan_wave4(p, cur, srow(p, wv), w, we0, we1, full & ~sv,
+                                                                lk, true, false);
                     if (found) {
                         if (lane == 0) {
                             row(nxt, wv, W)[w] = found;
@@ -819,9 +856,10 @@ __global__ __launch_bounds__(kBlock) void k_ms_out(MsLevel p) {
                 lv[r] = make_int4(-1, -1, -1, -1);
                 pa[r] = lv[r];
                 bits[r] = 0;
-                if (v < p.n) bits[r] = (uint32_t)(row(p.vis, v, W)[w] >> g4) & 15u;
+                const int32_t x = v < p.n ? label_of(p, v) : 0;
+                if (v < p.n) bits[r] = (uint32_t)(row(p.vis, x, W)[w] >> g4) & 15u;
                 if (bits[r]) {                          // read once: streaming loads
-                    const size_t at = (size_t)v * S + w * 64u + g4;
+                    const size_t at = (size_t)(p.stage_labels ? x : v) * S + w * 64u + g4;
                     const v4i a = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p.slev + at));
                     const v4i b = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p.spar + at));
                     lv[r] = make_int4(a.x, a.y, a.z, a.w);

@@ -248,3 +248,56 @@ def test_range_ordered_pull(P, name):
                             f"{name}/{nq}/{ranges}/{variant}/vm")
     with pytest.raises(P.BfsError):
         P.bfs_batch(G, src[:3], variant="pull", ms_ranges=65)
+
+
+@pytest.mark.parametrize("name", ["rmat", "rmat_dup", "grid", "er_isolated"])
+def test_degree_ordered_copy(P, name):
+    """The multi-source search over the graph's degree-ordered copy (labels by
+    descending degree, lists in the caller's order, results and parents in the
+    caller's ids): every query of a 70-source batch, both layouts, every
+    direction policy, and small grids whose long rows' later chunks get a
+    launch of their own (the chunks skip sources settled by earlier chunks by
+    comparing caller ids), against the oracle."""
+    import torch
+    from paper_1906_03113_amd import selector as S
+    if name == "rmat":
+        g = graphgen.rmat(14, 16, 91)
+        ptr, idx = g.ptr, g.idx
+    elif name == "rmat_dup":                       # duplicates and self-loops, clean graph for the oracle
+        g = graphgen.rmat(12, 16, 92)
+        rows = []
+        for v in range(g.n):
+            r = list(g.idx[g.ptr[v]:g.ptr[v + 1]])
+            rows.append(sorted(r + r[: len(r) // 3] + [v]))
+        ptr = np.zeros(g.n + 1, np.int32)
+        ptr[1:] = np.cumsum([len(r) for r in rows])
+        idx = np.array([x for r in rows for x in r], np.int32)
+    elif name == "grid":
+        g = graphgen.grid(70, 0.9, 93)
+        ptr, idx = g.ptr, g.idx
+    else:
+        g = graphgen.erdos_renyi(20000, 3.0, 94)   # isolated vertices among them
+        ptr, idx = g.ptr, g.idx
+    G = P.Graph.from_csr(g.n, ptr, idx, ms_degree_order=True)
+    cand = np.nonzero(g.out_degree() > 0)[0]
+    src = [int(s) for s in np.random.default_rng(95).choice(cand, size=70, replace=False)]
+    src[5] = src[4]                                 # a repeated source
+    want = oracle_all(g, src)
+    msw = S.load_weights(S.MS_WEIGHTS)
+    runs = [dict(variant="push"), dict(variant="pull"), dict(variant="heuristic"),
+            dict(variant="learned", selector=msw), dict(variant="pull", grid_blocks=1),
+            dict(variant="pull", grid_blocks=3)]
+    for kw in runs:
+        say(f"[batch] degree-ordered copy {name} {kw.get('variant')} {kw.get('grid_blocks', '')}")
+        lv, pa = P.bfs_batch(G, src, **kw)
+        vl, vp = P.bfs_batch_vm(G, src, **kw)
+        torch.cuda.synchronize()
+        compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/{kw}")
+        compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"{name}/{kw}/vm")
+    # the same graph without the copy gives the same arrays
+    H = P.Graph.from_csr(g.n, ptr, idx, ms_degree_order=False)
+    a_l, a_p = P.bfs_batch(H, src, variant="heuristic")
+    b_l, b_p = P.bfs_batch(G, src, variant="heuristic")
+    torch.cuda.synchronize()
+    for q in range(len(src)):
+        assert torch.equal(a_l[q], b_l[q]) and torch.equal(a_p[q], b_p[q]), q
