@@ -97,8 +97,8 @@ __device__ __forceinline__ unsigned long long scan_step(const MsLevel &p, const 
     unsigned long long hit = 0ull;
     if (e < e1) {
         const int32_t u = p.in_idx[e];
-        uc = entry_caller(p, e, u);
         if (in_frontier(p, u)) hit = row(cur, u, p.W)[w] & rem;
+        if (hit) uc = caller_id(p, u);                  // only an entry that may give a parent
     }
     return scan_resolve<G>(p, vo, w, uc, hit, lk, owner_alone);
 }
@@ -498,11 +498,11 @@ __device__ __forceinline__ unsigned long long scan_wave4(const MsLevel &p, const
             const int32_t e = eb + t * 64 + lane;
             const bool in = t < nst && e < e1;
             uu[t] = in ? p.in_idx[e] : -1;
-            oo[t] = in ? entry_caller(p, e, uu[t]) : -1;
         }
         if (prune) {
+            const uint32_t first = (uint32_t)(p.ent ? p.ent[eb] : __shfl(uu[0], 0, 64));
             const uint32_t sp = p.spar[stage(p, vo, w * 64u + (uint32_t)lane)];
-            rem &= ~__ballot(sp < (uint32_t)__shfl(oo[0], 0, 64));
+            rem &= ~__ballot(sp < first);
             if (!rem) break;                                            // uniform
         }
         if (p.use_fbits) {
@@ -517,6 +517,11 @@ __device__ __forceinline__ unsigned long long scan_wave4(const MsLevel &p, const
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) mm[t] = ok[t] ? row(cur, uu[t], W)[w] : 0ull;
+        // the caller's ids of the entries that may give a parent (with the
+        // degree-ordered copy a lookup, mostly in the few megabytes of the
+        // labels of largest degree; streaming every entry's id cost more)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) oo[t] = (mm[t] & rem) ? caller_id(p, uu[t]) : -1;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (rem) {                                                  // uniform
