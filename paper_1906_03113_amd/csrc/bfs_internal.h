@@ -216,7 +216,9 @@ struct MsLevel {
     // results staged vertex-major while the search runs, [n][W * 64]: row v
     // holds every source's level / parent of v (valid where vis has the bit),
     // so the writes of one row share its 256-byte lines; k_ms_out transposes
-    // them into the callers' per-source arrays at the end
+    // them into the callers' per-source arrays at the end (with stage_labels
+    // the row of a vertex is its label, else its caller id; parents are
+    // caller ids either way)
     int32_t *slev;
     uint32_t *spar;
     int32_t *const *level;         // device array of nq device pointers
