@@ -53,8 +53,7 @@ enum {
     BFS_DIRECTED = 1u << 0,           /* A is not symmetric: the CSC is needed for pull */
     BFS_INPUT_ON_DEVICE = 1u << 1,    /* the four input arrays are device pointers */
     BFS_VALIDATE_TRANSPOSE = 1u << 2, /* check that the given CSC is the transpose of the CSR */
-    BFS_MS_DEGREE_ORDER = 1u << 3,    /* keep the multi-source search's degree-ordered copy
-                                         (undirected graphs only; BFS_EINVAL with BFS_DIRECTED) */
+    BFS_MS_DEGREE_ORDER = 1u << 3,    /* keep the multi-source search's degree-ordered copy */
     BFS_MS_NO_DEGREE_ORDER = 1u << 4  /* never keep it (default: kept for undirected graphs of
                                          2^19+ vertices with skewed degrees) */
 };
@@ -196,8 +195,9 @@ enum {
  * The library copies and sorts its own copy of every neighbour list; self-loops
  * and duplicate entries are accepted (they change no result).  For the
  * multi-source search (bfs_run_batch, bfs_run_batch_vm on one graph) it may
- * also keep a second copy of an undirected graph with the vertices ranked by
- * descending degree (about 8 bytes per entry more; see the flags): the
+ * also keep a second copy of the lists with the vertices ranked by
+ * descending out-degree (about 8 bytes per entry more, twice that for a
+ * directed graph's two list sets; see the flags): the
  * frontier masks that most list entries point to then share a few megabytes
  * that stay in the L2 caches.  Results are the same either way.  Synchronous
  * on hip_stream; the caller may free its arrays once this returns.

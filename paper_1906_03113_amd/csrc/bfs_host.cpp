@@ -53,10 +53,11 @@ struct bfs_graph {
     uint32_t *lomap = nullptr, *limap = nullptr;
     uint32_t nlo = 0, nlo_chunks = 0, nli = 0, nli_chunks = 0;
     uint32_t *lirest = nullptr;       // the long rows' later chunks, by position in the row, then row
-    // the multi-source search's degree-ordered copy of an undirected graph
-    // (null when not kept): search label x = rank of the vertex by descending
-    // degree; x's list holds its neighbours' labels in the order of their
-    // caller ids, with those ids beside them; its split entries as above
+    // the multi-source search's degree-ordered copy of the graph (null when
+    // not kept): search label x = rank of the vertex by descending
+    // out-degree; x's in-list (an undirected graph's only list) holds its
+    // neighbours' labels in the order of their caller ids, with those ids
+    // beside them; its split entries as above
     int32_t *do_ptr = nullptr, *do_idx = nullptr, *do_ent = nullptr;
     int32_t *do_orig = nullptr, *do_pos = nullptr;   // label -> caller id, caller id -> label
     bfsi::MsLong *do_long = nullptr;
@@ -64,6 +65,12 @@ struct bfs_graph {
     uint32_t do_nlong = 0, do_nchunks = 0;
     int32_t *do_rows = nullptr;       // the pull's row chunk bounds over the labels
     uint32_t do_nrows = 0;
+    // a directed graph's out-lists over the same labels (the lists above are
+    // then its in-lists), with their caller ids and long columns
+    int32_t *do_optr = nullptr, *do_oidx = nullptr, *do_oent = nullptr;
+    bfsi::MsLong *do_olong = nullptr;
+    uint32_t *do_omap = nullptr;
+    uint32_t do_onlong = 0, do_onchunks = 0;
     // sliced push (bfs_slice.hip): per-vertex slice starts in the sorted
     // out-lists and the chunks of long slice parts; sl_S = 0 when the graph's
     // bitmap needs more than kSlMaxSlices slices
@@ -156,8 +163,11 @@ void free_graph(bfs_graph *g) {
     if (g->lo) (void)hipFree(g->lo);
     if (g->lomap) (void)hipFree(g->lomap);
     if (g->lirest) (void)hipFree(g->lirest);
-    for (int32_t *a : {g->do_ptr, g->do_idx, g->do_ent, g->do_orig, g->do_pos, g->do_rows})
+    for (int32_t *a : {g->do_ptr, g->do_idx, g->do_ent, g->do_orig, g->do_pos, g->do_rows, g->do_optr,
+                       g->do_oidx, g->do_oent})
         if (a) (void)hipFree(a);
+    if (g->do_olong) (void)hipFree(g->do_olong);
+    if (g->do_omap) (void)hipFree(g->do_omap);
     if (g->do_long) (void)hipFree(g->do_long);
     if (g->do_map) (void)hipFree(g->do_map);
     if (g->do_rest) (void)hipFree(g->do_rest);
@@ -211,7 +221,7 @@ bfs_status build_rest(int32_t n, const std::vector<int32_t> &ptr, uint32_t **out
     return upload(out, order.data(), order.size(), bytes);
 }
 
-// The degree-ordered copy of an undirected graph for the multi-source search.
+// The degree-ordered copy of a graph for the multi-source search.
 // Its frontier masks are gathered once per scanned list entry; with the
 // vertices ranked by descending degree the masks most entries point to share
 // a few megabytes (R-MAT s22: 85% of the entries point to the 262,144 vertices
@@ -219,16 +229,15 @@ bfs_status build_rest(int32_t n, const std::vector<int32_t> &ptr, uint32_t **out
 // whole array.  Each list keeps the order of the caller's ids, and the
 // caller's ids sit beside the labels, so that the first frontier neighbour
 // found in list order is still the one of smallest caller id (the parent).
-bfs_status build_degree_order(bfs_graph *g, const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx) {
-    const int32_t n = g->n;
-    std::vector<int32_t> orig((size_t)n), pos((size_t)n);
-    for (int32_t v = 0; v < n; ++v) orig[(size_t)v] = v;
-    std::stable_sort(orig.begin(), orig.end(), [&](int32_t a, int32_t b) {
-        return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b];
-    });
-    for (int32_t x = 0; x < n; ++x) pos[(size_t)orig[(size_t)x]] = x;
-    std::vector<int32_t> dptr((size_t)n + 1), didx(idx.size()), dent(idx.size());
-    dptr[0] = 0;
+// Lists of the caller's CSR (ptr, idx) over labels: row x = the list of
+// vertex orig[x] in its own order, entries as labels (dptr, didx) and as the
+// caller's ids (dent).
+static void relabel_lists(int32_t n, const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                          const std::vector<int32_t> &orig, const std::vector<int32_t> &pos,
+                          std::vector<int32_t> &dptr, std::vector<int32_t> &didx, std::vector<int32_t> &dent) {
+    dptr.assign((size_t)n + 1, 0);
+    didx.resize(idx.size());
+    dent.resize(idx.size());
     for (int32_t x = 0; x < n; ++x) {
         const int32_t v = orig[(size_t)x];
         int32_t o = dptr[(size_t)x];
@@ -238,7 +247,32 @@ bfs_status build_degree_order(bfs_graph *g, const std::vector<int32_t> &ptr, con
         }
         dptr[(size_t)x + 1] = o;
     }
-    bfs_status st = upload(&g->do_ptr, dptr.data(), dptr.size(), g->bytes);
+}
+
+// ptr / idx: the out-lists; iptr / iidx: the in-lists (the same arrays for an
+// undirected graph).  Labels rank the vertices by descending out-degree (how
+// often a vertex's mask is gathered by the pull's scans of in-lists).
+bfs_status build_degree_order(bfs_graph *g, const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                              const std::vector<int32_t> &iptr, const std::vector<int32_t> &iidx) {
+    const int32_t n = g->n;
+    std::vector<int32_t> orig((size_t)n), pos((size_t)n);
+    for (int32_t v = 0; v < n; ++v) orig[(size_t)v] = v;
+    std::stable_sort(orig.begin(), orig.end(), [&](int32_t a, int32_t b) {
+        return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b];
+    });
+    for (int32_t x = 0; x < n; ++x) pos[(size_t)orig[(size_t)x]] = x;
+    std::vector<int32_t> dptr, didx, dent;
+    relabel_lists(n, iptr, iidx, orig, pos, dptr, didx, dent);
+    bfs_status st = BFS_OK;
+    if (g->directed) {
+        std::vector<int32_t> optr, oidx, oent;
+        relabel_lists(n, ptr, idx, orig, pos, optr, oidx, oent);
+        st = upload(&g->do_optr, optr.data(), optr.size(), g->bytes);
+        if (st == BFS_OK) st = upload(&g->do_oidx, oidx.data(), oidx.size(), g->bytes);
+        if (st == BFS_OK) st = upload(&g->do_oent, oent.data(), oent.size(), g->bytes);
+        if (st == BFS_OK) st = build_long(n, optr, &g->do_olong, &g->do_omap, g->do_onlong, g->do_onchunks, g->bytes);
+    }
+    if (st == BFS_OK) st = upload(&g->do_ptr, dptr.data(), dptr.size(), g->bytes);
     if (st == BFS_OK) st = upload(&g->do_idx, didx.data(), didx.size(), g->bytes);
     if (st == BFS_OK) st = upload(&g->do_ent, dent.data(), dent.size(), g->bytes);
     if (st == BFS_OK) st = upload(&g->do_orig, orig.data(), orig.size(), g->bytes);
@@ -1180,8 +1214,6 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
         return fail(BFS_EINVAL, "unknown flags 0x%x", flags);
     if ((flags & BFS_MS_DEGREE_ORDER) && (flags & BFS_MS_NO_DEGREE_ORDER))
         return fail(BFS_EINVAL, "BFS_MS_DEGREE_ORDER and BFS_MS_NO_DEGREE_ORDER together");
-    if ((flags & BFS_MS_DEGREE_ORDER) && (flags & BFS_DIRECTED))
-        return fail(BFS_EINVAL, "BFS_MS_DEGREE_ORDER needs an undirected graph");
     const bool directed = (flags & BFS_DIRECTED) != 0;
     const bool on_dev = (flags & BFS_INPUT_ON_DEVICE) != 0;
     if (!directed && in_ptr) return fail(BFS_EINVAL, "a CSC is only accepted with BFS_DIRECTED");
@@ -1269,10 +1301,14 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
         }
         if (st == BFS_OK) st = build_rest(n, directed ? iptr : ptr, &g->lirest, g->bytes);
         // automatic: undirected graphs whose masks outgrow an XCD's L2 (2^19+
-        // vertices) and whose degrees are skewed (no locality of their own to lose)
+        // vertices) and whose degrees are skewed (no locality of their own to
+        // lose); a directed graph's copy only on request (directed R-MAT s20,
+        // 16 sources: 1.13 ms per batch with it, 0.93 ms without)
         const bool keep_order = (flags & BFS_MS_DEGREE_ORDER) ||
-                                (!(flags & BFS_MS_NO_DEGREE_ORDER) && !directed && n >= (1 << 19) && skewed_graph(g));
-        if (st == BFS_OK && keep_order) st = build_degree_order(g, ptr, idx);
+                                (!(flags & BFS_MS_NO_DEGREE_ORDER) && !directed && n >= (1 << 19) &&
+                                 skewed_graph(g));
+        if (st == BFS_OK && keep_order)
+            st = directed ? build_degree_order(g, ptr, idx, iptr, iidx) : build_degree_order(g, ptr, idx, ptr, idx);
     } catch (const std::bad_alloc &) {
         st = fail(BFS_ENOMEM, "host allocation failed");
     }
@@ -1495,10 +1531,10 @@ static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
     p.nli_chunks = g->nli_chunks;
     p.lirest = g->lirest;
     p.orig = p.pos = p.ent = nullptr;
-    if (g->do_ptr) {                  // the degree-ordered copy (undirected: one list serves both ways)
+    if (g->do_ptr) {                  // the degree-ordered copy (undirected: one list set serves both ways)
         p.out_ptr = p.in_ptr = g->do_ptr;
         p.out_idx = p.in_idx = g->do_idx;
-        p.ent = g->do_ent;
+        p.ent = p.out_ent = g->do_ent;
         p.orig = g->do_orig;
         p.pos = g->do_pos;
         p.lo = p.li = g->do_long;
@@ -1508,6 +1544,14 @@ static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
         p.lirest = g->do_rest;
         p.row_chunks = g->do_rows;
         p.nrow_chunks = g->do_nrows;
+        if (g->directed) {            // the out-lists for the push
+            p.out_ptr = g->do_optr;
+            p.out_idx = g->do_oidx;
+            p.out_ent = g->do_oent;
+            p.lo = g->do_olong;
+            p.lomap = g->do_omap;
+            p.nlo_chunks = g->do_onchunks;
+        }
         // the library's staged rows by label (written in label order, k_ms_out
         // maps them back); the caller's vertex-major arrays by caller id
         p.stage_labels = vm ? 0u : 1u;
@@ -1574,7 +1618,7 @@ static void ms_caller_order(const bfs_graph *g, MsLevel &p) {
     p.out_idx = g->out_idx;
     p.in_ptr = g->in_ptr;
     p.in_idx = g->in_idx;
-    p.orig = p.pos = p.ent = nullptr;
+    p.orig = p.pos = p.ent = p.out_ent = nullptr;
     p.row_chunks = nullptr;
     p.nrow_chunks = 0;
     p.stage_labels = 0;

@@ -207,7 +207,7 @@ struct MsLevel {
     // the caller's id to its label, ent[e] is the caller's id of entry e; the
     // masks, vis, flags and lists use labels, the staged results and every
     // parent value the caller's ids
-    const int32_t *orig, *pos, *ent;
+    const int32_t *orig, *pos, *ent, *out_ent;   // ent: in-list entries, out_ent: out-list entries
     // the pull's row chunks: row_chunks[c] .. row_chunks[c + 1] - 1, at most
     // kMsRows rows each (null: chunks of kMsRows consecutive rows)
     const int32_t *row_chunks;

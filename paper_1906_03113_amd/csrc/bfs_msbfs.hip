@@ -56,16 +56,13 @@ __device__ __forceinline__ bool in_frontier(const MsLevel &p, int32_t u) {
 }
 
 // With the graph's degree-ordered copy the kernels walk search labels: the
-// caller's id of label x, the label of the caller's vertex v, and the caller's
-// id of list entry e (label x).  All identities in the caller's order.
+// caller's id of label x and the label of the caller's vertex v (identities
+// in the caller's order).
 __device__ __forceinline__ int32_t caller_id(const MsLevel &p, int32_t x) {
     return p.orig ? p.orig[x] : x;
 }
 __device__ __forceinline__ int32_t label_of(const MsLevel &p, int32_t v) {
     return p.pos ? p.pos[v] : v;
-}
-__device__ __forceinline__ int32_t entry_caller(const MsLevel &p, int32_t e, int32_t x) {
-    return p.ent ? p.ent[e] : x;
 }
 // The staged row of label x: the label itself when the staged results are
 // the library's own (k_ms_out maps them back), else the caller's id.
@@ -264,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_push(MsLevel p, uint32_t k) {
             // parents only decrease, so a stale pre-read can only let
             // an atomic through that was not needed (staged rows and parent
             // values in the caller's ids)
-            const int32_t vo = p.stage_labels ? v : entry_caller(p, e, v);
+            const int32_t vo = p.stage_labels ? v : (p.out_ent ? p.out_ent[e] : v);
             const uint32_t uo = (uint32_t)caller_id(p, u);
             for (unsigned long long b = nb; b; b &= b - 1ull) {
                 uint32_t *at = &p.spar[stage(p, vo, w * 64u + (uint32_t)__ffsll((long long)b) - 1u)];

@@ -68,8 +68,6 @@ def test_validation_errors_without_gpu(L):
         (2, ok_ptr, ok_idx, None, None, 1 << 9, B.BFS_EINVAL, "unknown flag"),
         (2, ok_ptr, ok_idx, None, None, B.BFS_MS_DEGREE_ORDER | B.BFS_MS_NO_DEGREE_ORDER, B.BFS_EINVAL,
          "degree order on and off"),
-        (2, ok_ptr, ok_idx, ok_ptr, ok_idx, B.BFS_DIRECTED | B.BFS_MS_DEGREE_ORDER, B.BFS_EINVAL,
-         "degree order of a directed graph"),
         (2, ok_ptr, ok_idx, np.array([0, 1, 3], np.int32), np.array([1, 0, 0], np.int32),
          B.BFS_DIRECTED, B.BFS_ECSR, "CSC size differs"),
         (2, ok_ptr, ok_idx, np.array([0, 0, 2], np.int32), np.array([0, 1], np.int32),

@@ -250,7 +250,7 @@ def test_range_ordered_pull(P, name):
         P.bfs_batch(G, src[:3], variant="pull", ms_ranges=65)
 
 
-@pytest.mark.parametrize("name", ["rmat", "rmat_dup", "grid", "er_isolated"])
+@pytest.mark.parametrize("name", ["rmat", "rmat_dup", "grid", "er_isolated", "rmatd"])
 def test_degree_ordered_copy(P, name):
     """The multi-source search over the graph's degree-ordered copy (labels by
     descending degree, lists in the caller's order, results and parents in the
@@ -275,10 +275,16 @@ def test_degree_ordered_copy(P, name):
     elif name == "grid":
         g = graphgen.grid(70, 0.9, 93)
         ptr, idx = g.ptr, g.idx
-    else:
+    elif name == "er_isolated":
         g = graphgen.erdos_renyi(20000, 3.0, 94)   # isolated vertices among them
         ptr, idx = g.ptr, g.idx
-    G = P.Graph.from_csr(g.n, ptr, idx, ms_degree_order=True)
+    else:                                          # directed: an out-list and an in-list copy
+        g = graphgen.rmat(13, 16, 96, directed=True)
+        ptr, idx = g.ptr, g.idx
+    if g.directed:
+        G = P.Graph.from_csr(g.n, ptr, idx, g.in_ptr, g.in_idx, directed=True, ms_degree_order=True)
+    else:
+        G = P.Graph.from_csr(g.n, ptr, idx, ms_degree_order=True)
     cand = np.nonzero(g.out_degree() > 0)[0]
     src = [int(s) for s in np.random.default_rng(95).choice(cand, size=70, replace=False)]
     src[5] = src[4]                                 # a repeated source
@@ -295,7 +301,10 @@ def test_degree_ordered_copy(P, name):
         compare_all(want, src, lambda q: (lv[q].cpu().numpy(), pa[q].cpu().numpy()), f"{name}/{kw}")
         compare_all(want, src, lambda q: (vl[:, q].cpu().numpy(), vp[:, q].cpu().numpy()), f"{name}/{kw}/vm")
     # the same graph without the copy gives the same arrays
-    H = P.Graph.from_csr(g.n, ptr, idx, ms_degree_order=False)
+    if g.directed:
+        H = P.Graph.from_csr(g.n, ptr, idx, g.in_ptr, g.in_idx, directed=True, ms_degree_order=False)
+    else:
+        H = P.Graph.from_csr(g.n, ptr, idx, ms_degree_order=False)
     a_l, a_p = P.bfs_batch(H, src, variant="heuristic")
     b_l, b_p = P.bfs_batch(G, src, variant="heuristic")
     torch.cuda.synchronize()
