@@ -1604,13 +1604,6 @@ static hipError_t ms_level(MsLevel &p, uint32_t k, bool pull, uint32_t frontier,
     return launch_ms(p, 3, k, grid, s);
 }
 
-// Multi-source launch size: 8 workgroups per compute unit, up to 32 on graphs
-// of more than 4,096 vertices per compute unit (one workgroup per 512
-// vertices, one pull row chunk each: R-MAT s22, 64 sources, 5.63 ms at 32 per
-// compute unit, 5.90 ms at 16; 6.25 ms at 8 with chunks of 1,024 rows), except
-// on thin graphs, whose thousands of small levels pay for
-// every workgroup of every launch (4096^2 grid, 16 sources: 239 ms at 8 per
-// compute unit, 272 ms at 32).
 // The multi-source parameters over the caller's vertex order instead of the
 // degree-ordered copy.
 static void ms_caller_order(const bfs_graph *g, MsLevel &p) {
@@ -1632,11 +1625,18 @@ static void ms_caller_order(const bfs_graph *g, MsLevel &p) {
     p.lirest = g->lirest;
 }
 
+// Multi-source launch size: 8 workgroups per compute unit, up to 48 on graphs
+// of more than 2,730 vertices per compute unit (three workgroups per 1,024
+// vertices: R-MAT s22, 64 sources, with the degree-ordered copy 4.99 ms at 48
+// per compute unit, 5.00 at 24, 5.08 at 32, 5.11 at 64; 6.25 ms at 8 before
+// that copy), except on thin graphs, whose thousands of small levels pay for
+// every workgroup of every launch (4096^2 grid, 16 sources: 239 ms at 8 per
+// compute unit, 272 ms at 32).
 static uint32_t ms_grid(const bfs_graph *g, const bfs_run_options *opt) {
     if (opt && opt->grid_blocks) return opt->grid_blocks;
     const uint32_t cus = (uint32_t)(g->cus > 0 ? g->cus : 256);
     if (thin_graph(g)) return 8u * cus;
-    const uint32_t want = (uint32_t)std::min<int64_t>((int64_t)g->n / 512, (int64_t)32 * cus);
+    const uint32_t want = (uint32_t)std::min<int64_t>((int64_t)g->n * 3 / 1024, (int64_t)48 * cus);
     return std::max<uint32_t>(8u * cus, want);
 }
 
