@@ -54,8 +54,9 @@ enum {
     BFS_INPUT_ON_DEVICE = 1u << 1,    /* the four input arrays are device pointers */
     BFS_VALIDATE_TRANSPOSE = 1u << 2, /* check that the given CSC is the transpose of the CSR */
     BFS_MS_DEGREE_ORDER = 1u << 3,    /* keep the multi-source search's degree-ordered copy */
-    BFS_MS_NO_DEGREE_ORDER = 1u << 4  /* never keep it (default: kept for undirected graphs of
-                                         2^19+ vertices with skewed degrees) */
+    BFS_MS_NO_DEGREE_ORDER = 1u << 4  /* never keep it (default: kept for graphs of 2^19+
+                                         vertices with skewed degrees; a directed graph's
+                                         copy serves batches of more than 64 sources) */
 };
 
 /* variant policies: which form of the product a level uses */

@@ -1300,13 +1300,10 @@ bfs_status bfs_graph_create(int32_t n, const int32_t *out_ptr, const int32_t *ou
             g->nli_chunks = g->nlo_chunks;
         }
         if (st == BFS_OK) st = build_rest(n, directed ? iptr : ptr, &g->lirest, g->bytes);
-        // automatic: undirected graphs whose masks outgrow an XCD's L2 (2^19+
-        // vertices) and whose degrees are skewed (no locality of their own to
-        // lose); a directed graph's copy only on request (directed R-MAT s20,
-        // 16 sources: 1.13 ms per batch with it, 0.93 ms without)
+        // automatic: graphs whose masks outgrow an XCD's L2 (2^19+ vertices)
+        // and whose degrees are skewed (no locality of their own to lose)
         const bool keep_order = (flags & BFS_MS_DEGREE_ORDER) ||
-                                (!(flags & BFS_MS_NO_DEGREE_ORDER) && !directed && n >= (1 << 19) &&
-                                 skewed_graph(g));
+                                (!(flags & BFS_MS_NO_DEGREE_ORDER) && n >= (1 << 19) && skewed_graph(g));
         if (st == BFS_OK && keep_order)
             st = directed ? build_degree_order(g, ptr, idx, iptr, iidx) : build_degree_order(g, ptr, idx, ptr, idx);
     } catch (const std::bad_alloc &) {
@@ -1531,7 +1528,11 @@ static bfs_status ms_prepare(bfs_graph *g, int32_t nq, const int32_t *sources,
     p.nli_chunks = g->nli_chunks;
     p.lirest = g->lirest;
     p.orig = p.pos = p.ent = nullptr;
-    if (g->do_ptr) {                  // the degree-ordered copy (undirected: one list set serves both ways)
+    // the degree-ordered copy (undirected: one list set serves both ways); a
+    // directed graph's only for batches of more than one mask word (directed
+    // R-MAT s20: 16 sources 1.08 ms with it, 0.92 without; 256 sources 4.35
+    // against 4.62 ms)
+    if (g->do_ptr && (!g->directed || p.W > 1)) {
         p.out_ptr = p.in_ptr = g->do_ptr;
         p.out_idx = p.in_idx = g->do_idx;
         p.ent = p.out_ent = g->do_ent;
