@@ -163,3 +163,40 @@ def test_vertex_major_binding_checks_output_shapes():
                    (torch.empty((10, 64), dtype=torch.int64), torch.empty((10, 64), **good))):
         with pytest.raises(ValueError):
             P.bfs_batch_vm(FakeGraph(), [0, 1], level=lv, parent=pa)
+
+
+def test_degree_order_flags_pass_validation_without_gpu(L):
+    """BFS_MS_DEGREE_ORDER / BFS_MS_NO_DEGREE_ORDER alone (and the first with a
+    directed graph) pass argument validation: without a GPU the call then
+    fails at its first HIP call, not with BFS_EINVAL."""
+    from paper_1906_03113_amd import _lib as B
+    ptr = np.array([0, 1, 2], np.int32)
+    idx = np.array([1, 0], np.int32)
+    for fl, ip, ii in ((B.BFS_MS_DEGREE_ORDER, None, None), (B.BFS_MS_NO_DEGREE_ORDER, None, None),
+                       (B.BFS_DIRECTED | B.BFS_MS_DEGREE_ORDER, ptr, idx)):
+        rc, h = _create(L, 2, ptr, idx, ip, ii, fl)
+        if rc == B.BFS_OK:                         # a GPU is present after all
+            L.bfs_graph_destroy(h)
+            continue
+        assert rc != B.BFS_EINVAL, (fl, L.bfs_last_error_detail())
+
+
+def test_binding_maps_degree_order_flag(monkeypatch):
+    """Graph.from_csr(ms_degree_order=...) passes the matching create flag."""
+    import paper_1906_03113_amd as P
+    from paper_1906_03113_amd import _lib as B
+    seen = []
+
+    class FakeLib:
+        def bfs_graph_create(self, n, ptr, idx, ip, ii, flags, stream, out):
+            seen.append(flags)
+            return B.BFS_OK
+
+    monkeypatch.setattr(B, "lib", lambda: FakeLib())
+    monkeypatch.setattr(P, "_device_ready", lambda: None)
+    ptr = np.array([0, 1, 2], np.int32)
+    idx = np.array([1, 0], np.int32)
+    for arg, want in ((None, 0), (True, B.BFS_MS_DEGREE_ORDER), (False, B.BFS_MS_NO_DEGREE_ORDER)):
+        g = P.Graph.from_csr(2, ptr, idx, ms_degree_order=arg)
+        g._h = None                                    # nothing to free
+        assert seen[-1] == want, (arg, seen)
